@@ -1,0 +1,226 @@
+"""CPU oracle for the SPC 2-hop label index (ctypes wrapper over spc_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it; the product path never imports it.  It shares no
+code with the GPU library.  Results are numpy arrays.
+
+All builders take a graph in original ids plus an order (rank -> vertex),
+relabel it into rank space (vertex id == rank, 0 = most important) and
+return labels in rank space, sorted by hub within each vertex, together with
+the order.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+INF = 0xFFFFFFFF
+SAT = 0xFFFFFFFFFFFFFFFF
+
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile liboracle.so in-tree with gcc."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=199309L", "-Wall", "-Wextra",
+               "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build_oracle()
+    L = C.CDLL(_LIB)
+    vp = C.c_void_p
+    L.oracle_degree_order.argtypes = [C.c_uint32, _u64p, vp, _u32p]
+    L.oracle_degree_order.restype = None
+    L.oracle_relabel.argtypes = [C.c_uint32, _u64p, _u32p, _u32p, _u64p, _u32p]
+    L.oracle_relabel.restype = None
+    L.oracle_bfs_count.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, C.c_int, C.c_uint32,
+                                   _u32p, _u64p]
+    L.oracle_bfs_count.restype = None
+    L.oracle_hub_column.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, C.c_uint32,
+                                    _u32p, _u32p, _u64p]
+    L.oracle_hub_column.restype = C.c_uint64
+    for nm in ("oracle_build_definition", "oracle_build_pull"):
+        f = getattr(L, nm)
+        f.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32]
+        f.restype = vp
+    L.oracle_build_pruned.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, C.c_uint32,
+                                      C.c_double]
+    L.oracle_build_pruned.restype = vp
+    L.oracle_index_entries.argtypes = [vp]
+    L.oracle_index_entries.restype = C.c_uint64
+    L.oracle_index_rounds.argtypes = [vp]
+    L.oracle_index_rounds.restype = C.c_uint32
+    L.oracle_index_hubs_done.argtypes = [vp]
+    L.oracle_index_hubs_done.restype = C.c_uint32
+    L.oracle_index_export.argtypes = [vp, _u64p, _u32p, _u32p, _u64p]
+    L.oracle_index_export.restype = None
+    L.oracle_index_round_stats.argtypes = [vp, _u64p, _u64p, _u64p, _u64p]
+    L.oracle_index_round_stats.restype = None
+    L.oracle_index_free.argtypes = [vp]
+    L.oracle_index_free.restype = None
+    L.oracle_query_arrays.argtypes = [_u64p, _u32p, _u32p, _u64p, C.c_uint64, _u32p, _u32p,
+                                      _u32p, _u64p]
+    L.oracle_query_arrays.restype = None
+    _lib = L
+    return L
+
+
+def _u32(a):
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def _u64(a):
+    return np.ascontiguousarray(a, dtype=np.uint64)
+
+
+def degree_order(off, tie_key=None) -> np.ndarray:
+    """Rank -> vertex: degree descending, ties by tie_key then id."""
+    off = _u64(off)
+    n = off.shape[0] - 1
+    order = np.zeros(n, dtype=np.uint32)
+    tk = None if tie_key is None else _u64(tie_key)
+    lib().oracle_degree_order(n, off, None if tk is None else tk.ctypes.data, order)
+    return order
+
+
+def relabel(off, adj, order):
+    off, adj, order = _u64(off), _u32(adj), _u32(order)
+    n = off.shape[0] - 1
+    roff = np.zeros(n + 1, dtype=np.uint64)
+    radj = np.zeros(adj.shape[0], dtype=np.uint32)
+    lib().oracle_relabel(n, off, adj, order, roff, radj)
+    return roff, radj
+
+
+def bfs_count(off, adj, src: int, restricted: bool = False, depth_cap: int = 0):
+    """Distances (uint32, INF unreached) and saturated path counts (uint64)."""
+    off, adj = _u64(off), _u32(adj)
+    n = off.shape[0] - 1
+    d = np.zeros(n, dtype=np.uint32)
+    s = np.zeros(n, dtype=np.uint64)
+    lib().oracle_bfs_count(n, off, adj, int(src), int(restricted), int(depth_cap), d, s)
+    return d, s
+
+
+def hub_column(roff, radj, w: int, depth_cap: int = 0):
+    """(vertex, dist, count) of every entry with hub w (rank space)."""
+    roff, radj = _u64(roff), _u32(radj)
+    n = roff.shape[0] - 1
+    v = np.zeros(n, dtype=np.uint32)
+    d = np.zeros(n, dtype=np.uint32)
+    c = np.zeros(n, dtype=np.uint64)
+    k = lib().oracle_hub_column(n, roff, radj, int(w), int(depth_cap), v, d, c)
+    return v[:k].copy(), d[:k].copy(), c[:k].copy()
+
+
+@dataclass
+class Labels:
+    """Labels in rank space: entries of vertex r at off[r]:off[r+1], by hub."""
+    n: int
+    off: np.ndarray
+    hub: np.ndarray
+    dist: np.ndarray
+    count: np.ndarray
+    order: np.ndarray        # rank -> original vertex
+    rounds: int
+    hubs_done: int
+    stats: dict | None = None
+
+    @property
+    def entries(self) -> int:
+        return int(self.off[-1])
+
+    def rank_of(self) -> np.ndarray:
+        r = np.zeros(self.n, dtype=np.uint32)
+        r[self.order] = np.arange(self.n, dtype=np.uint32)
+        return r
+
+    def query(self, s, t):
+        """SPC query with ORIGINAL vertex ids; returns (dist uint32, count uint64)."""
+        rk = self.rank_of()
+        s = _u32(rk[_u32(s)])
+        t = _u32(rk[_u32(t)])
+        return query_arrays(self.off, self.hub, self.dist, self.count, s, t)
+
+
+def query_arrays(off, hub, dist, count, s, t):
+    """Query over label arrays (ids in the labels' own space)."""
+    s, t = _u32(s), _u32(t)
+    q = s.shape[0]
+    od = np.zeros(q, dtype=np.uint32)
+    oc = np.zeros(q, dtype=np.uint64)
+    lib().oracle_query_arrays(_u64(off), _u32(hub), _u32(dist), _u64(count), q, s, t, od, oc)
+    return od, oc
+
+
+def _collect(h, n, order, with_stats: bool) -> Labels:
+    L = lib()
+    try:
+        e = L.oracle_index_entries(h)
+        off = np.zeros(n + 1, dtype=np.uint64)
+        hub = np.zeros(e, dtype=np.uint32)
+        dist = np.zeros(e, dtype=np.uint32)
+        cnt = np.zeros(e, dtype=np.uint64)
+        L.oracle_index_export(h, off, hub, dist, cnt)
+        rounds = L.oracle_index_rounds(h)
+        stats = None
+        if with_stats:
+            k = rounds + 1
+            raw, mer, kept, scan = (np.zeros(k, dtype=np.uint64) for _ in range(4))
+            L.oracle_index_round_stats(h, raw, mer, kept, scan)
+            stats = dict(raw=raw, merged=mer, kept=kept, scanned=scan)
+        return Labels(n, off, hub, dist, cnt, order, int(rounds), int(L.oracle_index_hubs_done(h)),
+                      stats)
+    finally:
+        L.oracle_index_free(h)
+
+
+def _prep(off, adj, order, tie_key):
+    off, adj = _u64(off), _u32(adj)
+    if order is None:
+        order = degree_order(off, tie_key)
+    order = _u32(order)
+    roff, radj = relabel(off, adj, order)
+    return off.shape[0] - 1, roff, radj, order
+
+
+def build(off, adj, order=None, tie_key=None, method: str = "pruned", depth_cap: int = 0,
+          max_hubs: int = 0, time_limit_s: float = 0.0) -> Labels:
+    """Build the label index; method in {"definition", "pruned", "pull"}."""
+    n, roff, radj, order = _prep(off, adj, order, tie_key)
+    L = lib()
+    if method == "definition":
+        h = L.oracle_build_definition(n, roff, radj, depth_cap)
+    elif method == "pruned":
+        h = L.oracle_build_pruned(n, roff, radj, depth_cap, max_hubs, time_limit_s)
+    elif method == "pull":
+        h = L.oracle_build_pull(n, roff, radj, depth_cap)
+    else:
+        raise ValueError(method)
+    return _collect(h, n, order, with_stats=(method == "pull"))
+
+
+def build_graph(g, method: str = "pruned", depth_cap: int = 0, **kw) -> Labels:
+    """Build for an inputs.Graph (uses its explicit order or tie keys)."""
+    return build(g.off, g.adj, order=g.order, tie_key=g.tie_key, method=method,
+                 depth_cap=depth_cap, **kw)
