@@ -1,0 +1,170 @@
+/*
+ * spc.h -- C ABI of the MI355X (gfx950) shortest-path-counting label library.
+ *
+ * The library builds the 2-hop SPC label index of PSPC (Peng, Yu, Wang,
+ * "PSPC: Efficient Parallel Shortest Path Counting on Large-Scale Graphs")
+ * round by round over the distance d = 0, 1, 2, ... with the PULL
+ * propagation (Alg. 2, label propagation function Eq. PSPCdu, Label
+ * Elimination / Label Merging), and answers SPC queries with the label merge
+ * of Eq. (con:spc1)-(con:spc2).  Every step runs in the library's own HIP
+ * kernels on the GPU; no entry point falls back to the CPU.
+ *
+ * Index semantics (Section "The Construction of an ESPC Index"): with the
+ * vertices ranked by a total order (rank 0 = most important), L(v) holds
+ * (w, sd(v,w), tau(v,w)) for every w ranked at or above v with tau >= 1, where
+ * tau counts the shortest v-w paths whose vertices other than w all rank
+ * below w.  Both canonical and non-canonical hubs are kept; this is exactly
+ * the set that makes the query return (sd(s,t), number of shortest paths).
+ *
+ * Integer semantics: distances are uint8 or uint16 (dist_bits); counts are
+ * uint64 and saturate: every stored or returned count is
+ * min(true count, 2^64-1), and 2^64-1 itself is reported as saturated.
+ *
+ * Conventions for every entry point
+ *   - Status codes only; nothing throws across the ABI.  On error, *out
+ *     arguments are left untouched and no memory is leaked.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Build and stats calls synchronise that stream before returning; query
+ *     calls are asynchronous on it.
+ *   - Device pointers are plain device addresses (e.g. a torch tensor's
+ *     data_ptr()); the caller owns them.  The index owns all device memory it
+ *     allocates until spc_free.
+ *   - Thread safety: concurrent spc_query_batch calls on one index, from any
+ *     streams, are safe (the index is read-only once built).
+ */
+#ifndef SPC_H
+#define SPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spc_index spc_index;
+
+typedef enum {
+    SPC_OK = 0,
+    SPC_ERR_INVALID_ARG = 1,   /* NULL pointer, bad size, id >= n, not a simple symmetric CSR */
+    SPC_ERR_OUT_OF_MEMORY = 2, /* device allocation failed or mem_budget exceeded */
+    SPC_ERR_DEVICE = 3,        /* a HIP runtime call failed */
+    SPC_ERR_DIST_RANGE = 4,    /* a distance does not fit the requested dist_bits */
+    SPC_ERR_UNSUPPORTED = 5    /* graph larger than the packed label layout allows */
+} spc_status;
+
+/* Per-query flag bits written by spc_query_batch. */
+#define SPC_FLAG_SATURATED 0x1u  /* count is 2^64-1: true count >= 2^64-1 */
+#define SPC_FLAG_UNREACHABLE 0x2u /* no common hub: dist = INF (type max), count 0 */
+#define SPC_FLAG_HORIZON 0x4u    /* truncated index: answer not proven exact (dist > round cap or none found) */
+#define SPC_FLAG_INVALID 0x8u    /* s or t >= n: dist = INF, count 0 */
+
+/* An undirected, unweighted graph (Preliminaries: G = (V, E)) as a symmetric
+ * CSR: the neighbours of v are col[row_off[v] .. row_off[v+1]).  Every edge
+ * appears in both directions; no self loops, no duplicate entries.
+ * nnz = row_off[n] = 2m.  All pointers are device pointers when on_device is
+ * nonzero, host pointers otherwise; they are only read during the call. */
+typedef struct {
+    uint32_t n;
+    uint64_t nnz;
+    const uint64_t *row_off; /* [n+1] */
+    const uint32_t *col;     /* [nnz] */
+    /* Optional explicit total order, order[r] = vertex of rank r (a
+     * permutation of 0..n-1).  NULL: degree-based order (Section "Vertex
+     * Ordering Strategies": higher degree ranks higher), ties by tie_key
+     * ascending when tie_key is given, then by vertex id. */
+    const uint32_t *order;
+    const uint64_t *tie_key; /* [n] or NULL */
+    int32_t on_device;
+} spc_graph;
+
+typedef struct {
+    uint32_t dist_bits;  /* 0 = 8-bit labels, widened to 16 bits when a round passes 254;
+                            8 = fail with SPC_ERR_DIST_RANGE past 254; 16 = 16-bit labels */
+    uint32_t round_cap;  /* 0 = build to completion; D > 0 = build the distance-partial
+                            set L_{<=D} (Def. DPLS) and mark the index truncated if
+                            round D+1 would have had candidates */
+    uint64_t mem_budget; /* device bytes the build may hold at once; 0 = unlimited */
+    uint32_t validate;   /* nonzero: check that the CSR is simple and symmetric */
+    uint32_t reserved;   /* must be 0 */
+} spc_build_opts;
+
+typedef struct {
+    uint32_t n;               /* vertices (all graphs of a batch) */
+    uint32_t num_graphs;      /* 1, or k for spc_build_index_batch */
+    uint64_t m;               /* undirected edges */
+    uint64_t entries;         /* label entries, self entries included */
+    uint32_t rounds;          /* last round run: first empty round, or the cap */
+    uint32_t max_dist;        /* largest label distance */
+    uint32_t dist_bits;       /* 8 or 16: width of query dist outputs */
+    uint32_t truncated;       /* 1 if round_cap stopped the build early */
+    uint64_t saturated_entries; /* entries whose count is 2^64-1 */
+    uint64_t index_bytes;     /* device bytes held by the finished index */
+    uint64_t peak_build_bytes;/* largest device footprint during the build */
+    double ms_order;          /* vertex ordering + relabel + validation */
+    double ms_rounds;         /* distance rounds (expand, aggregate, prune, insert) */
+    double ms_finalize;       /* hub-ordered count array */
+    double ms_total;          /* whole build on the device */
+    double ms_round_kernel;   /* time inside the fused round kernel only */
+    uint64_t alg_bytes_round_kernel; /* algorithmic bytes of the fused round kernel */
+} spc_stats;
+
+/* Build the index of one graph (Alg. 2 rounds until a round adds no entry).
+ * g, opts and out must be non-NULL.  Returns SPC_ERR_INVALID_ARG for a
+ * malformed graph (ids >= n, self loops, asymmetric or duplicate entries when
+ * validate is set, order not a permutation), SPC_ERR_UNSUPPORTED when
+ * n >= 2^24 with 8-bit labels, SPC_ERR_DIST_RANGE as documented above. */
+spc_status spc_build_index(const spc_graph *g, const spc_build_opts *opts, void *stream,
+                           spc_index **out);
+
+/* Build one index over k independent graphs at once (their disjoint union,
+ * each graph ranked by its own order).  Labels never cross graphs, so every
+ * graph's labels equal those of a solo build.  gs[k]; queries name a graph. */
+spc_status spc_build_index_batch(const spc_graph *gs, uint32_t k, const spc_build_opts *opts,
+                                 void *stream, spc_index **out);
+
+/* SPC queries (Eq. con:spc1 and con:spc2) on graph `graph_id` of the index
+ * (0 for single-graph indexes).  s, t: device uint32[nq] with vertex ids of
+ * that graph.  Outputs (device, caller-owned, nq each): dist_out is uint8 when
+ * the index has 8-bit labels and uint16 otherwise, INF = the type's maximum;
+ * count_out uint64; flags_out uint8 (SPC_FLAG_*, may be NULL).  s = t gives
+ * (0, 1).  Asynchronous on `stream`; nq == 0 is a no-op. */
+spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
+                           const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                           uint8_t *flags_out, void *stream);
+
+/* Release the index.  spc_free(NULL) is a no-op. */
+void spc_free(spc_index *ix);
+
+/* Summary numbers of a finished build (host struct). */
+spc_status spc_index_stats(const spc_index *ix, spc_stats *out);
+
+/* Per-round counters, rounds 0 .. min(rounds, max_rounds-1), into host arrays
+ * of max_rounds entries (any may be NULL): raw = candidates pulled that pass
+ * the rank rule (Lemma prune1), merged = distinct candidate hubs left after
+ * Label Elimination and Label Merging, kept = entries inserted, scanned =
+ * probe entries read in hub order up to and including the first one proving
+ * a shorter distance (all of L(w) when the candidate is kept). */
+spc_status spc_round_stats(const spc_index *ix, uint32_t max_rounds, uint64_t *raw,
+                           uint64_t *merged, uint64_t *kept, uint64_t *scanned);
+
+/* Number of label entries of graph `graph_id` (host out). */
+spc_status spc_graph_entries(const spc_index *ix, uint32_t graph_id, uint32_t *n_out,
+                             uint64_t *entries_out);
+
+/* Export the labels of graph `graph_id` in RANK space (vertex id = rank in
+ * that graph, hubs likewise), each label sorted by hub: off[n+1], hub, dist,
+ * count[entries], order[n] (rank -> vertex id).  Pointers are device pointers
+ * when on_device is nonzero, host pointers otherwise; any may be NULL to skip
+ * it.  Synchronises `stream`. */
+spc_status spc_export_labels(const spc_index *ix, uint32_t graph_id, uint64_t *off,
+                             uint32_t *hub, uint16_t *dist, uint64_t *count, uint32_t *order,
+                             int32_t on_device, void *stream);
+
+/* Static string for a status code. */
+const char *spc_status_string(spc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPC_H */

@@ -474,19 +474,28 @@ oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t 
             qsort(touched, ntouch, sizeof(uint32_t), cmp_u32);
             for (uint32_t j = 0; j < ntouch; j++) {
                 uint32_t w = touched[j];
-                /* Query(w, u, entries of distance < d), early exit in hub order */
+                /* Query(w, u, entries of distance < d).  The counter `scanned`
+                 * is the number of entries a scan of L(w) in hub order reads
+                 * up to and including the first hub that proves a shorter
+                 * distance (all of L(w) when none does); L(w) is stored here
+                 * in insertion order, so it counts the entries whose hub is at
+                 * most the smallest proving hub. */
                 olabel *lw = &ix->lab[w];
                 int pruned = 0;
-                uint64_t i;
-                for (i = 0; i < lw->len; i++) {
+                uint32_t hmin = ORACLE_INF;
+                for (uint64_t i = 0; i < lw->len; i++) {
                     uint32_t du = udist[lw->hub[i]];
                     if (lw->dist[i] >= d) continue; /* entries of round >= d are not read */
                     if (du != ORACLE_INF && du + lw->dist[i] < d) {
                         pruned = 1;
-                        break;
+                        if (lw->hub[i] < hmin) hmin = lw->hub[i];
                     }
                 }
-                s_scanned += pruned ? i + 1 : lw->len;
+                if (pruned) {
+                    for (uint64_t i = 0; i < lw->len; i++) s_scanned += lw->hub[i] <= hmin;
+                } else {
+                    s_scanned += lw->len;
+                }
                 if (!pruned) {
                     if (cur_len == cur_cap) {
                         cur_cap *= 2;

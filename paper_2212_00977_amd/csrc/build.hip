@@ -1,0 +1,1305 @@
+// SPC label index construction on gfx950: vertex ordering, relabelling and
+// the round-by-distance PULL propagation of PSPC (Alg. 2, Eq. PSPCdu, Label
+// Elimination / Label Merging), then the hub-ordered count array.
+//
+// Layout in HBM (rank space: vertex id == rank, 0 = most important)
+//   graph      goff u64[N+1], gadj u32[2m]
+//   labels     lab_off u64[N+1], lab_hd E[entries]: packed (hub, dist), each
+//              label sorted by hub; rebuilt each round by merging the round's
+//              entries in (double-buffered), so probes always stream sorted
+//              labels and the final index needs no sort
+//   rounds     pool_hub u32[], pool_cnt u64[]: every round's entries, appended
+//              round after round; round r of vertex v is the hub-sorted
+//              segment pool[rstart[r][v] .. + rlen[r][v])
+//   counts     lab_cnt u64[entries], filled at the end from the round pool
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "spc_internal.h"
+
+namespace spc {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Preprocessing kernels
+// ---------------------------------------------------------------------------
+// Copy one graph's CSR into the union, shifting offsets by the graph's edge
+// base and neighbour ids by its vertex base; flags out-of-range ids and
+// non-monotone offsets.
+__global__ void k_union_off(const uint64_t *src, uint64_t *dst, uint32_t n, uint64_t nnz,
+                            uint64_t ebase, uint32_t *err) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    uint64_t x = src[i];
+    if ((i == 0 && x != 0) || (i == n && x != nnz) || x > nnz) atomicOr(err, 1u);
+    if (i < n && src[i + 1] < x) atomicOr(err, 1u);
+    dst[i] = x + ebase;
+}
+__global__ void k_union_col(const uint32_t *src, uint32_t *dst, uint64_t nnz, uint32_t n,
+                            uint32_t vbase, uint32_t *err) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnz) return;
+    uint32_t x = src[i];
+    if (x >= n) atomicOr(err, 2u);
+    dst[i] = x + vbase;
+}
+
+__global__ void k_degrees(const uint64_t *off, uint32_t N, uint32_t *deg, uint32_t *maxdeg) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    uint32_t dv = (uint32_t)(off[v + 1] - off[v]);
+    deg[v] = dv;
+    atomicMax(maxdeg, dv);
+}
+
+// graph id of union vertex v: largest g with vbase[g] <= v
+__device__ __forceinline__ uint32_t graph_of(const uint32_t *vbase, uint32_t k, uint32_t v) {
+    uint32_t lo = 0, hi = k - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (vbase[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// key for the degree pass: (graph id, maxdeg - degree), values = vertices in
+// their current (stable) order
+__global__ void k_degree_keys(const uint32_t *vals, const uint32_t *deg, uint32_t N, uint32_t maxdeg,
+                              int degbits, const uint32_t *vbase, uint32_t k, uint64_t *keys) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    uint32_t v = vals[i];
+    uint64_t g = (k > 1) ? graph_of(vbase, k, v) : 0;
+    keys[i] = (g << degbits) | (uint64_t)(maxdeg - deg[v]);
+}
+__global__ void k_iota_keys(const uint64_t *tie, uint32_t N, uint64_t *keys, uint32_t *vals) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    keys[i] = tie ? tie[i] : 0;
+    vals[i] = i;
+}
+// explicit per-graph order, shifted into the union; counts hits per vertex
+__global__ void k_union_order(const uint32_t *src, uint32_t *dst, uint32_t n, uint32_t vbase,
+                              uint32_t *hits, uint32_t *err) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t v = src[i];
+    if (v >= n) {
+        atomicOr(err, 4u);
+        v = 0;
+    }
+    dst[vbase + i] = v + vbase;
+    atomicAdd(&hits[vbase + v], 1u);
+}
+__global__ void k_check_perm(const uint32_t *hits, uint32_t N, uint32_t *err) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && hits[i] != 1) atomicOr(err, 4u);
+}
+__global__ void k_rank_of(const uint32_t *order, uint32_t N, const uint32_t *deg, uint32_t *rank_of,
+                          uint32_t *rdeg) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    uint32_t v = order[r];
+    rank_of[v] = r;
+    rdeg[r] = deg[v];
+}
+// rank-space adjacency: one wave per rank
+__global__ __launch_bounds__(kBlock) void k_relabel(const uint32_t *order, const uint32_t *rank_of,
+                                                    const uint64_t *off, const uint32_t *col,
+                                                    const uint64_t *roff, uint32_t *radj,
+                                                    uint32_t N) {
+    uint32_t r = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (r >= N) return;
+    uint32_t lane = threadIdx.x & 63;
+    uint32_t v = order[r];
+    uint64_t s = off[v], len = off[v + 1] - s, o = roff[r];
+    for (uint64_t k = lane; k < len; k += 64) radj[o + k] = rank_of[col[s + k]];
+}
+// keys (row << xbits | neighbour) for sorting each adjacency list
+__global__ __launch_bounds__(kBlock) void k_row_keys(const uint64_t *roff, const uint32_t *radj,
+                                                     uint32_t N, int xbits, uint64_t *keys) {
+    uint32_t r = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (r >= N) return;
+    uint32_t lane = threadIdx.x & 63;
+    for (uint64_t k = roff[r] + lane; k < roff[r + 1]; k += 64)
+        keys[k] = ((uint64_t)r << xbits) | radj[k];
+}
+__global__ void k_keys_to_adj(const uint64_t *keys, uint64_t nnz, int xbits, uint32_t *radj) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnz) radj[i] = (uint32_t)(keys[i] & ((1ull << xbits) - 1));
+}
+// simple + symmetric check on sorted rank-space adjacency
+__global__ __launch_bounds__(kBlock) void k_check_adj(const uint64_t *roff, const uint32_t *radj,
+                                                      uint32_t N, uint32_t *err) {
+    uint32_t r = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (r >= N) return;
+    uint32_t lane = threadIdx.x & 63;
+    uint64_t s = roff[r], e = roff[r + 1];
+    for (uint64_t k = s + lane; k < e; k += 64) {
+        uint32_t x = radj[k];
+        if (x == r) atomicOr(err, 8u);                       // self loop
+        if (k > s && radj[k - 1] == x) atomicOr(err, 16u);   // duplicate
+        uint64_t xs = roff[x];
+        uint32_t xl = (uint32_t)(roff[x + 1] - xs);
+        uint32_t p = lower_bound_u32(radj + xs, xl, r);
+        if (p >= xl || radj[xs + p] != r) atomicOr(err, 32u); // asymmetric
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Round 0: L_0(v) = {(v, 0, 1)}.
+// ---------------------------------------------------------------------------
+template <int DB>
+__global__ void k_round0(uint32_t N, uint32_t *pool_hub, uint64_t *pool_cnt, uint64_t *rstart,
+                         uint32_t *rlen, uint64_t *lab_off, typename Ent<DB>::T *lab_hd) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > N) return;
+    lab_off[v] = v;
+    if (v == N) return;
+    pool_hub[v] = v;
+    pool_cnt[v] = 1;
+    rstart[v] = v;
+    rlen[v] = 1;
+    lab_hd[v] = e_make<DB>(v, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Expand count: raw[u] = number of round d-1 entries of u's neighbours whose
+// hub outranks u (Lemma propagation + rank rule).  The round d-1 segment of a
+// neighbour v is hub-sorted, so this is a prefix length; when v outranks u
+// every hub of that segment does too.  One wave per u.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_expand_count(uint32_t N, const uint64_t *goff,
+                                                         const uint32_t *gadj, const uint64_t *pstart,
+                                                         const uint32_t *plen,
+                                                         const uint32_t *pool_hub, uint64_t *raw) {
+    uint32_t u = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (u >= N) return;
+    uint32_t lane = threadIdx.x & 63;
+    uint64_t s = 0;
+    for (uint64_t k = goff[u] + lane; k < goff[u + 1]; k += 64) {
+        uint32_t v = gadj[k];
+        uint32_t ln = plen[v];
+        if (ln == 0) continue;
+        s += (v < u) ? ln : lower_bound_u32(pool_hub + pstart[v], ln, u);
+    }
+    s = wave_sum(s);
+    if (lane == 0) raw[u] = s;
+}
+
+// ---------------------------------------------------------------------------
+// The fused round kernel.  One workgroup per puller u (largest rank ids
+// first: they have the most candidates).
+//   1. stage L_{<d}(u) (hub -> dist) in an LDS hash table; if u's label is
+//      longer than the table allows, the tail (largest hubs) is searched in
+//      HBM by binary search instead;
+//   2. walk the hub range [0, u) in chunks: pull every neighbour's round d-1
+//      entries with hub in the chunk, drop hubs u already holds (Label
+//      Elimination: they hold a smaller distance) and merge equal hubs in an
+//      LDS hash by summing counts (Label Merging, saturating).  A chunk whose
+//      distinct hubs overflow the table is retried with half the width;
+//   3. sort the chunk's merged candidates by hub (bitonic, LDS);
+//   4. prune each candidate w with the 2-hop query over entries of distance
+//      < d (Eq. PSPCdu): stream L_{<d}(w) in hub order, one wave per
+//      candidate, and look every hub up in u's table; the first hub with
+//      d_u(h) + d_w(h) < d proves a shorter path.  Equality is kept.  Only
+//      entries with d_w <= d-2 can prove anything (h != u forces d_u >= 1);
+//   5. append the survivors, in hub order, to u's slot of the temp buffer.
+// ---------------------------------------------------------------------------
+constexpr int kLBits = 12;
+constexpr int kLCap = 1 << kLBits;   // L(u) hash slots
+constexpr int kLStage = kLCap / 2;   // staged entries (load <= 1/2)
+constexpr int kCBits = 10;
+constexpr int kCCap = 1 << kCBits;   // candidate hash slots
+constexpr int kULimit = kCCap / 2;   // distinct candidates per chunk
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+struct RoundArgs {
+    uint32_t d, u_lo, u_hi;
+    const uint64_t *goff;
+    const uint32_t *gadj;
+    const uint64_t *lab_off;
+    const void *lab_hd;
+    const uint64_t *pstart;  // round d-1 segments
+    const uint32_t *plen;
+    const uint32_t *pool_hub;
+    const uint64_t *pool_cnt;
+    const uint64_t *raw_off;  // exclusive prefix of raw over all vertices
+    uint32_t *tmp_hub;
+    uint64_t *tmp_cnt;
+    uint32_t *surv;
+    unsigned long long *ctr;  // raw, merged, kept, scanned, staged
+};
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t h, int bits) {
+    return (h * 0x9E3779B1u) >> (32 - bits);
+}
+
+template <int DB>
+struct LabelLookup {
+    using E = typename Ent<DB>::T;
+    const E *tab;     // LDS table
+    const E *tail;    // unstaged entries in HBM, hub-sorted
+    uint64_t ntail;
+    uint32_t x;       // hubs >= x live in the tail
+    __device__ __forceinline__ uint32_t operator()(uint32_t h) const {
+        if (h < x) {
+            uint32_t s = hash_slot(h, kLBits);
+            while (true) {
+                E e = tab[s];
+                if (e == (E)~(E)0) return kNone;
+                if (e_hub<DB>(e) == h) return e_dist<DB>(e);
+                s = (s + 1) & (kLCap - 1);
+            }
+        }
+        uint64_t p = lower_bound_hub<DB>(tail, ntail, h);
+        if (p < ntail && e_hub<DB>(tail[p]) == h) return e_dist<DB>(tail[p]);
+        return kNone;
+    }
+};
+
+template <int DB>
+__global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
+    using E = typename Ent<DB>::T;
+    __shared__ E ltab[kLCap];
+    __shared__ uint32_t ckey[kCCap];
+    __shared__ unsigned long long cval[kCCap];
+    __shared__ uint8_t cwrap[kCCap];
+    __shared__ uint32_t lhub[kULimit];
+    __shared__ unsigned long long lcnt[kULimit];
+    __shared__ uint8_t lkeep[kULimit];
+    __shared__ uint64_t nb_start[kBlock];
+    __shared__ uint32_t nb_off[kBlock];
+    __shared__ uint32_t red32[kWaves];
+    __shared__ uint32_t s_nuniq, s_ovf;
+    __shared__ unsigned long long s_scanned;
+
+    const E *hd = static_cast<const E *>(a.lab_hd);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t u = a.u_hi - 1 - blockIdx.x;
+    const uint64_t raw_u = a.raw_off[u + 1] - a.raw_off[u];
+    if (raw_u == 0) {
+        if (tid == 0) a.surv[u] = 0;
+        return;
+    }
+    const uint32_t d = a.d;
+    const E kEmptyE = (E)~(E)0;
+
+    // 1. stage L_{<d}(u)
+    const uint64_t l0 = a.lab_off[u];
+    const uint64_t nL = a.lab_off[u + 1] - l0;
+    const uint32_t nst = nL < (uint64_t)kLStage ? (uint32_t)nL : (uint32_t)kLStage;
+    for (int i = tid; i < kLCap; i += kBlock) ltab[i] = kEmptyE;
+    if (tid == 0) s_scanned = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < nst; i += kBlock) {
+        E e = hd[l0 + i];
+        uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
+        while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
+    }
+    LabelLookup<DB> look;
+    look.tab = ltab;
+    look.tail = hd + l0 + nst;
+    look.ntail = nL - nst;
+    look.x = (nst < nL) ? e_hub<DB>(hd[l0 + nst]) : 0xFFFFFFFFu;
+    __syncthreads();
+
+    const uint64_t g0 = a.goff[u];
+    const uint32_t deg = (uint32_t)(a.goff[u + 1] - g0);
+    const uint64_t tbase = a.raw_off[u] - a.raw_off[a.u_lo];
+    uint32_t nout = 0;
+    uint64_t st_raw = 0, st_merged = 0, st_kept = 0;
+    uint32_t lo = 0, width = u;
+
+    // 2-5, chunk by chunk over the hub range [0, u)
+    while (lo < u) {
+        const uint32_t hi = (width >= u - lo) ? u : lo + width;
+        for (int i = tid; i < kCCap; i += kBlock) {
+            ckey[i] = kEmpty32;
+            cval[i] = 0;
+            cwrap[i] = 0;
+        }
+        if (tid == 0) {
+            s_nuniq = 0;
+            s_ovf = 0;
+        }
+        __syncthreads();
+        uint64_t chunk_raw = 0;
+        for (uint32_t nb0 = 0; nb0 < deg; nb0 += kBlock) {
+            uint32_t nb = nb0 + tid;
+            uint64_t sb = 0;
+            uint32_t len = 0;
+            if (nb < deg) {
+                uint32_t v = a.gadj[g0 + nb];
+                uint32_t ln = a.plen[v];
+                if (v >= lo && ln) {  // hubs of v's segment are <= v
+                    uint64_t ps = a.pstart[v];
+                    const uint32_t *ph = a.pool_hub + ps;
+                    uint32_t b = lo ? lower_bound_u32(ph, ln, lo) : 0;
+                    uint32_t e = lower_bound_u32(ph, ln, hi);
+                    sb = ps + b;
+                    len = e - b;
+                }
+            }
+            uint32_t tot;
+            uint32_t ex = block_excl_scan<uint32_t>(len, red32, tot);
+            nb_start[tid] = sb;
+            nb_off[tid] = ex;
+            __syncthreads();
+            chunk_raw += tot;
+            for (uint32_t k = tid; k < tot; k += kBlock) {
+                if (*(volatile uint32_t *)&s_ovf) break;
+                uint32_t jl = 0, jh = kBlock - 1;  // owner: last j with nb_off[j] <= k
+                while (jl < jh) {
+                    uint32_t mid = (jl + jh + 1) >> 1;
+                    if (nb_off[mid] <= k)
+                        jl = mid;
+                    else
+                        jh = mid - 1;
+                }
+                uint64_t idx = nb_start[jl] + (k - nb_off[jl]);
+                uint32_t w = a.pool_hub[idx];
+                uint64_t c = a.pool_cnt[idx];
+                if (look(w) != kNone) continue;  // Label Elimination
+                uint32_t s = hash_slot(w, kCBits);
+                bool ok = true;
+                for (uint32_t probes = 0;; probes++) {
+                    uint32_t kk = ckey[s];
+                    if (kk == w) break;
+                    if (kk == kEmpty32) {
+                        uint32_t old = atomicCAS(&ckey[s], kEmpty32, w);
+                        if (old == kEmpty32) {
+                            if (atomicAdd(&s_nuniq, 1u) + 1 > (uint32_t)kULimit) s_ovf = 1;
+                            break;
+                        }
+                        if (old == w) break;
+                    }
+                    s = (s + 1) & (kCCap - 1);
+                    if (probes + 1 >= (uint32_t)kCCap) {
+                        s_ovf = 1;
+                        ok = false;
+                        break;
+                    }
+                }
+                if (ok) {  // Label Merging: saturating sum, wrap recorded
+                    unsigned long long old = atomicAdd(&cval[s], (unsigned long long)c);
+                    if (old + c < old) cwrap[s] = 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (s_ovf) {  // too many distinct hubs: retry a narrower range
+            width = (hi - lo) > 1 ? (hi - lo) >> 1 : 1;
+            __syncthreads();
+            continue;
+        }
+
+        // compact the table into a list
+        uint32_t nv = 0;
+        for (int j = 0; j < kCCap / kBlock; j++) nv += ckey[tid * (kCCap / kBlock) + j] != kEmpty32;
+        uint32_t M;
+        uint32_t ex = block_excl_scan<uint32_t>(nv, red32, M);
+        for (int j = 0; j < kCCap / kBlock; j++) {
+            uint32_t s = tid * (kCCap / kBlock) + j;
+            uint32_t kk = ckey[s];
+            if (kk != kEmpty32) {
+                lhub[ex] = kk;
+                lcnt[ex] = cwrap[s] ? kSat : cval[s];
+                ex++;
+            }
+        }
+        uint32_t P = 1;
+        while (P < M) P <<= 1;
+        for (uint32_t i = M + tid; i < P; i += kBlock) lhub[i] = kEmpty32;
+        __syncthreads();
+
+        // 3. bitonic sort by hub
+        for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+            for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = tid; i < P; i += kBlock) {
+                    uint32_t ixj = i ^ j;
+                    if (ixj > i) {
+                        bool asc = (i & kk) == 0;
+                        uint32_t x = lhub[i], y = lhub[ixj];
+                        if ((x > y) == asc) {
+                            lhub[i] = y;
+                            lhub[ixj] = x;
+                            unsigned long long t = lcnt[i];
+                            lcnt[i] = lcnt[ixj];
+                            lcnt[ixj] = t;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        // 4. prune probes, one wave per candidate
+        for (uint32_t i = wv; i < M; i += kWaves) {
+            uint32_t w = lhub[i];
+            uint64_t lw0 = a.lab_off[w];
+            uint64_t nw = a.lab_off[w + 1] - lw0;
+            bool pruned = false;
+            uint64_t scanned = nw;
+            if (d >= 2) {
+                for (uint64_t j0 = 0; j0 < nw; j0 += 64) {
+                    uint64_t j = j0 + lane;
+                    bool hit = false;
+                    if (j < nw) {
+                        E e = hd[lw0 + j];
+                        uint32_t dw = e_dist<DB>(e);
+                        if (dw + 2 <= d) {
+                            uint32_t du = look(e_hub<DB>(e));
+                            hit = du != kNone && du + dw < d;
+                        }
+                    }
+                    uint64_t m = __ballot(hit);
+                    if (m) {
+                        pruned = true;
+                        scanned = j0 + (uint64_t)__ffsll((long long)m);
+                        break;
+                    }
+                }
+            }
+            if (lane == 0) {
+                lkeep[i] = pruned ? 0 : 1;
+                atomicAdd(&s_scanned, (unsigned long long)scanned);
+            }
+        }
+        __syncthreads();
+
+        // 5. survivors in hub order
+        uint32_t i0 = tid * 2;
+        uint32_t k0 = (i0 < M) ? lkeep[i0] : 0;
+        uint32_t k1 = (i0 + 1 < M) ? lkeep[i0 + 1] : 0;
+        uint32_t S;
+        uint32_t pos = block_excl_scan<uint32_t>(k0 + k1, red32, S);
+        uint64_t obase = tbase + nout;
+        if (k0) {
+            a.tmp_hub[obase + pos] = lhub[i0];
+            a.tmp_cnt[obase + pos] = lcnt[i0];
+            pos++;
+        }
+        if (k1) {
+            a.tmp_hub[obase + pos] = lhub[i0 + 1];
+            a.tmp_cnt[obase + pos] = lcnt[i0 + 1];
+        }
+        nout += S;
+        st_raw += chunk_raw;
+        st_merged += M;
+        st_kept += S;
+        lo = hi;
+        if (M < (uint32_t)kULimit / 4 && width < 0x40000000u) width <<= 1;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.surv[u] = nout;
+        atomicAdd(&a.ctr[0], (unsigned long long)st_raw);
+        atomicAdd(&a.ctr[1], (unsigned long long)st_merged);
+        atomicAdd(&a.ctr[2], (unsigned long long)st_kept);
+        atomicAdd(&a.ctr[3], s_scanned);
+        atomicAdd(&a.ctr[4], (unsigned long long)nL);
+    }
+}
+
+// Move a batch's survivors from the temp buffer to the round pool, and record
+// the round's segment of every vertex of the batch.  One wave per vertex.
+__global__ __launch_bounds__(kBlock) void k_compact(uint32_t u_lo, uint32_t u_hi,
+                                                    const uint64_t *raw_off, const uint64_t *soff,
+                                                    const uint32_t *surv, const uint32_t *tmp_hub,
+                                                    const uint64_t *tmp_cnt, uint64_t pool_base,
+                                                    uint32_t *pool_hub, uint64_t *pool_cnt,
+                                                    uint64_t *rstart, uint32_t *rlen) {
+    uint32_t u = u_lo + blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (u >= u_hi) return;
+    uint32_t lane = threadIdx.x & 63;
+    uint32_t s = surv[u];
+    uint64_t src = raw_off[u] - raw_off[u_lo];
+    uint64_t dst = pool_base + soff[u - u_lo];
+    for (uint32_t i = lane; i < s; i += 64) {
+        pool_hub[dst + i] = tmp_hub[src + i];
+        pool_cnt[dst + i] = tmp_cnt[src + i];
+    }
+    if (lane == 0) {
+        rstart[u] = dst;
+        rlen[u] = s;
+    }
+}
+
+__global__ void k_new_len(uint32_t N, const uint64_t *lab_off, const uint32_t *rlen, uint64_t *nlen) {
+    uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < N) nlen[u] = (lab_off[u + 1] - lab_off[u]) + rlen[u];
+}
+
+// L_{<=d}(u) = merge of L_{<d}(u) and round d (disjoint hubs, both sorted).
+// Each element's output position is its own index plus the number of smaller
+// hubs in the other list.  One wave per vertex.
+template <int DB>
+__global__ __launch_bounds__(kBlock) void k_merge(uint32_t N, uint32_t d, const uint64_t *lab_off,
+                                                  const typename Ent<DB>::T *lab_hd,
+                                                  const uint64_t *rstart, const uint32_t *rlen,
+                                                  const uint32_t *pool_hub, const uint64_t *new_off,
+                                                  typename Ent<DB>::T *new_hd) {
+    using E = typename Ent<DB>::T;
+    uint32_t u = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (u >= N) return;
+    uint32_t lane = threadIdx.x & 63;
+    uint64_t a0 = lab_off[u], na = lab_off[u + 1] - a0;
+    uint32_t nb = rlen[u];
+    const E *A = lab_hd + a0;
+    const uint32_t *B = pool_hub + rstart[u];
+    E *out = new_hd + new_off[u];
+    if (nb == 0) {
+        for (uint64_t i = lane; i < na; i += 64) out[i] = A[i];
+        return;
+    }
+    for (uint64_t i = lane; i < na; i += 64) {
+        E e = A[i];
+        out[i + lower_bound_u32(B, nb, e_hub<DB>(e))] = e;
+    }
+    for (uint32_t j = lane; j < nb; j += 64) {
+        uint32_t h = B[j];
+        out[j + lower_bound_hub<DB>(A, na, h)] = e_make<DB>(h, d);
+    }
+}
+
+// Widen packed entries from 8-bit to 16-bit distances.
+__global__ void k_widen(const uint32_t *src, uint64_t *dst, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        uint32_t e = src[i];
+        dst[i] = e_make<16>(e_hub<8>(e), e_dist<8>(e));
+    }
+}
+
+// Count of every final entry, from its round's segment in the pool.
+template <int DB>
+__global__ __launch_bounds__(kBlock) void k_finalize(uint32_t N, const uint64_t *lab_off,
+                                                     const typename Ent<DB>::T *lab_hd,
+                                                     const uint64_t *const *rstart_tab,
+                                                     const uint32_t *const *rlen_tab,
+                                                     const uint32_t *pool_hub,
+                                                     const uint64_t *pool_cnt, uint64_t *lab_cnt,
+                                                     unsigned long long *nsat) {
+    uint32_t u = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (u >= N) return;
+    uint32_t lane = threadIdx.x & 63;
+    uint64_t a0 = lab_off[u], na = lab_off[u + 1] - a0;
+    uint32_t sat = 0;
+    for (uint64_t i = lane; i < na; i += 64) {
+        auto e = lab_hd[a0 + i];
+        uint32_t r = e_dist<DB>(e), h = e_hub<DB>(e);
+        uint64_t ps = rstart_tab[r][u];
+        uint32_t ln = rlen_tab[r][u];
+        uint32_t p = lower_bound_u32(pool_hub + ps, ln, h);
+        uint64_t c = pool_cnt[ps + p];
+        lab_cnt[a0 + i] = c;
+        sat += (c == kSat);
+    }
+    sat = wave_sum(sat);
+    if (lane == 0 && sat) atomicAdd(nsat, (unsigned long long)sat);
+}
+
+inline uint32_t grid_for(uint64_t items, uint32_t per_block) {
+    return (uint32_t)((items + per_block - 1) / per_block);
+}
+
+inline int bit_width(uint64_t x) {
+    int b = 0;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side build state
+// ---------------------------------------------------------------------------
+struct Build {
+    Arena arena;
+    hipStream_t st;
+    uint32_t N = 0;
+    uint64_t NNZ = 0;
+    uint32_t k = 1;
+    std::vector<uint32_t> vbase, gn;
+    // graph
+    uint64_t *goff = nullptr;
+    uint32_t *gadj = nullptr;
+    uint32_t *rank_of = nullptr, *order = nullptr;
+    // labels
+    uint64_t *lab_off = nullptr, *lab_off2 = nullptr;
+    void *lab_hd = nullptr, *lab_hd2 = nullptr;
+    uint64_t lab_cap = 0, lab_cap2 = 0, entries = 0;
+    int db = 8;
+    // round pool
+    uint32_t *pool_hub = nullptr;
+    uint64_t *pool_cnt = nullptr;
+    uint64_t pool_cap = 0, pool_cnt_cap = 0, pool_used = 0;
+    std::vector<uint64_t *> rstart;
+    std::vector<uint32_t *> rlen;
+    // per-round scratch
+    uint64_t *raw = nullptr, *raw_off = nullptr, *soff = nullptr, *nlen = nullptr;
+    uint32_t *surv = nullptr;
+    uint32_t *tmp_hub = nullptr;
+    uint64_t *tmp_cnt = nullptr;
+    uint64_t tmp_cap = 0;
+    uint64_t *ws = nullptr;
+    unsigned long long *ctr = nullptr;
+    uint64_t *h_pin = nullptr;  // pinned host scratch
+    std::vector<RoundCounters> stats;
+    double ms_round_kernel = 0;
+    uint64_t alg_bytes = 0;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+
+    Build(uint64_t budget, hipStream_t s) : arena(budget), st(s) {}
+    ~Build() {
+        if (h_pin) (void)hipHostFree(h_pin);
+        if (ev_a) (void)hipEventDestroy(ev_a);
+        if (ev_b) (void)hipEventDestroy(ev_b);
+    }
+
+    spc_status read_u64(const uint64_t *dev, uint64_t *out, size_t count = 1) {
+        SPC_HIP(hipMemcpyAsync(h_pin, dev, count * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        SPC_HIP(hipStreamSynchronize(st));
+        std::memcpy(out, h_pin, count * sizeof(uint64_t));
+        return SPC_OK;
+    }
+
+    template <typename T>
+    spc_status grow(T **p, uint64_t *cap, uint64_t need, uint64_t keep) {
+        if (need <= *cap) return SPC_OK;
+        uint64_t nc = std::max<uint64_t>(need, *cap + *cap / 2);
+        T *q = nullptr;
+        spc_status s = arena.alloc(&q, nc);
+        if (s != SPC_OK && nc > need) {
+            nc = need;
+            s = arena.alloc(&q, nc);
+        }
+        SPC_TRY(s);
+        if (keep && *p) SPC_HIP(hipMemcpyAsync(q, *p, keep * sizeof(T), hipMemcpyDeviceToDevice, st));
+        if (*p) {
+            SPC_HIP(hipStreamSynchronize(st));
+            arena.release(*p);
+        }
+        *p = q;
+        *cap = nc;
+        return SPC_OK;
+    }
+};
+
+// union CSR + ordering + relabel (+ validation)
+spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_tie, bool validate) {
+    const uint32_t N = B.N;
+    const uint64_t NNZ = B.NNZ;
+    uint64_t *off = nullptr;
+    uint32_t *col = nullptr, *deg = nullptr, *err = nullptr, *vb_dev = nullptr;
+    SPC_TRY(B.arena.alloc(&off, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&col, NNZ));
+    SPC_TRY(B.arena.alloc(&deg, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&err, 2));
+    SPC_TRY(B.arena.alloc(&vb_dev, (uint64_t)B.k + 1));
+    SPC_HIP(hipMemsetAsync(err, 0, 2 * sizeof(uint32_t), B.st));
+    SPC_HIP(hipMemcpyAsync(vb_dev, B.vbase.data(), B.k * sizeof(uint32_t), hipMemcpyHostToDevice, B.st));
+
+    // staging for host inputs
+    uint64_t max_n1 = 0, max_nnz = 0;
+    for (uint32_t g = 0; g < B.k; g++) {
+        max_n1 = std::max<uint64_t>(max_n1, (uint64_t)gs[g].n + 1);
+        max_nnz = std::max<uint64_t>(max_nnz, gs[g].nnz);
+    }
+    uint64_t *st_off = nullptr;
+    uint32_t *st_col = nullptr;
+    uint64_t *st_tie = nullptr;
+    uint32_t *st_ord = nullptr;
+    bool host_in = !gs[0].on_device;
+    if (host_in) {
+        SPC_TRY(B.arena.alloc(&st_off, max_n1));
+        SPC_TRY(B.arena.alloc(&st_col, std::max<uint64_t>(max_nnz, 1)));
+        if (use_order) SPC_TRY(B.arena.alloc(&st_ord, max_n1));
+    }
+    uint64_t *tie_union = nullptr;
+    if (use_tie) SPC_TRY(B.arena.alloc(&tie_union, (uint64_t)N + 1));
+    uint32_t *ord_union = nullptr, *hits = nullptr;
+    if (use_order) {
+        SPC_TRY(B.arena.alloc(&ord_union, (uint64_t)N + 1));
+        SPC_TRY(B.arena.alloc(&hits, (uint64_t)N + 1));
+        SPC_HIP(hipMemsetAsync(hits, 0, ((uint64_t)N + 1) * sizeof(uint32_t), B.st));
+    }
+
+    uint64_t ebase = 0;
+    for (uint32_t g = 0; g < B.k; g++) {
+        const spc_graph &G = gs[g];
+        const uint64_t *src_off = G.row_off;
+        const uint32_t *src_col = G.col;
+        const uint32_t *src_ord = G.order;
+        if (host_in) {
+            SPC_HIP(hipMemcpyAsync(st_off, G.row_off, ((uint64_t)G.n + 1) * sizeof(uint64_t),
+                                   hipMemcpyHostToDevice, B.st));
+            if (G.nnz)
+                SPC_HIP(hipMemcpyAsync(st_col, G.col, G.nnz * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                       B.st));
+            if (use_order && G.n)
+                SPC_HIP(hipMemcpyAsync(st_ord, G.order, (uint64_t)G.n * sizeof(uint32_t),
+                                       hipMemcpyHostToDevice, B.st));
+            src_off = st_off;
+            src_col = st_col;
+            src_ord = st_ord;
+        }
+        hipLaunchKernelGGL(k_union_off, dim3(grid_for((uint64_t)G.n + 1, kBlock)), dim3(kBlock), 0,
+                           B.st, src_off, off + B.vbase[g], G.n, G.nnz, ebase, err);
+        SPC_LAUNCHED();
+        if (G.nnz) {
+            hipLaunchKernelGGL(k_union_col, dim3(grid_for(G.nnz, kBlock)), dim3(kBlock), 0, B.st,
+                               src_col, col + ebase, G.nnz, G.n, B.vbase[g], err);
+            SPC_LAUNCHED();
+        }
+        if (use_order && G.n) {
+            hipLaunchKernelGGL(k_union_order, dim3(grid_for(G.n, kBlock)), dim3(kBlock), 0, B.st,
+                               src_ord, ord_union, G.n, B.vbase[g], hits, err);
+            SPC_LAUNCHED();
+        }
+        if (use_tie && G.n)
+            SPC_HIP(hipMemcpyAsync(tie_union + B.vbase[g], G.tie_key, (uint64_t)G.n * sizeof(uint64_t),
+                                   G.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                   B.st));
+        if (host_in) SPC_HIP(hipStreamSynchronize(B.st));  // staging is reused
+        ebase += G.nnz;
+    }
+    if (use_order) {
+        hipLaunchKernelGGL(k_check_perm, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st, hits, N,
+                           err);
+        SPC_LAUNCHED();
+    }
+    uint64_t e2[1];
+    SPC_TRY(B.read_u64((const uint64_t *)err, e2));
+    if ((uint32_t)e2[0] != 0) return SPC_ERR_INVALID_ARG;
+    B.arena.release(st_off);
+    B.arena.release(st_col);
+    B.arena.release(st_ord);
+
+    // degrees and order
+    uint32_t *maxdeg = err + 1;
+    hipLaunchKernelGGL(k_degrees, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st, off, N, deg,
+                       maxdeg);
+    SPC_LAUNCHED();
+    SPC_TRY(B.arena.alloc(&B.order, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.rank_of, (uint64_t)N + 1));
+    if (use_order) {
+        SPC_HIP(hipMemcpyAsync(B.order, ord_union, (uint64_t)N * sizeof(uint32_t),
+                               hipMemcpyDeviceToDevice, B.st));
+    } else {
+        uint64_t md[1];
+        SPC_TRY(B.read_u64((const uint64_t *)err, md));
+        uint32_t maxd = (uint32_t)(md[0] >> 32);
+        uint64_t *keys = nullptr, *keys2 = nullptr;
+        uint32_t *vals2 = nullptr;
+        SPC_TRY(B.arena.alloc(&keys, (uint64_t)N + 1));
+        SPC_TRY(B.arena.alloc(&keys2, (uint64_t)N + 1));
+        SPC_TRY(B.arena.alloc(&vals2, (uint64_t)N + 1));
+        hipLaunchKernelGGL(k_iota_keys, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st,
+                           (const uint64_t *)tie_union, N, keys, B.order);
+        SPC_LAUNCHED();
+        if (use_tie) SPC_TRY(radix_sort_pairs(keys, B.order, keys2, vals2, N, 64, B.ws, B.st));
+        int degbits = std::max(1, bit_width(maxd));
+        hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st, B.order,
+                           deg, N, maxd, degbits, vb_dev, B.k, keys);
+        SPC_LAUNCHED();
+        int gbits = B.k > 1 ? bit_width(B.k - 1) : 0;
+        SPC_TRY(radix_sort_pairs(keys, B.order, keys2, vals2, N, degbits + gbits, B.ws, B.st));
+        B.arena.release(keys);
+        B.arena.release(keys2);
+        B.arena.release(vals2);
+    }
+    B.arena.release(tie_union);
+    B.arena.release(ord_union);
+    B.arena.release(hits);
+
+    // rank space CSR
+    uint32_t *rdeg = nullptr;
+    SPC_TRY(B.arena.alloc(&rdeg, (uint64_t)N + 1));
+    hipLaunchKernelGGL(k_rank_of, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st, B.order, N, deg,
+                       B.rank_of, rdeg);
+    SPC_LAUNCHED();
+    SPC_TRY(B.arena.alloc(&B.goff, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.gadj, std::max<uint64_t>(NNZ, 1)));
+    SPC_TRY(scan_u32(rdeg, B.goff, N, B.ws, B.st));
+    hipLaunchKernelGGL(k_relabel, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, B.order,
+                       B.rank_of, off, col, B.goff, B.gadj, N);
+    SPC_LAUNCHED();
+    B.arena.release(rdeg);
+    B.arena.release(off);
+    B.arena.release(col);
+    B.arena.release(deg);
+
+    if (validate && NNZ) {
+        int xb = std::max(1, bit_width(N));
+        uint64_t *keys = nullptr, *keys2 = nullptr;
+        SPC_TRY(B.arena.alloc(&keys, NNZ));
+        SPC_TRY(B.arena.alloc(&keys2, NNZ));
+        uint64_t *rws = nullptr;
+        SPC_TRY(B.arena.alloc(&rws, radix_ws_elems(NNZ)));
+        hipLaunchKernelGGL(k_row_keys, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, B.goff,
+                           B.gadj, N, xb, keys);
+        SPC_LAUNCHED();
+        SPC_TRY(radix_sort_pairs(keys, nullptr, keys2, nullptr, NNZ, 2 * xb, rws, B.st));
+        hipLaunchKernelGGL(k_keys_to_adj, dim3(grid_for(NNZ, kBlock)), dim3(kBlock), 0, B.st, keys,
+                           NNZ, xb, B.gadj);
+        SPC_LAUNCHED();
+        SPC_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), B.st));
+        hipLaunchKernelGGL(k_check_adj, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, B.goff,
+                           B.gadj, N, err);
+        SPC_LAUNCHED();
+        uint64_t ev[1];
+        SPC_TRY(B.read_u64((const uint64_t *)err, ev));
+        B.arena.release(keys);
+        B.arena.release(keys2);
+        B.arena.release(rws);
+        if ((uint32_t)ev[0] != 0) return SPC_ERR_INVALID_ARG;
+    }
+    B.arena.release(err);
+    B.arena.release(vb_dev);
+    return SPC_OK;
+}
+
+// largest temp buffer (entries) one batch of pullers may use
+constexpr uint64_t kTempMax = 1ull << 27;
+
+// One distance round d >= 1.  Returns the number of entries it inserted.
+template <int DB>
+spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
+    using E = typename Ent<DB>::T;
+    const uint32_t N = B.N;
+    const uint64_t *pstart = B.rstart[d - 1];
+    const uint32_t *plen = B.rlen[d - 1];
+    hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, B.goff,
+                       B.gadj, pstart, plen, B.pool_hub, B.raw);
+    SPC_LAUNCHED();
+    SPC_TRY(scan_u64(B.raw, B.raw_off, N, B.ws, B.st));
+    uint64_t total_raw;
+    SPC_TRY(B.read_u64(B.raw_off + N, &total_raw));
+    *any_cand = total_raw > 0;
+    *kept_out = 0;
+    if (total_raw == 0) return SPC_OK;
+
+    // batches of pullers whose temp space fits
+    std::vector<uint32_t> bounds{0};
+    if (total_raw <= kTempMax) {
+        bounds.push_back(N);
+    } else {
+        std::vector<uint64_t> ro((size_t)N + 1);
+        SPC_HIP(hipMemcpyAsync(ro.data(), B.raw_off, ((size_t)N + 1) * sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, B.st));
+        SPC_HIP(hipStreamSynchronize(B.st));
+        uint32_t b0 = 0;
+        while (b0 < N) {
+            uint64_t lim = ro[b0] + kTempMax;
+            uint32_t b1 = (uint32_t)(std::upper_bound(ro.begin() + b0 + 1, ro.end(), lim) - ro.begin()) - 1;
+            if (b1 <= b0) b1 = b0 + 1;
+            bounds.push_back(b1);
+            b0 = b1;
+        }
+    }
+
+    uint64_t *rs = nullptr;
+    uint32_t *rl = nullptr;
+    SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&rl, (uint64_t)N + 1));
+    B.rstart.push_back(rs);
+    B.rlen.push_back(rl);
+    SPC_HIP(hipMemsetAsync(B.ctr, 0, 8 * sizeof(unsigned long long), B.st));
+
+    uint64_t kept = 0;
+    for (size_t bi = 0; bi + 1 < bounds.size(); bi++) {
+        uint32_t b0 = bounds[bi], b1 = bounds[bi + 1];
+        uint64_t r2[2];
+        SPC_HIP(hipMemcpyAsync(B.h_pin, B.raw_off + b0, sizeof(uint64_t), hipMemcpyDeviceToHost, B.st));
+        SPC_HIP(hipMemcpyAsync(B.h_pin + 1, B.raw_off + b1, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                               B.st));
+        SPC_HIP(hipStreamSynchronize(B.st));
+        r2[0] = B.h_pin[0];
+        r2[1] = B.h_pin[1];
+        uint64_t need = r2[1] - r2[0];
+        if (need > B.tmp_cap) {
+            B.arena.release(B.tmp_hub);
+            B.arena.release(B.tmp_cnt);
+            B.tmp_cap = 0;
+            uint64_t cap = std::max<uint64_t>(need, 1024);
+            SPC_TRY(B.arena.alloc(&B.tmp_hub, cap));
+            SPC_TRY(B.arena.alloc(&B.tmp_cnt, cap));
+            B.tmp_cap = cap;
+        }
+        RoundArgs ra;
+        ra.d = d;
+        ra.u_lo = b0;
+        ra.u_hi = b1;
+        ra.goff = B.goff;
+        ra.gadj = B.gadj;
+        ra.lab_off = B.lab_off;
+        ra.lab_hd = B.lab_hd;
+        ra.pstart = pstart;
+        ra.plen = plen;
+        ra.pool_hub = B.pool_hub;
+        ra.pool_cnt = B.pool_cnt;
+        ra.raw_off = B.raw_off;
+        ra.tmp_hub = B.tmp_hub;
+        ra.tmp_cnt = B.tmp_cnt;
+        ra.surv = B.surv;
+        ra.ctr = B.ctr;
+        SPC_HIP(hipEventRecord(B.ev_a, B.st));
+        hipLaunchKernelGGL(k_round<DB>, dim3(b1 - b0), dim3(kBlock), 0, B.st, ra);
+        SPC_LAUNCHED();
+        SPC_HIP(hipEventRecord(B.ev_b, B.st));
+        SPC_TRY(scan_u32(B.surv + b0, B.soff, b1 - b0, B.ws, B.st));
+        uint64_t sb;
+        SPC_TRY(B.read_u64(B.soff + (b1 - b0), &sb));
+        float ms = 0;
+        SPC_HIP(hipEventElapsedTime(&ms, B.ev_a, B.ev_b));
+        B.ms_round_kernel += ms;
+        SPC_TRY(B.grow(&B.pool_hub, &B.pool_cap, B.pool_used + sb, B.pool_used));
+        SPC_TRY(B.grow(&B.pool_cnt, &B.pool_cnt_cap, B.pool_used + sb, B.pool_used));
+        hipLaunchKernelGGL(k_compact, dim3(grid_for(b1 - b0, kWaves)), dim3(kBlock), 0, B.st, b0, b1,
+                           B.raw_off, B.soff, B.surv, B.tmp_hub, B.tmp_cnt, B.pool_used, B.pool_hub,
+                           B.pool_cnt, rs, rl);
+        SPC_LAUNCHED();
+        B.pool_used += sb;
+        kept += sb;
+    }
+    uint64_t c[8];
+    SPC_TRY(B.read_u64((const uint64_t *)B.ctr, c, 8));
+    RoundCounters rc;
+    rc.raw = c[0];
+    rc.merged = c[1];
+    rc.kept = c[2];
+    rc.scanned = c[3];
+    B.stats.push_back(rc);
+    // algorithmic bytes of the fused kernel: CSR of the pullers, the pulled
+    // entries (hub + count), u's staged label, every probed entry, the
+    // candidates' label offsets, and the survivors written
+    uint64_t es = sizeof(E);
+    B.alg_bytes += c[0] * 12 + c[4] * es + c[3] * es + c[1] * 16 + c[2] * 12;
+    *kept_out = kept;
+    if (kept == 0) return SPC_OK;
+
+    // merge the round into the labels
+    hipLaunchKernelGGL(k_new_len, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st, N, B.lab_off, rl,
+                       B.nlen);
+    SPC_LAUNCHED();
+    SPC_TRY(scan_u64(B.nlen, B.lab_off2, N, B.ws, B.st));
+    uint64_t new_entries = B.entries + kept;
+    {
+        E *p2 = static_cast<E *>(B.lab_hd2);
+        SPC_TRY(B.grow(&p2, &B.lab_cap2, new_entries, 0));
+        B.lab_hd2 = p2;
+    }
+    hipLaunchKernelGGL(k_merge<DB>, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, d, B.lab_off,
+                       static_cast<const E *>(B.lab_hd), rs, rl, B.pool_hub, B.lab_off2,
+                       static_cast<E *>(B.lab_hd2));
+    SPC_LAUNCHED();
+    std::swap(B.lab_off, B.lab_off2);
+    std::swap(B.lab_hd, B.lab_hd2);
+    std::swap(B.lab_cap, B.lab_cap2);
+    B.entries = new_entries;
+    return SPC_OK;
+}
+
+}  // namespace
+}  // namespace spc
+
+namespace spc {
+namespace {
+
+enum class LoopEnd { Done, Widen };
+
+// Rounds d, d+1, ... with DB-bit distances until a round inserts nothing, the
+// cap is reached, or (auto width) distances outgrow 8 bits.
+template <int DB>
+spc_status rounds_loop(Build &B, uint32_t &d, uint32_t cap, bool auto_width, bool &truncated,
+                       uint32_t &last_round, LoopEnd &end) {
+    for (;; d++) {
+        if (cap && d > cap) {
+            // truncated iff round cap+1 would still pull candidates
+            const uint32_t N = B.N;
+            hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N,
+                               B.goff, B.gadj, B.rstart[d - 1], B.rlen[d - 1], B.pool_hub, B.raw);
+            SPC_LAUNCHED();
+            SPC_TRY(scan_u64(B.raw, B.raw_off, N, B.ws, B.st));
+            uint64_t tr;
+            SPC_TRY(B.read_u64(B.raw_off + N, &tr));
+            truncated = tr > 0;
+            last_round = cap;
+            end = LoopEnd::Done;
+            return SPC_OK;
+        }
+        if (d > Ent<DB>::kMaxDist) {
+            if (DB == 8 && auto_width) {
+                end = LoopEnd::Widen;
+                return SPC_OK;
+            }
+            return SPC_ERR_DIST_RANGE;
+        }
+        uint64_t kept;
+        bool any;
+        SPC_TRY(run_round<DB>(B, d, &kept, &any));
+        if (kept == 0) {
+            if (any) {
+                // the round ran its kernels but inserted nothing: record an
+                // empty segment table is not needed; nothing reads it
+            }
+            last_round = d;
+            end = LoopEnd::Done;
+            return SPC_OK;
+        }
+    }
+}
+
+spc_status widen_labels(Build &B) {
+    uint64_t *w = nullptr;
+    uint64_t cap = std::max<uint64_t>(B.entries, 1);
+    SPC_TRY(B.arena.alloc(&w, cap));
+    hipLaunchKernelGGL(k_widen, dim3(grid_for(B.entries, kBlock)), dim3(kBlock), 0, B.st,
+                       static_cast<const uint32_t *>(B.lab_hd), w, B.entries);
+    SPC_LAUNCHED();
+    SPC_HIP(hipStreamSynchronize(B.st));
+    uint32_t *old = static_cast<uint32_t *>(B.lab_hd), *old2 = static_cast<uint32_t *>(B.lab_hd2);
+    B.arena.release(old);
+    B.arena.release(old2);
+    B.lab_hd = w;
+    B.lab_hd2 = nullptr;
+    B.lab_cap = cap;
+    B.lab_cap2 = 0;
+    B.db = 16;
+    return SPC_OK;
+}
+
+template <int DB>
+spc_status finalize_counts(Build &B, uint64_t **lab_cnt, uint64_t *nsat_out) {
+    using E = typename Ent<DB>::T;
+    SPC_TRY(B.arena.alloc(lab_cnt, std::max<uint64_t>(B.entries, 1)));
+    uint64_t R = B.rstart.size();
+    uint64_t **rs_tab = nullptr;
+    uint32_t **rl_tab = nullptr;
+    SPC_TRY(B.arena.alloc(&rs_tab, R));
+    SPC_TRY(B.arena.alloc(&rl_tab, R));
+    SPC_HIP(hipMemcpyAsync(rs_tab, B.rstart.data(), R * sizeof(uint64_t *), hipMemcpyHostToDevice,
+                           B.st));
+    SPC_HIP(hipMemcpyAsync(rl_tab, B.rlen.data(), R * sizeof(uint32_t *), hipMemcpyHostToDevice, B.st));
+    SPC_HIP(hipMemsetAsync(B.ctr, 0, sizeof(unsigned long long), B.st));
+    hipLaunchKernelGGL(k_finalize<DB>, dim3(grid_for(B.N, kWaves)), dim3(kBlock), 0, B.st, B.N,
+                       B.lab_off, static_cast<const E *>(B.lab_hd), (const uint64_t *const *)rs_tab,
+                       (const uint32_t *const *)rl_tab, B.pool_hub, B.pool_cnt, *lab_cnt, B.ctr);
+    SPC_LAUNCHED();
+    SPC_TRY(B.read_u64((const uint64_t *)B.ctr, nsat_out));
+    B.arena.release(rs_tab);
+    B.arena.release(rl_tab);
+    return SPC_OK;
+}
+
+inline float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0;
+    return ms;
+}
+
+}  // namespace
+
+spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, hipStream_t st,
+                      spc_index **out) {
+    if (!gs || !o || !out || k == 0) return SPC_ERR_INVALID_ARG;
+    if (o->reserved != 0) return SPC_ERR_INVALID_ARG;
+    if (o->dist_bits != 0 && o->dist_bits != 8 && o->dist_bits != 16) return SPC_ERR_INVALID_ARG;
+    uint64_t N64 = 0, NNZ = 0;
+    uint32_t n_order = 0, n_tie = 0, n_dev = 0;
+    for (uint32_t g = 0; g < k; g++) {
+        const spc_graph &G = gs[g];
+        if (!G.row_off || (G.nnz && !G.col)) return SPC_ERR_INVALID_ARG;
+        if (G.nnz & 1) return SPC_ERR_INVALID_ARG;  // symmetric: every edge twice
+        N64 += G.n;
+        NNZ += G.nnz;
+        n_order += G.order != nullptr;
+        n_tie += G.tie_key != nullptr;
+        n_dev += G.on_device != 0;
+    }
+    if ((n_order && n_order != k) || (n_tie && n_tie != k) || (n_dev && n_dev != k))
+        return SPC_ERR_INVALID_ARG;
+    if (N64 >= 0xFFFFFFFFull) return SPC_ERR_UNSUPPORTED;
+    int db = (o->dist_bits == 16) ? 16 : 8;
+    if (db == 8 && N64 > Ent<8>::kMaxHub - 1) {
+        if (o->dist_bits == 8) return SPC_ERR_UNSUPPORTED;
+        db = 16;
+    }
+    const bool auto_width = o->dist_bits == 0;
+
+    int dev = 0;
+    SPC_HIP(hipGetDevice(&dev));
+    Build B(o->mem_budget, st);
+    B.N = (uint32_t)N64;
+    B.NNZ = NNZ;
+    B.k = k;
+    B.db = db;
+    {
+        uint32_t base = 0;
+        for (uint32_t g = 0; g < k; g++) {
+            B.vbase.push_back(base);
+            B.gn.push_back(gs[g].n);
+            base += gs[g].n;
+        }
+        B.vbase.push_back(base);
+    }
+    SPC_HIP(hipHostMalloc((void **)&B.h_pin, 64 * sizeof(uint64_t), hipHostMallocDefault));
+    SPC_HIP(hipEventCreate(&B.ev_a));
+    SPC_HIP(hipEventCreate(&B.ev_b));
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < 4; i++)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } evg{ev};
+    for (int i = 0; i < 4; i++) SPC_HIP(hipEventCreate(&ev[i]));
+    const uint32_t N = B.N;
+    if (N == 0) {  // nothing to order or label: an empty index
+        if (NNZ) return SPC_ERR_INVALID_ARG;
+        spc_index *ix = new (std::nothrow) spc_index();
+        if (!ix) return SPC_ERR_OUT_OF_MEMORY;
+        SPC_TRY(B.arena.alloc(&ix->lab_off, 1));
+        SPC_HIP(hipMemsetAsync(ix->lab_off, 0, sizeof(uint64_t), st));
+        uint32_t *hd = nullptr;
+        SPC_TRY(B.arena.alloc(&hd, 1));
+        ix->lab_hd = hd;
+        SPC_TRY(B.arena.alloc(&ix->lab_cnt, 1));
+        SPC_TRY(B.arena.alloc(&ix->rank_of, 1));
+        SPC_TRY(B.arena.alloc(&ix->order, 1));
+        SPC_HIP(hipStreamSynchronize(st));
+        ix->device = dev;
+        ix->dist_bits = (uint32_t)db;
+        ix->vbase.assign(B.vbase.begin(), B.vbase.end());
+        ix->gn = B.gn;
+        ix->round_stats.push_back(RoundCounters());
+        ix->index_bytes = B.arena.detach(ix->lab_off) + B.arena.detach(hd) +
+                          B.arena.detach(ix->lab_cnt) + B.arena.detach(ix->rank_of) +
+                          B.arena.detach(ix->order);
+        *out = ix;
+        return SPC_OK;
+    }
+    SPC_TRY(B.arena.alloc(&B.ws, std::max(radix_ws_elems((uint64_t)N + 1), scan_ws_elems((uint64_t)N + 1))));
+    SPC_TRY(B.arena.alloc(&B.ctr, 8));
+
+    SPC_HIP(hipEventRecord(ev[0], st));
+    SPC_TRY(preprocess(B, gs, n_order == k, n_tie == k, o->validate != 0));
+    SPC_HIP(hipEventRecord(ev[1], st));
+
+    // round 0
+    SPC_TRY(B.arena.alloc(&B.raw, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.raw_off, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.soff, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.nlen, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.surv, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.lab_off, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.lab_off2, (uint64_t)N + 1));
+    {
+        uint64_t pcap = (uint64_t)N + std::max<uint64_t>(NNZ, 1024);
+        SPC_TRY(B.arena.alloc(&B.pool_hub, pcap));
+        SPC_TRY(B.arena.alloc(&B.pool_cnt, pcap));
+        B.pool_cap = B.pool_cnt_cap = pcap;
+        uint64_t *rs = nullptr;
+        uint32_t *rl = nullptr;
+        SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
+        SPC_TRY(B.arena.alloc(&rl, (uint64_t)N + 1));
+        B.rstart.push_back(rs);
+        B.rlen.push_back(rl);
+        uint64_t lcap = std::max<uint64_t>((uint64_t)N + NNZ / 2, 1024);
+        if (db == 8) {
+            uint32_t *h = nullptr;
+            SPC_TRY(B.arena.alloc(&h, lcap));
+            B.lab_hd = h;
+            hipLaunchKernelGGL(k_round0<8>, dim3(grid_for((uint64_t)N + 1, kBlock)), dim3(kBlock), 0,
+                               st, N, B.pool_hub, B.pool_cnt, rs, rl, B.lab_off, h);
+        } else {
+            uint64_t *h = nullptr;
+            SPC_TRY(B.arena.alloc(&h, lcap));
+            B.lab_hd = h;
+            hipLaunchKernelGGL(k_round0<16>, dim3(grid_for((uint64_t)N + 1, kBlock)), dim3(kBlock), 0,
+                               st, N, B.pool_hub, B.pool_cnt, rs, rl, B.lab_off, h);
+        }
+        SPC_LAUNCHED();
+        B.lab_cap = lcap;
+        B.pool_used = N;
+        B.entries = N;
+        RoundCounters r0;
+        r0.kept = N;
+        B.stats.push_back(r0);
+    }
+
+    uint32_t d = 1, last_round = 0;
+    bool truncated = false;
+    if (N > 0) {
+        while (true) {
+            LoopEnd end;
+            if (B.db == 8)
+                SPC_TRY(rounds_loop<8>(B, d, o->round_cap, auto_width, truncated, last_round, end));
+            else
+                SPC_TRY(rounds_loop<16>(B, d, o->round_cap, auto_width, truncated, last_round, end));
+            if (end == LoopEnd::Widen) {
+                SPC_TRY(widen_labels(B));
+                continue;
+            }
+            break;
+        }
+    }
+    SPC_HIP(hipEventRecord(ev[2], st));
+    uint64_t *lab_cnt = nullptr;
+    uint64_t nsat = 0;
+    if (B.db == 8)
+        SPC_TRY(finalize_counts<8>(B, &lab_cnt, &nsat));
+    else
+        SPC_TRY(finalize_counts<16>(B, &lab_cnt, &nsat));
+    SPC_HIP(hipEventRecord(ev[3], st));
+    SPC_HIP(hipStreamSynchronize(st));
+
+    spc_index *ix = new (std::nothrow) spc_index();
+    if (!ix) return SPC_ERR_OUT_OF_MEMORY;
+    ix->device = dev;
+    ix->n = N;
+    ix->m = NNZ / 2;
+    ix->dist_bits = (uint32_t)B.db;
+    ix->rounds = last_round;
+    ix->round_cap = o->round_cap;
+    ix->truncated = truncated;
+    ix->entries = B.entries;
+    ix->saturated = nsat;
+    uint32_t maxd = 0;
+    for (size_t r = 0; r < B.stats.size(); r++)
+        if (B.stats[r].kept) maxd = (uint32_t)r;
+    ix->max_dist = maxd;
+    ix->vbase.assign(B.vbase.begin(), B.vbase.end());
+    ix->gn = B.gn;
+    ix->round_stats = B.stats;
+    ix->peak_build_bytes = B.arena.peak();
+    ix->ms_order = elapsed(ev[0], ev[1]);
+    ix->ms_rounds = elapsed(ev[1], ev[2]);
+    ix->ms_finalize = elapsed(ev[2], ev[3]);
+    ix->ms_total = elapsed(ev[0], ev[3]);
+    ix->ms_round_kernel = B.ms_round_kernel;
+    ix->alg_bytes_round_kernel = B.alg_bytes;
+    ix->lab_off = B.lab_off;
+    ix->lab_hd = B.lab_hd;
+    ix->lab_cnt = lab_cnt;
+    ix->rank_of = B.rank_of;
+    ix->order = B.order;
+    ix->index_bytes = B.arena.detach(B.lab_off) + B.arena.detach(B.lab_hd) + B.arena.detach(lab_cnt) +
+                      B.arena.detach(B.rank_of) + B.arena.detach(B.order);
+    *out = ix;
+    return SPC_OK;
+}
+
+}  // namespace spc

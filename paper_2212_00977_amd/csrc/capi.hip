@@ -1,0 +1,109 @@
+// C ABI entry points (declared in include/spc.h).  Each call validates its
+// host-side arguments, then runs the library's kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "spc_internal.h"
+
+extern "C" {
+
+const char *spc_status_string(spc_status s) {
+    switch (s) {
+        case SPC_OK: return "ok";
+        case SPC_ERR_INVALID_ARG: return "invalid argument";
+        case SPC_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case SPC_ERR_DEVICE: return "device error";
+        case SPC_ERR_DIST_RANGE: return "distance exceeds the label width";
+        case SPC_ERR_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+spc_status spc_build_index(const spc_graph *g, const spc_build_opts *opts, void *stream,
+                           spc_index **out) {
+    if (!g || !opts || !out) return SPC_ERR_INVALID_ARG;
+    return spc::build_impl(g, 1, opts, static_cast<hipStream_t>(stream), out);
+}
+
+spc_status spc_build_index_batch(const spc_graph *gs, uint32_t k, const spc_build_opts *opts,
+                                 void *stream, spc_index **out) {
+    if (!gs || k == 0 || !opts || !out) return SPC_ERR_INVALID_ARG;
+    return spc::build_impl(gs, k, opts, static_cast<hipStream_t>(stream), out);
+}
+
+spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
+                           const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                           uint8_t *flags_out, void *stream) {
+    return spc::query_impl(ix, graph_id, s, t, nq, dist_out, count_out, flags_out,
+                           static_cast<hipStream_t>(stream));
+}
+
+void spc_free(spc_index *ix) {
+    if (!ix) return;
+    (void)hipFree(ix->lab_off);
+    (void)hipFree(ix->lab_hd);
+    (void)hipFree(ix->lab_cnt);
+    (void)hipFree(ix->rank_of);
+    (void)hipFree(ix->order);
+    delete ix;
+}
+
+spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
+    if (!ix || !out) return SPC_ERR_INVALID_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->n = ix->n;
+    out->num_graphs = (uint32_t)ix->gn.size();
+    out->m = ix->m;
+    out->entries = ix->entries;
+    out->rounds = ix->rounds;
+    out->max_dist = ix->max_dist;
+    out->dist_bits = ix->dist_bits;
+    out->truncated = ix->truncated ? 1u : 0u;
+    out->saturated_entries = ix->saturated;
+    out->index_bytes = ix->index_bytes;
+    out->peak_build_bytes = ix->peak_build_bytes;
+    out->ms_order = ix->ms_order;
+    out->ms_rounds = ix->ms_rounds;
+    out->ms_finalize = ix->ms_finalize;
+    out->ms_total = ix->ms_total;
+    out->ms_round_kernel = ix->ms_round_kernel;
+    out->alg_bytes_round_kernel = ix->alg_bytes_round_kernel;
+    return SPC_OK;
+}
+
+spc_status spc_round_stats(const spc_index *ix, uint32_t max_rounds, uint64_t *raw, uint64_t *merged,
+                           uint64_t *kept, uint64_t *scanned) {
+    if (!ix) return SPC_ERR_INVALID_ARG;
+    for (uint32_t r = 0; r < max_rounds; r++) {
+        spc::RoundCounters c;
+        if (r < ix->round_stats.size()) c = ix->round_stats[r];
+        if (raw) raw[r] = c.raw;
+        if (merged) merged[r] = c.merged;
+        if (kept) kept[r] = c.kept;
+        if (scanned) scanned[r] = c.scanned;
+    }
+    return SPC_OK;
+}
+
+spc_status spc_graph_entries(const spc_index *ix, uint32_t graph_id, uint32_t *n_out,
+                             uint64_t *entries_out) {
+    if (!ix || graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
+    uint32_t vb = ix->vbase[graph_id], n = ix->gn[graph_id];
+    uint64_t e[2] = {0, 0};
+    if (hipMemcpy(&e[0], ix->lab_off + vb, 8, hipMemcpyDeviceToHost) != hipSuccess) return SPC_ERR_DEVICE;
+    if (hipMemcpy(&e[1], ix->lab_off + vb + n, 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return SPC_ERR_DEVICE;
+    if (n_out) *n_out = n;
+    if (entries_out) *entries_out = e[1] - e[0];
+    return SPC_OK;
+}
+
+spc_status spc_export_labels(const spc_index *ix, uint32_t graph_id, uint64_t *off, uint32_t *hub,
+                             uint16_t *dist, uint64_t *count, uint32_t *order, int32_t on_device,
+                             void *stream) {
+    return spc::export_impl(ix, graph_id, off, hub, dist, count, order, on_device,
+                            static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

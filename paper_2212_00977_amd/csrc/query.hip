@@ -1,0 +1,230 @@
+// SPC queries over the finished index (Eq. con:spc1 and con:spc2) and label
+// export, gfx950.
+//
+// A query (s, t) merges the hub-sorted labels L(s) and L(t): the common hubs
+// with the least d_s + d_t form H, and the answer is the saturating sum of
+// count_s * count_t over H.  One wave per query walks both labels in tiles of
+// 64 entries (coalesced loads); each lane looks its L(s) entry's hub up in
+// the current L(t) tile with a 6-step binary search over lane shuffles, and
+// the tile whose last hub is smaller advances (both on a tie).  Every pair of
+// equal hubs meets exactly once: while one of them is in the current tile,
+// the other list's tile cannot move past it.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "spc_internal.h"
+
+namespace spc {
+
+namespace {
+
+struct QueryArgs {
+    const uint64_t *lab_off;
+    const void *lab_hd;
+    const uint64_t *lab_cnt;
+    const uint32_t *rank_of;
+    const uint32_t *s, *t;
+    uint64_t nq;
+    uint32_t vbase, gn;     // graph view
+    uint32_t cap;           // round cap of a truncated index, 0 otherwise
+    void *dist_out;
+    uint64_t *count_out;
+    uint8_t *flags_out;
+};
+
+template <int DB>
+__global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
+    using E = typename Ent<DB>::T;
+    using DT = typename std::conditional<DB == 8, uint8_t, uint16_t>::type;
+    const uint64_t q = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (q >= a.nq) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const E *hd = static_cast<const E *>(a.lab_hd);
+    const uint32_t s = a.s[q], t = a.t[q];
+    const DT kInf = (DT)~(DT)0;
+    if (s >= a.gn || t >= a.gn) {
+        if (lane == 0) {
+            static_cast<DT *>(a.dist_out)[q] = kInf;
+            a.count_out[q] = 0;
+            if (a.flags_out) a.flags_out[q] = SPC_FLAG_INVALID;
+        }
+        return;
+    }
+    const uint32_t rs = a.rank_of[a.vbase + s], rt = a.rank_of[a.vbase + t];
+    const uint64_t as = a.lab_off[rs], na = a.lab_off[rs + 1] - as;
+    const uint64_t bs = a.lab_off[rt], nb = a.lab_off[rt + 1] - bs;
+    uint32_t best = 0xFFFFFFFFu;
+    uint64_t sum = 0;
+    uint64_t ia = 0, ib = 0;
+    while (ia < na && ib < nb) {
+        const bool va = ia + lane < na, vb = ib + lane < nb;
+        const E ea = va ? hd[as + ia + lane] : (E)~(E)0;
+        const E eb = vb ? hd[bs + ib + lane] : (E)~(E)0;
+        const uint32_t ha = va ? e_hub<DB>(ea) : 0xFFFFFFFFu;
+        const uint32_t hb = vb ? e_hub<DB>(eb) : 0xFFFFFFFFu;
+        // lower bound of ha among the 64 hubs of the B tile
+        uint32_t p = 0;
+#pragma unroll
+        for (uint32_t step = 32; step > 0; step >>= 1) {
+            uint32_t x = __shfl(hb, (int)(p + step - 1), 64);
+            if (x < ha) p += step;
+        }
+        const uint32_t pc = p < 64 ? p : 63;
+        const uint32_t hp = __shfl(hb, (int)pc, 64);
+        const E ep = __shfl(eb, (int)pc, 64);
+        if (va && p < 64 && hp == ha) {
+            uint32_t dd = e_dist<DB>(ea) + e_dist<DB>(ep);
+            if (dd <= best) {
+                uint64_t c = sat_mul(a.lab_cnt[as + ia + lane], a.lab_cnt[bs + ib + pc]);
+                sum = (dd < best) ? c : sat_add(sum, c);
+                best = dd;
+            }
+        }
+        const uint64_t la = (na - ia < 64) ? na - ia - 1 : 63;
+        const uint64_t lb = (nb - ib < 64) ? nb - ib - 1 : 63;
+        const uint32_t lasta = __shfl(ha, (int)la, 64);
+        const uint32_t lastb = __shfl(hb, (int)lb, 64);
+        if (lasta <= lastb) ia += 64;
+        if (lastb <= lasta) ib += 64;
+    }
+    // wave reduction: least distance, then the saturating sum at it
+    uint32_t mn = best;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
+    uint64_t part = (best == mn) ? sum : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part = sat_add(part, __shfl_xor(part, o, 64));
+    if (lane == 0) {
+        uint8_t fl = 0;
+        DT dout;
+        uint64_t cout;
+        if (mn == 0xFFFFFFFFu) {
+            dout = kInf;
+            cout = 0;
+            fl |= SPC_FLAG_UNREACHABLE;
+            if (a.cap) fl |= SPC_FLAG_HORIZON;
+        } else {
+            dout = (DT)mn;
+            cout = part;
+            if (part == kSat) fl |= SPC_FLAG_SATURATED;
+            if (a.cap && mn > a.cap) fl |= SPC_FLAG_HORIZON;
+        }
+        static_cast<DT *>(a.dist_out)[q] = dout;
+        a.count_out[q] = cout;
+        if (a.flags_out) a.flags_out[q] = fl;
+    }
+}
+
+// Export kernels: labels of one graph, rank space of that graph.
+__global__ void k_export_off(const uint64_t *lab_off, uint32_t vbase, uint32_t n, uint64_t *off) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) off[i] = lab_off[vbase + i] - lab_off[vbase];
+}
+template <int DB>
+__global__ void k_export_ent(const typename Ent<DB>::T *hd, const uint64_t *cnt, uint64_t e0,
+                             uint64_t ne, uint32_t vbase, uint32_t *hub, uint16_t *dist,
+                             uint64_t *count) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    auto e = hd[e0 + i];
+    if (hub) hub[i] = e_hub<DB>(e) - vbase;
+    if (dist) dist[i] = (uint16_t)e_dist<DB>(e);
+    if (count) count[i] = cnt[e0 + i];
+}
+__global__ void k_export_order(const uint32_t *order, uint32_t vbase, uint32_t n, uint32_t *out) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = order[vbase + i] - vbase;
+}
+
+inline uint32_t grid1(uint64_t items) { return (uint32_t)((items + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                      uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
+                      hipStream_t st) {
+    if (!ix) return SPC_ERR_INVALID_ARG;
+    if (graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
+    if (nq == 0) return SPC_OK;
+    if (!s || !t || !dist_out || !count_out) return SPC_ERR_INVALID_ARG;
+    QueryArgs a;
+    a.lab_off = ix->lab_off;
+    a.lab_hd = ix->lab_hd;
+    a.lab_cnt = ix->lab_cnt;
+    a.rank_of = ix->rank_of;
+    a.s = s;
+    a.t = t;
+    a.nq = nq;
+    a.vbase = ix->vbase[graph_id];
+    a.gn = ix->gn[graph_id];
+    a.cap = ix->truncated ? ix->round_cap : 0;
+    a.dist_out = dist_out;
+    a.count_out = count_out;
+    a.flags_out = flags_out;
+    uint64_t blocks = (nq + kWaves - 1) / kWaves;
+    if (blocks > 0x7FFFFFFFull) return SPC_ERR_INVALID_ARG;
+    if (ix->dist_bits == 8)
+        hipLaunchKernelGGL(k_query<8>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_query<16>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, a);
+    SPC_LAUNCHED();
+    return SPC_OK;
+}
+
+spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, uint32_t *hub,
+                       uint16_t *dist, uint64_t *count, uint32_t *order, int32_t on_device,
+                       hipStream_t st) {
+    if (!ix || graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
+    const uint32_t vb = ix->vbase[graph_id], n = ix->gn[graph_id];
+    uint64_t e0 = 0, e1 = 0;
+    SPC_HIP(hipMemcpy(&e0, ix->lab_off + vb, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    SPC_HIP(hipMemcpy(&e1, ix->lab_off + vb + n, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    const uint64_t ne = e1 - e0;
+    // device staging when the destination is host memory
+    uint64_t *d_off = off;
+    uint32_t *d_hub = hub, *d_ord = order;
+    uint16_t *d_dist = dist;
+    uint64_t *d_cnt = count;
+    Arena tmp(0);
+    if (!on_device) {
+        if (off) SPC_TRY(tmp.alloc(&d_off, (uint64_t)n + 1));
+        if (hub) SPC_TRY(tmp.alloc(&d_hub, ne));
+        if (dist) SPC_TRY(tmp.alloc(&d_dist, ne));
+        if (count) SPC_TRY(tmp.alloc(&d_cnt, ne));
+        if (order) SPC_TRY(tmp.alloc(&d_ord, (uint64_t)n));
+    }
+    if (off) {
+        hipLaunchKernelGGL(k_export_off, dim3(grid1((uint64_t)n + 1)), dim3(kBlock), 0, st,
+                           ix->lab_off, vb, n, d_off);
+        SPC_LAUNCHED();
+    }
+    if ((hub || dist || count) && ne) {
+        if (ix->dist_bits == 8)
+            hipLaunchKernelGGL(k_export_ent<8>, dim3(grid1(ne)), dim3(kBlock), 0, st,
+                               static_cast<const uint32_t *>(ix->lab_hd), ix->lab_cnt, e0, ne, vb,
+                               hub ? d_hub : nullptr, dist ? d_dist : nullptr,
+                               count ? d_cnt : nullptr);
+        else
+            hipLaunchKernelGGL(k_export_ent<16>, dim3(grid1(ne)), dim3(kBlock), 0, st,
+                               static_cast<const uint64_t *>(ix->lab_hd), ix->lab_cnt, e0, ne, vb,
+                               hub ? d_hub : nullptr, dist ? d_dist : nullptr,
+                               count ? d_cnt : nullptr);
+        SPC_LAUNCHED();
+    }
+    if (order && n) {
+        hipLaunchKernelGGL(k_export_order, dim3(grid1(n)), dim3(kBlock), 0, st, ix->order, vb, n, d_ord);
+        SPC_LAUNCHED();
+    }
+    if (!on_device) {
+        if (off) SPC_HIP(hipMemcpyAsync(off, d_off, ((uint64_t)n + 1) * 8, hipMemcpyDeviceToHost, st));
+        if (hub && ne) SPC_HIP(hipMemcpyAsync(hub, d_hub, ne * 4, hipMemcpyDeviceToHost, st));
+        if (dist && ne) SPC_HIP(hipMemcpyAsync(dist, d_dist, ne * 2, hipMemcpyDeviceToHost, st));
+        if (count && ne) SPC_HIP(hipMemcpyAsync(count, d_cnt, ne * 8, hipMemcpyDeviceToHost, st));
+        if (order && n) SPC_HIP(hipMemcpyAsync(order, d_ord, (uint64_t)n * 4, hipMemcpyDeviceToHost, st));
+    }
+    SPC_HIP(hipStreamSynchronize(st));
+    return SPC_OK;
+}
+
+}  // namespace spc

@@ -1,0 +1,264 @@
+// Internal declarations of the gfx950 SPC label library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <unordered_map>
+#include <vector>
+
+#include "spc.h"
+
+namespace spc {
+
+constexpr uint64_t kSat = 0xFFFFFFFFFFFFFFFFull;
+constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+constexpr int kBlock = 256;  // threads per workgroup everywhere (4 wave64)
+constexpr int kWaves = kBlock / 64;
+
+#define SPC_TRY(expr)                          \
+    do {                                       \
+        spc_status _st = (expr);               \
+        if (_st != SPC_OK) return _st;         \
+    } while (0)
+#define SPC_HIP(expr)                                \
+    do {                                             \
+        if ((expr) != hipSuccess) return SPC_ERR_DEVICE; \
+    } while (0)
+#define SPC_LAUNCHED()                                         \
+    do {                                                       \
+        if (hipGetLastError() != hipSuccess) return SPC_ERR_DEVICE; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
+    uint64_t s = a + b;
+    return s < a ? kSat : s;
+}
+__device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b) {
+    return __umul64hi(a, b) ? kSat : a * b;
+}
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (1ull << (threadIdx.x & 63)) - 1ull;
+}
+
+
+// inclusive scan across the 64 lanes of a wave
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T x = __shfl_up(v, o, 64);
+        if (lane >= o) v += x;
+    }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// exclusive scan over the kBlock threads of a block; `total` gets the block
+// sum.  lds must hold kWaves values; every thread of the block must call it.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *lds, T &total) {
+    T inc = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; i++) {
+        T x = lds[i];
+        pre += (i < w) ? x : (T)0;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + inc - v;
+}
+
+// Packed label entry: hub in the high bits, distance in the low bits, so the
+// packed value sorts by hub.  8-bit distances use a u32 (hub < 2^24),
+// 16-bit distances a u64.
+template <int DB>
+struct Ent;
+template <>
+struct Ent<8> {
+    using T = uint32_t;
+    static constexpr int kShift = 8;
+    static constexpr uint32_t kDistMask = 0xFFu;
+    static constexpr uint32_t kMaxDist = 254;  // 255 is INF in query outputs
+    static constexpr uint64_t kMaxHub = (1ull << 24) - 1;
+};
+template <>
+struct Ent<16> {
+    using T = uint64_t;
+    static constexpr int kShift = 16;
+    static constexpr uint32_t kDistMask = 0xFFFFu;
+    static constexpr uint32_t kMaxDist = 65534;
+    static constexpr uint64_t kMaxHub = 0xFFFFFFFEull;
+};
+template <int DB>
+__device__ __host__ __forceinline__ uint32_t e_hub(typename Ent<DB>::T e) {
+    return (uint32_t)(e >> Ent<DB>::kShift);
+}
+template <int DB>
+__device__ __host__ __forceinline__ uint32_t e_dist(typename Ent<DB>::T e) {
+    return (uint32_t)(e & Ent<DB>::kDistMask);
+}
+template <int DB>
+__device__ __host__ __forceinline__ typename Ent<DB>::T e_make(uint32_t hub, uint32_t d) {
+    return ((typename Ent<DB>::T)hub << Ent<DB>::kShift) | (typename Ent<DB>::T)d;
+}
+
+// first index i in [0, len) with a[i] >= key (a sorted ascending)
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t len, uint32_t key) {
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+// same over packed entries, comparing hubs
+template <int DB>
+__device__ __forceinline__ uint64_t lower_bound_hub(const typename Ent<DB>::T *a, uint64_t len,
+                                                    uint32_t hub) {
+    uint64_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (e_hub<DB>(a[mid]) < hub)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory accounting (per build): every allocation is checked against
+// the caller's budget; whatever is still held when the arena dies is freed
+// unless it was handed over to the index.
+// ---------------------------------------------------------------------------
+class Arena {
+  public:
+    explicit Arena(uint64_t budget) : budget_(budget) {}
+    ~Arena() {
+        for (auto &kv : sizes_) (void)hipFree(kv.first);
+    }
+    Arena(const Arena &) = delete;
+    Arena &operator=(const Arena &) = delete;
+
+    template <typename T>
+    spc_status alloc(T **p, size_t count) {
+        void *q = nullptr;
+        size_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 256;
+        bytes = (bytes + 255) & ~size_t(255);
+        if (budget_ && used_ + bytes > budget_) return SPC_ERR_OUT_OF_MEMORY;
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return SPC_ERR_OUT_OF_MEMORY;
+        }
+        sizes_[q] = bytes;
+        used_ += bytes;
+        if (used_ > peak_) peak_ = used_;
+        *p = static_cast<T *>(q);
+        return SPC_OK;
+    }
+    template <typename T>
+    void release(T *&p) {
+        if (!p) return;
+        auto it = sizes_.find((void *)p);
+        if (it != sizes_.end()) {
+            used_ -= it->second;
+            sizes_.erase(it);
+        }
+        (void)hipFree((void *)p);
+        p = nullptr;
+    }
+    // hand an allocation to the index: the arena stops tracking it
+    template <typename T>
+    uint64_t detach(T *p) {
+        auto it = sizes_.find((void *)p);
+        if (it == sizes_.end()) return 0;
+        uint64_t b = it->second;
+        sizes_.erase(it);
+        return b;
+    }
+    uint64_t used() const { return used_; }
+    uint64_t peak() const { return peak_; }
+
+  private:
+    uint64_t budget_;
+    uint64_t used_ = 0, peak_ = 0;
+    std::unordered_map<void *, size_t> sizes_;
+};
+
+// ---------------------------------------------------------------------------
+// Library-wide primitives (scan.hip, sort.hip)
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum: out[i] = sum in[0..i), out[n] = total.  `ws` must hold
+// scan_ws_elems(n) uint64 values.
+size_t scan_ws_elems(uint64_t n);
+spc_status scan_u32(const uint32_t *in, uint64_t *out, uint64_t n, uint64_t *ws, hipStream_t st);
+spc_status scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, uint64_t *ws, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits), in
+// place (ping-pong through the alt buffers; the result ends in keys/vals).
+size_t radix_ws_elems(uint64_t n);
+spc_status radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                            uint64_t n, int bits, uint64_t *ws, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// The index
+// ---------------------------------------------------------------------------
+struct RoundCounters {
+    uint64_t raw = 0, merged = 0, kept = 0, scanned = 0;
+};
+
+}  // namespace spc
+
+struct spc_index {
+    int device = 0;
+    uint32_t n = 0;       // all vertices (union for batches)
+    uint64_t m = 0;       // undirected edges
+    uint32_t dist_bits = 8;
+    uint32_t rounds = 0, max_dist = 0, round_cap = 0;
+    bool truncated = false;
+    uint64_t entries = 0, saturated = 0;
+    // final index, rank space (hub-sorted labels)
+    uint64_t *lab_off = nullptr;  // [n+1]
+    void *lab_hd = nullptr;       // packed (hub, dist)[entries]
+    uint64_t *lab_cnt = nullptr;  // [entries]
+    uint32_t *rank_of = nullptr;  // vertex -> rank (union ids)
+    uint32_t *order = nullptr;    // rank -> vertex (union ids)
+    // graphs of a batch: vertex/rank range [vbase[i], vbase[i] + gn[i])
+    std::vector<uint32_t> vbase, gn;
+    std::vector<spc::RoundCounters> round_stats;
+    uint64_t index_bytes = 0, peak_build_bytes = 0;
+    double ms_order = 0, ms_rounds = 0, ms_finalize = 0, ms_total = 0, ms_round_kernel = 0;
+    uint64_t alg_bytes_round_kernel = 0;
+};
+
+namespace spc {
+// build.hip
+spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *opts, hipStream_t st,
+                      spc_index **out);
+// query.hip
+spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                      uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
+                      hipStream_t st);
+spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, uint32_t *hub,
+                       uint16_t *dist, uint64_t *count, uint32_t *order, int32_t on_device,
+                       hipStream_t st);
+}  // namespace spc

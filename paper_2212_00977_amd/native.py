@@ -1,0 +1,97 @@
+"""Build and load ``libspc.so``, the gfx950 HIP library behind include/spc.h.
+
+The library is compiled in-tree with hipcc for gfx950 only.  Loading fails
+loudly when it is missing: there is no CPU fallback for any entry point.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIBDIR = os.path.join(PKG, "lib")
+LIBPATH = os.path.join(LIBDIR, "libspc.so")
+SOURCES = ["primitives.hip", "build.hip", "query.hip", "capi.hip"]
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_free",
+           "spc_index_stats", "spc_round_stats", "spc_graph_entries", "spc_export_labels",
+           "spc_status_string"]
+
+
+def build_library(verbose: bool = False) -> str:
+    """Compile every HIP source into libspc.so (always recompiles)."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    tmp = LIBPATH + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I", INCLUDE, "-o", tmp,
+           *[os.path.join(CSRC, s) for s in SOURCES]]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+    if verbose:
+        print(r.stderr)
+    os.replace(tmp, LIBPATH)
+    return LIBPATH
+
+
+class SpcStats(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("num_graphs", C.c_uint32), ("m", C.c_uint64),
+                ("entries", C.c_uint64), ("rounds", C.c_uint32), ("max_dist", C.c_uint32),
+                ("dist_bits", C.c_uint32), ("truncated", C.c_uint32),
+                ("saturated_entries", C.c_uint64), ("index_bytes", C.c_uint64),
+                ("peak_build_bytes", C.c_uint64), ("ms_order", C.c_double),
+                ("ms_rounds", C.c_double), ("ms_finalize", C.c_double), ("ms_total", C.c_double),
+                ("ms_round_kernel", C.c_double), ("alg_bytes_round_kernel", C.c_uint64)]
+
+
+class SpcGraph(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("nnz", C.c_uint64), ("row_off", C.c_void_p),
+                ("col", C.c_void_p), ("order", C.c_void_p), ("tie_key", C.c_void_p),
+                ("on_device", C.c_int32)]
+
+
+class SpcBuildOpts(C.Structure):
+    _fields_ = [("dist_bits", C.c_uint32), ("round_cap", C.c_uint32),
+                ("mem_budget", C.c_uint64), ("validate", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libspc.so (torch is imported first so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (HIP runtime of the process)
+    path = path or LIBPATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"libspc.so not built ({path}); run __graft_entry__.build()")
+    L = C.CDLL(path)
+    vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
+    L.spc_build_index.argtypes = [C.POINTER(SpcGraph), C.POINTER(SpcBuildOpts), vp, C.POINTER(vp)]
+    L.spc_build_index.restype = C.c_int
+    L.spc_build_index_batch.argtypes = [C.POINTER(SpcGraph), u32, C.POINTER(SpcBuildOpts), vp,
+                                        C.POINTER(vp)]
+    L.spc_build_index_batch.restype = C.c_int
+    L.spc_query_batch.argtypes = [vp, u32, vp, vp, u64, vp, vp, vp, vp]
+    L.spc_query_batch.restype = C.c_int
+    L.spc_free.argtypes = [vp]
+    L.spc_free.restype = None
+    L.spc_index_stats.argtypes = [vp, C.POINTER(SpcStats)]
+    L.spc_index_stats.restype = C.c_int
+    L.spc_round_stats.argtypes = [vp, u32, vp, vp, vp, vp]
+    L.spc_round_stats.restype = C.c_int
+    L.spc_graph_entries.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(u64)]
+    L.spc_graph_entries.restype = C.c_int
+    L.spc_export_labels.argtypes = [vp, u32, vp, vp, vp, vp, vp, i32, vp]
+    L.spc_export_labels.restype = C.c_int
+    L.spc_status_string.argtypes = [C.c_int]
+    L.spc_status_string.restype = C.c_char_p
+    _lib = L
+    return L

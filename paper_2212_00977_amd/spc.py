@@ -1,0 +1,258 @@
+"""Python binding of the SPC label library: argument marshalling only.
+
+Every step (ordering, distance rounds, counts, queries) runs in the HIP
+kernels of libspc.so.  torch provides device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import native
+
+SPC_OK = 0
+STATUS = {0: "SPC_OK", 1: "SPC_ERR_INVALID_ARG", 2: "SPC_ERR_OUT_OF_MEMORY", 3: "SPC_ERR_DEVICE",
+          4: "SPC_ERR_DIST_RANGE", 5: "SPC_ERR_UNSUPPORTED"}
+FLAG_SATURATED, FLAG_UNREACHABLE, FLAG_HORIZON, FLAG_INVALID = 1, 2, 4, 8
+
+
+class SpcError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        lib = native.load()
+        super().__init__(f"{where}: {STATUS.get(code, code)} "
+                         f"({lib.spc_status_string(code).decode()})")
+
+
+def _check(code: int, where: str):
+    if code != SPC_OK:
+        raise SpcError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(a, dtype_np, dtype_t, device):
+    """Contiguous device tensor holding `a` (numpy array or tensor) with the
+    bit pattern of dtype_np."""
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device)
+        if t.dtype != dtype_t:
+            t = t.to(dtype_t)
+        return t.contiguous()
+    arr = np.ascontiguousarray(np.asarray(a, dtype=dtype_np))
+    return torch.from_numpy(arr.view(_np_view(dtype_t))).to(device)
+
+
+def _np_view(dtype_t):
+    torch = _torch()
+    return {torch.int32: np.int32, torch.int64: np.int64, torch.int16: np.int16,
+            torch.uint8: np.uint8}[dtype_t]
+
+
+def _graph_struct(off, adj, order, tie_key, device, keep):
+    torch = _torch()
+    off_t = _dev(off, np.uint64, torch.int64, device)
+    n = off_t.shape[0] - 1
+    adj_t = _dev(adj, np.uint32, torch.int32, device) if int(np.asarray(adj.shape[0])) else \
+        torch.zeros(1, dtype=torch.int32, device=device)
+    nnz = int(adj.shape[0])
+    g = native.SpcGraph()
+    g.n = n
+    g.nnz = nnz
+    g.row_off = off_t.data_ptr()
+    g.col = adj_t.data_ptr()
+    keep += [off_t, adj_t]
+    if order is not None:
+        o = _dev(order, np.uint32, torch.int32, device)
+        keep.append(o)
+        g.order = o.data_ptr()
+    if tie_key is not None:
+        tk = _dev(tie_key, np.uint64, torch.int64, device)
+        keep.append(tk)
+        g.tie_key = tk.data_ptr()
+    g.on_device = 1
+    return g
+
+
+@dataclass
+class BuildOptions:
+    dist_bits: int = 0
+    round_cap: int = 0
+    mem_budget: int = 0
+    validate: bool = True
+
+    def struct(self):
+        o = native.SpcBuildOpts()
+        o.dist_bits = self.dist_bits
+        o.round_cap = self.round_cap
+        o.mem_budget = self.mem_budget
+        o.validate = 1 if self.validate else 0
+        o.reserved = 0
+        return o
+
+
+class Index:
+    """A built SPC label index resident in device memory."""
+
+    def __init__(self, handle: C.c_void_p, device):
+        self._h = handle
+        self.device = device
+        self._stats = None
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            native.load().spc_free(self._h)
+        self._h = None
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("index freed")
+        return self._h
+
+    def stats(self) -> dict:
+        st = native.SpcStats()
+        _check(native.load().spc_index_stats(self.handle, C.byref(st)), "spc_index_stats")
+        return {f: getattr(st, f) for f, _ in native.SpcStats._fields_}
+
+    def round_stats(self) -> dict:
+        R = self.stats()["rounds"] + 1
+        arrs = {k: np.zeros(R, dtype=np.uint64) for k in ("raw", "merged", "kept", "scanned")}
+        _check(native.load().spc_round_stats(self.handle, R, *(arrs[k].ctypes.data for k in
+                                                                ("raw", "merged", "kept",
+                                                                 "scanned"))),
+               "spc_round_stats")
+        return arrs
+
+    def graph_entries(self, graph_id: int = 0):
+        n = C.c_uint32()
+        e = C.c_uint64()
+        _check(native.load().spc_graph_entries(self.handle, graph_id, C.byref(n), C.byref(e)),
+               "spc_graph_entries")
+        return n.value, e.value
+
+    def query(self, s, t, graph_id: int = 0, stream=None, out=None):
+        """SPC(s, t) for vertex ids of graph `graph_id`.  Returns device
+        tensors (dist uint8 / int16-as-uint16, count int64-as-uint64,
+        flags uint8), written asynchronously on `stream`."""
+        torch = _torch()
+        s_t = _dev(s, np.uint32, torch.int32, self.device)
+        t_t = _dev(t, np.uint32, torch.int32, self.device)
+        nq = int(s_t.shape[0])
+        if int(t_t.shape[0]) != nq:
+            raise ValueError("s and t differ in length")
+        bits = self.dist_bits
+        if out is None:
+            dist = torch.empty(max(nq, 1), dtype=torch.uint8 if bits == 8 else torch.int16,
+                               device=self.device)
+            cnt = torch.empty(max(nq, 1), dtype=torch.int64, device=self.device)
+            flags = torch.empty(max(nq, 1), dtype=torch.uint8, device=self.device)
+        else:
+            dist, cnt, flags = out
+        rc = native.load().spc_query_batch(self.handle, graph_id, s_t.data_ptr(), t_t.data_ptr(),
+                                           nq, dist.data_ptr(), cnt.data_ptr(),
+                                           flags.data_ptr() if flags is not None else None,
+                                           _stream_handle(stream))
+        _check(rc, "spc_query_batch")
+        self._keep = (s_t, t_t)  # inputs stay alive until the next call
+        return dist[:nq], cnt[:nq], (flags[:nq] if flags is not None else None)
+
+    @property
+    def dist_bits(self) -> int:
+        if self._stats is None:
+            self._stats = self.stats()
+        return self._stats["dist_bits"]
+
+    def export(self, graph_id: int = 0):
+        """Labels of one graph in its rank space, on the host (numpy):
+        off, hub, dist (uint16), count (uint64), order (rank -> vertex)."""
+        n, e = self.graph_entries(graph_id)
+        off = np.zeros(n + 1, dtype=np.uint64)
+        hub = np.zeros(max(e, 1), dtype=np.uint32)
+        dist = np.zeros(max(e, 1), dtype=np.uint16)
+        cnt = np.zeros(max(e, 1), dtype=np.uint64)
+        order = np.zeros(max(n, 1), dtype=np.uint32)
+        rc = native.load().spc_export_labels(self.handle, graph_id, off.ctypes.data,
+                                             hub.ctypes.data, dist.ctypes.data, cnt.ctypes.data,
+                                             order.ctypes.data, 0, _stream_handle(None))
+        _check(rc, "spc_export_labels")
+        return dict(off=off, hub=hub[:e], dist=dist[:e], count=cnt[:e], order=order[:n])
+
+    def export_device(self, graph_id: int = 0):
+        """Same as export() into device tensors (int32/int16/int64 bit views)."""
+        torch = _torch()
+        n, e = self.graph_entries(graph_id)
+        dev = self.device
+        off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        hub = torch.empty(max(e, 1), dtype=torch.int32, device=dev)
+        dist = torch.empty(max(e, 1), dtype=torch.int16, device=dev)
+        cnt = torch.empty(max(e, 1), dtype=torch.int64, device=dev)
+        order = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        rc = native.load().spc_export_labels(self.handle, graph_id, off.data_ptr(), hub.data_ptr(),
+                                             dist.data_ptr(), cnt.data_ptr(), order.data_ptr(), 1,
+                                             _stream_handle(None))
+        _check(rc, "spc_export_labels")
+        return dict(off=off, hub=hub[:e], dist=dist[:e], count=cnt[:e], order=order[:n])
+
+
+def build_index(off, adj, order=None, tie_key=None, opts: BuildOptions | None = None,
+                device=None, stream=None) -> Index:
+    """Build the SPC label index of one graph (symmetric CSR off/adj, numpy or
+    torch).  Inputs are placed in device memory first."""
+    torch = _torch()
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    keep = []
+    g = _graph_struct(off, adj, order, tie_key, device, keep)
+    o = (opts or BuildOptions()).struct()
+    h = C.c_void_p()
+    rc = native.load().spc_build_index(C.byref(g), C.byref(o), _stream_handle(stream), C.byref(h))
+    _check(rc, "spc_build_index")
+    return Index(h, device)
+
+
+def build_graph(graph, opts: BuildOptions | None = None, device=None, stream=None) -> Index:
+    """build_index for an inputs.Graph (its explicit order / tie keys)."""
+    return build_index(graph.off, graph.adj, order=graph.order, tie_key=graph.tie_key, opts=opts,
+                       device=device, stream=stream)
+
+
+def build_index_batch(graphs, opts: BuildOptions | None = None, device=None, stream=None) -> Index:
+    """One index over many independent graphs (inputs.Graph objects)."""
+    torch = _torch()
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    keep = []
+    arr = (native.SpcGraph * len(graphs))()
+    for i, g in enumerate(graphs):
+        arr[i] = _graph_struct(g.off, g.adj, g.order, g.tie_key, device, keep)
+    o = (opts or BuildOptions()).struct()
+    h = C.c_void_p()
+    rc = native.load().spc_build_index_batch(arr, len(graphs), C.byref(o), _stream_handle(stream),
+                                             C.byref(h))
+    _check(rc, "spc_build_index_batch")
+    return Index(h, device)
+
+
+def as_u64(count_tensor) -> np.ndarray:
+    """Host uint64 view of a count tensor (int64 bit pattern)."""
+    return count_tensor.cpu().numpy().view(np.uint64)
+
+
+def as_dist(dist_tensor) -> np.ndarray:
+    """Host uint16 view of a dist tensor (uint8 or int16 bit pattern)."""
+    a = dist_tensor.cpu().numpy()
+    return a.astype(np.uint16) if a.dtype == np.uint8 else a.view(np.uint16)

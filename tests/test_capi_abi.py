@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/spc.h (CPU only: no compute call is made).  Host-side argument
+checks that return before any device work are exercised too."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2212_00977_amd import native
+
+HEADER = os.path.join(native.INCLUDE, "spc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spc_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(native.LIBPATH):
+        native.build_library()
+    return native.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("spc_build_index", "spc_query_batch", "spc_free"):
+        assert required in names
+    assert set(names) == set(native.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in range(6):
+        s = lib.spc_status_string(code)
+        assert s and len(s) > 1
+    assert lib.spc_status_string(99) == b"unknown status"
+
+
+def test_null_arguments_rejected_on_host(lib):
+    out = C.c_void_p()
+    assert lib.spc_build_index(None, None, None, C.byref(out)) == 1
+    assert lib.spc_build_index_batch(None, 0, None, None, C.byref(out)) == 1
+    assert lib.spc_query_batch(None, 0, None, None, 1, None, None, None, None) == 1
+    st = native.SpcStats()
+    assert lib.spc_index_stats(None, C.byref(st)) == 1
+    assert lib.spc_round_stats(None, 1, None, None, None, None) == 1
+    assert lib.spc_export_labels(None, 0, None, None, None, None, None, 0, None) == 1
+    lib.spc_free(None)  # no-op
+    assert out.value is None
+
+
+def test_bad_options_rejected_on_host(lib):
+    g = native.SpcGraph()
+    g.n = 4
+    g.nnz = 3  # odd: cannot be a symmetric CSR
+    g.row_off = 1
+    g.col = 1
+    o = native.SpcBuildOpts()
+    out = C.c_void_p()
+    assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
+    g.nnz = 2
+    o.dist_bits = 12
+    assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
+    o.dist_bits = 0
+    o.reserved = 7
+    assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
+    assert out.value is None

@@ -302,6 +302,33 @@ def test_invariants_and_stats():
         assert raw == int(L.stats["raw"][d]) and merged == int(L.stats["merged"][d]), d
 
 
+def test_scanned_counter_in_hub_order():
+    """Probe entries read in hub order, recounted from the final labels."""
+    g = inputs.erdos_renyi(150, 500, seed=21)
+    L = oracle.build_graph(g, method="pull")
+    n = g.n
+    roff, radj = oracle.relabel(g.off, g.adj, L.order)
+    lab = [[(int(L.hub[i]), int(L.dist[i])) for i in range(int(L.off[r]), int(L.off[r + 1]))]
+           for r in range(n)]
+    for d in range(1, L.rounds + 1):
+        scanned = 0
+        for u in range(n):
+            du = {h: x for h, x in lab[u] if x < d}
+            cands = set()
+            for k in range(int(roff[u]), int(roff[u + 1])):
+                v = int(radj[k])
+                cands.update(w for w, x in lab[v] if x == d - 1 and w < u and w not in du)
+            for w in cands:
+                lw = [(h, x) for h, x in lab[w] if x < d]   # hub-sorted already
+                k = len(lw)
+                for i, (h, x) in enumerate(lw):
+                    if h in du and du[h] + x < d:
+                        k = i + 1
+                        break
+                scanned += k
+        assert scanned == int(L.stats["scanned"][d]), d
+
+
 def test_depth_cap_is_distance_partial_set():
     g = inputs.grid_lcc(16, 0.05, seed=3)
     full = oracle.build_graph(g, method="pruned")
