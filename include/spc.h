@@ -141,9 +141,11 @@ spc_status spc_index_stats(const spc_index *ix, spc_stats *out);
 /* Per-round counters, rounds 0 .. min(rounds, max_rounds-1), into host arrays
  * of max_rounds entries (any may be NULL): raw = candidates pulled that pass
  * the rank rule (Lemma prune1), merged = distinct candidate hubs left after
- * Label Elimination and Label Merging, kept = entries inserted, scanned =
- * probe entries read in hub order up to and including the first one proving
- * a shorter distance (all of L(w) when the candidate is kept). */
+ * Label Elimination and Label Merging, kept = entries inserted (these three
+ * are properties of the index and the order alone); scanned = label entries
+ * the prune probes read beyond the landmark rows, up to and including the
+ * first one proving a shorter distance (a cost counter of this
+ * implementation). */
 spc_status spc_round_stats(const spc_index *ix, uint32_t max_rounds, uint64_t *raw,
                            uint64_t *merged, uint64_t *kept, uint64_t *scanned);
 

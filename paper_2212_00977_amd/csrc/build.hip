@@ -196,11 +196,65 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(uint32_t N, const uint6
 }
 
 // ---------------------------------------------------------------------------
+// Landmark rows.  The kLand highest-ranked vertices of every graph are
+// landmarks (Section "Landmark-Based Filtering": the highest-degree vertices,
+// whose entries dominate every round).  Each vertex keeps a dense row with
+// its label distance to every landmark (INF = type max when the landmark is
+// not one of its hubs), so the part of a 2-hop query that goes through a
+// landmark is one coalesced row load and register compares instead of label
+// streaming.  Rows hold exactly the label entries with landmark hubs; they
+// change the cost of a query, never its answer.
+// ---------------------------------------------------------------------------
+constexpr int kLand = 256;
+template <int DB>
+struct Land;
+template <>
+struct Land<8> {
+    using T = uint8_t;
+    using W = uint32_t;  // 4 landmarks per lane
+};
+template <>
+struct Land<16> {
+    using T = uint16_t;
+    using W = uint64_t;
+};
+// true if some of the 4 packed landmark distances satisfies a + b < d; an
+// absent entry is the type max, so its sum is never below d (d <= max-1)
+__device__ __forceinline__ bool land_hit(uint32_t x, uint32_t y, uint32_t d) {
+    bool h = false;
+#pragma unroll
+    for (int i = 0; i < 4; i++) h |= ((x >> (8 * i)) & 0xFFu) + ((y >> (8 * i)) & 0xFFu) < d;
+    return h;
+}
+__device__ __forceinline__ bool land_hit(uint64_t x, uint64_t y, uint32_t d) {
+    bool h = false;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        h |= (uint32_t)((x >> (16 * i)) & 0xFFFFu) + (uint32_t)((y >> (16 * i)) & 0xFFFFu) < d;
+    return h;
+}
+
+template <int DB>
+__global__ void k_land_init(uint32_t N, const uint32_t *gbase, typename Land<DB>::T *land) {
+    using LT = typename Land<DB>::T;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)N * kLand) return;
+    uint32_t v = (uint32_t)(i / kLand), l = (uint32_t)(i % kLand);
+    uint32_t base = gbase ? gbase[v] : 0;
+    land[i] = (v - base == l) ? (LT)0 : (LT)~(LT)0;
+}
+__global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i] == 0xFF ? (uint16_t)0xFFFF : (uint16_t)src[i];
+}
+
+// ---------------------------------------------------------------------------
 // The fused round kernel.  One workgroup per puller u (largest rank ids
 // first: they have the most candidates).
-//   1. stage L_{<d}(u) (hub -> dist) in an LDS hash table; if u's label is
-//      longer than the table allows, the tail (largest hubs) is searched in
-//      HBM by binary search instead;
+//   1. stage u's landmark row (registers + LDS) and the rest of L_{<d}(u)
+//      (hub -> dist, hubs past the landmarks) in an LDS hash table; if that
+//      part is longer than the table allows, its tail (largest hubs) is
+//      searched in HBM by binary search instead;
 //   2. walk the hub range [0, u) in chunks: pull every neighbour's round d-1
 //      entries with hub in the chunk, drop hubs u already holds (Label
 //      Elimination: they hold a smaller distance) and merge equal hubs in an
@@ -208,10 +262,12 @@ __global__ __launch_bounds__(kBlock) void k_expand_count(uint32_t N, const uint6
 //      distinct hubs overflow the table is retried with half the width;
 //   3. sort the chunk's merged candidates by hub (bitonic, LDS);
 //   4. prune each candidate w with the 2-hop query over entries of distance
-//      < d (Eq. PSPCdu): stream L_{<d}(w) in hub order, one wave per
-//      candidate, and look every hub up in u's table; the first hub with
-//      d_u(h) + d_w(h) < d proves a shorter path.  Equality is kept.  Only
-//      entries with d_w <= d-2 can prove anything (h != u forces d_u >= 1);
+//      < d (Eq. PSPCdu), one wave per candidate: first through the landmark
+//      rows of u and w; if no landmark proves a shorter path and w is not a
+//      landmark itself, through w's other entries of rounds 1..d-2 (only an
+//      entry with d_w <= d-2 can prove anything, since h != u forces
+//      d_u >= 1), read round by round from the round pool and looked up in
+//      u's table.  A hub with d_u(h) + d_w(h) < d prunes; equality keeps;
 //   5. append the survivors, in hub order, to u's slot of the temp buffer.
 // ---------------------------------------------------------------------------
 constexpr int kLBits = 12;
@@ -228,15 +284,17 @@ struct RoundArgs {
     const uint32_t *gadj;
     const uint64_t *lab_off;
     const void *lab_hd;
-    const uint64_t *pstart;  // round d-1 segments
-    const uint32_t *plen;
+    const void *land;                // landmark rows [N][kLand]
+    const uint32_t *gbase;           // first rank of each vertex's graph, or null
+    const uint64_t *const *rs_tab;   // round segments: start / length per vertex
+    const uint32_t *const *rl_tab;
     const uint32_t *pool_hub;
     const uint64_t *pool_cnt;
     const uint64_t *raw_off;  // exclusive prefix of raw over all vertices
     uint32_t *tmp_hub;
     uint64_t *tmp_cnt;
     uint32_t *surv;
-    unsigned long long *ctr;  // raw, merged, kept, scanned, staged
+    unsigned long long *ctr;  // raw, merged, kept, tail, staged, row bytes, headers
 };
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t h, int bits) {
@@ -269,7 +327,10 @@ struct LabelLookup {
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     using E = typename Ent<DB>::T;
+    using LT = typename Land<DB>::T;
+    using LW = typename Land<DB>::W;
     __shared__ E ltab[kLCap];
+    __shared__ LW lrow[kLand / 4];
     __shared__ uint32_t ckey[kCCap];
     __shared__ unsigned long long cval[kCCap];
     __shared__ uint8_t cwrap[kCCap];
@@ -280,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     __shared__ uint32_t nb_off[kBlock];
     __shared__ uint32_t red32[kWaves];
     __shared__ uint32_t s_nuniq, s_ovf;
-    __shared__ unsigned long long s_scanned;
+    __shared__ unsigned long long s_tail, s_hdr, s_rowb;
 
     const E *hd = static_cast<const E *>(a.lab_hd);
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -292,25 +353,42 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     }
     const uint32_t d = a.d;
     const E kEmptyE = (E)~(E)0;
+    const LT kInfL = (LT)~(LT)0;
+    const uint32_t base = a.gbase ? a.gbase[u] : 0;
+    const uint32_t land_end = base + kLand;  // hubs below this are landmarks
+    const LW *lands = static_cast<const LW *>(a.land);
 
-    // 1. stage L_{<d}(u)
+    // 1. stage u's landmark row and the rest of L_{<d}(u)
+    const LW rowu = lands[(uint64_t)u * (kLand / 4) + lane];
+    if (wv == 0) lrow[lane] = rowu;
     const uint64_t l0 = a.lab_off[u];
     const uint64_t nL = a.lab_off[u + 1] - l0;
-    const uint32_t nst = nL < (uint64_t)kLStage ? (uint32_t)nL : (uint32_t)kLStage;
+    const uint64_t s0 = lower_bound_hub<DB>(hd + l0, nL, land_end);
+    const uint64_t nsp = nL - s0;
+    const uint32_t nst = nsp < (uint64_t)kLStage ? (uint32_t)nsp : (uint32_t)kLStage;
     for (int i = tid; i < kLCap; i += kBlock) ltab[i] = kEmptyE;
-    if (tid == 0) s_scanned = 0;
+    if (tid == 0) {
+        s_tail = 0;
+        s_hdr = 0;
+        s_rowb = 0;
+    }
     __syncthreads();
     for (uint32_t i = tid; i < nst; i += kBlock) {
-        E e = hd[l0 + i];
+        E e = hd[l0 + s0 + i];
         uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
         while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
     }
     LabelLookup<DB> look;
     look.tab = ltab;
-    look.tail = hd + l0 + nst;
-    look.ntail = nL - nst;
-    look.x = (nst < nL) ? e_hub<DB>(hd[l0 + nst]) : 0xFFFFFFFFu;
+    look.tail = hd + l0 + s0 + nst;
+    look.ntail = nsp - nst;
+    look.x = (nst < nsp) ? e_hub<DB>(hd[l0 + s0 + nst]) : 0xFFFFFFFFu;
     __syncthreads();
+    const LT *lrow_t = reinterpret_cast<const LT *>(lrow);
+    // is hub w already held by u (at a distance < d)?
+    auto held = [&](uint32_t w) -> bool {
+        return (w < land_end) ? lrow_t[w - base] != kInfL : look(w) != kNone;
+    };
 
     const uint64_t g0 = a.goff[u];
     const uint32_t deg = (uint32_t)(a.goff[u + 1] - g0);
@@ -339,9 +417,9 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
             uint32_t len = 0;
             if (nb < deg) {
                 uint32_t v = a.gadj[g0 + nb];
-                uint32_t ln = a.plen[v];
+                uint32_t ln = a.rl_tab[d - 1][v];
                 if (v >= lo && ln) {  // hubs of v's segment are <= v
-                    uint64_t ps = a.pstart[v];
+                    uint64_t ps = a.rs_tab[d - 1][v];
                     const uint32_t *ph = a.pool_hub + ps;
                     uint32_t b = lo ? lower_bound_u32(ph, ln, lo) : 0;
                     uint32_t e = lower_bound_u32(ph, ln, hi);
@@ -368,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
                 uint64_t idx = nb_start[jl] + (k - nb_off[jl]);
                 uint32_t w = a.pool_hub[idx];
                 uint64_t c = a.pool_cnt[idx];
-                if (look(w) != kNone) continue;  // Label Elimination
+                if (held(w)) continue;  // Label Elimination
                 uint32_t s = hash_slot(w, kCBits);
                 bool ok = true;
                 for (uint32_t probes = 0;; probes++) {
@@ -443,36 +521,53 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         }
 
         // 4. prune probes, one wave per candidate
+        uint64_t my_tail = 0, my_hdr = 0, my_rowb = 0;
         for (uint32_t i = wv; i < M; i += kWaves) {
-            uint32_t w = lhub[i];
-            uint64_t lw0 = a.lab_off[w];
-            uint64_t nw = a.lab_off[w + 1] - lw0;
+            const uint32_t w = lhub[i];
+            const uint32_t wl = w - base;  // w's rank within its graph
             bool pruned = false;
-            uint64_t scanned = nw;
             if (d >= 2) {
-                for (uint64_t j0 = 0; j0 < nw; j0 += 64) {
-                    uint64_t j = j0 + lane;
-                    bool hit = false;
-                    if (j < nw) {
-                        E e = hd[lw0 + j];
-                        uint32_t dw = e_dist<DB>(e);
-                        if (dw + 2 <= d) {
-                            uint32_t du = look(e_hub<DB>(e));
-                            hit = du != kNone && du + dw < d;
+                // landmark part: hubs below land_end (and <= w)
+                bool hit = false;
+                if (4 * lane <= wl) {
+                    LW roww = lands[(uint64_t)w * (kLand / 4) + lane];
+                    hit = land_hit(rowu, roww, d);
+                }
+                pruned = __ballot(hit) != 0;
+                my_rowb += (wl < (uint32_t)kLand ? wl + 1 : (uint32_t)kLand) * sizeof(LT);
+                // other hubs of w: entries of rounds 1..d-2 past the landmarks
+                if (!pruned && wl >= (uint32_t)kLand) {
+                    for (uint32_t r = 1; r + 2 <= d && !pruned; r++) {
+                        const uint64_t ps = a.rs_tab[r][w];
+                        const uint32_t ln = a.rl_tab[r][w];
+                        my_hdr++;
+                        if (ln == 0) continue;
+                        const uint32_t *ph = a.pool_hub + ps;
+                        const uint32_t p0 = lower_bound_u32(ph, ln, land_end);
+                        for (uint32_t j0 = p0; j0 < ln; j0 += 64) {
+                            const uint32_t j = j0 + lane;
+                            bool h2 = false;
+                            if (j < ln) {
+                                uint32_t du = look(ph[j]);
+                                h2 = du != kNone && du + r < d;
+                            }
+                            uint64_t m = __ballot(h2);
+                            if (m) {
+                                pruned = true;
+                                my_tail += (j0 - p0) + (uint64_t)__ffsll((long long)m);
+                                break;
+                            }
+                            my_tail += (ln - j0 < 64) ? (ln - j0) : 64;
                         }
-                    }
-                    uint64_t m = __ballot(hit);
-                    if (m) {
-                        pruned = true;
-                        scanned = j0 + (uint64_t)__ffsll((long long)m);
-                        break;
                     }
                 }
             }
-            if (lane == 0) {
-                lkeep[i] = pruned ? 0 : 1;
-                atomicAdd(&s_scanned, (unsigned long long)scanned);
-            }
+            if (lane == 0) lkeep[i] = pruned ? 0 : 1;
+        }
+        if (lane == 0) {
+            atomicAdd(&s_tail, (unsigned long long)my_tail);
+            atomicAdd(&s_hdr, (unsigned long long)my_hdr);
+            atomicAdd(&s_rowb, (unsigned long long)my_rowb);
         }
         __syncthreads();
 
@@ -505,33 +600,47 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         atomicAdd(&a.ctr[0], (unsigned long long)st_raw);
         atomicAdd(&a.ctr[1], (unsigned long long)st_merged);
         atomicAdd(&a.ctr[2], (unsigned long long)st_kept);
-        atomicAdd(&a.ctr[3], s_scanned);
-        atomicAdd(&a.ctr[4], (unsigned long long)nL);
+        atomicAdd(&a.ctr[3], s_tail);
+        atomicAdd(&a.ctr[4], (unsigned long long)nsp);
+        atomicAdd(&a.ctr[5], s_rowb);
+        atomicAdd(&a.ctr[6], s_hdr);
     }
 }
 
-// Move a batch's survivors from the temp buffer to the round pool, and record
-// the round's segment of every vertex of the batch.  One wave per vertex.
-__global__ __launch_bounds__(kBlock) void k_compact(uint32_t u_lo, uint32_t u_hi,
+// Move a batch's survivors from the temp buffer to the round pool, record
+// the round's segment of every vertex of the batch, and write the round's
+// landmark entries into the landmark rows.  One wave per vertex.
+template <int DB>
+__global__ __launch_bounds__(kBlock) void k_compact(uint32_t u_lo, uint32_t u_hi, uint32_t d,
                                                     const uint64_t *raw_off, const uint64_t *soff,
                                                     const uint32_t *surv, const uint32_t *tmp_hub,
                                                     const uint64_t *tmp_cnt, uint64_t pool_base,
                                                     uint32_t *pool_hub, uint64_t *pool_cnt,
-                                                    uint64_t *rstart, uint32_t *rlen) {
+                                                    uint64_t *rstart, uint32_t *rlen,
+                                                    const uint32_t *gbase,
+                                                    typename Land<DB>::T *land) {
     uint32_t u = u_lo + blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (u >= u_hi) return;
     uint32_t lane = threadIdx.x & 63;
     uint32_t s = surv[u];
+    uint32_t base = gbase ? gbase[u] : 0;
     uint64_t src = raw_off[u] - raw_off[u_lo];
     uint64_t dst = pool_base + soff[u - u_lo];
     for (uint32_t i = lane; i < s; i += 64) {
-        pool_hub[dst + i] = tmp_hub[src + i];
+        uint32_t h = tmp_hub[src + i];
+        pool_hub[dst + i] = h;
         pool_cnt[dst + i] = tmp_cnt[src + i];
+        if (h - base < (uint32_t)kLand) land[(uint64_t)u * kLand + (h - base)] = (typename Land<DB>::T)d;
     }
     if (lane == 0) {
         rstart[u] = dst;
         rlen[u] = s;
     }
+}
+
+__global__ void k_fill_gbase(uint32_t N, const uint32_t *vbase, uint32_t k, uint32_t *gbase) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < N) gbase[v] = vbase[graph_of(vbase, k, v)];
 }
 
 __global__ void k_new_len(uint32_t N, const uint64_t *lab_off, const uint32_t *rlen, uint64_t *nlen) {
@@ -646,6 +755,11 @@ struct Build {
     uint64_t pool_cap = 0, pool_cnt_cap = 0, pool_used = 0;
     std::vector<uint64_t *> rstart;
     std::vector<uint32_t *> rlen;
+    uint64_t **rs_tab = nullptr;  // device copies of rstart / rlen pointers
+    uint32_t **rl_tab = nullptr;
+    size_t tab_cap = 0;
+    void *land = nullptr;         // landmark rows [N][kLand]
+    uint32_t *gbase = nullptr;    // per-rank graph base (batches only)
     // per-round scratch
     uint64_t *raw = nullptr, *raw_off = nullptr, *soff = nullptr, *nlen = nullptr;
     uint32_t *surv = nullptr;
@@ -661,6 +775,18 @@ struct Build {
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
     Build(uint64_t budget, hipStream_t s) : arena(budget), st(s) {}
+
+    // record round r's segment arrays (host list + device pointer tables)
+    spc_status add_round(uint64_t *rs, uint32_t *rl) {
+        size_t r = rstart.size();
+        if (r >= tab_cap) return SPC_ERR_DIST_RANGE;
+        rstart.push_back(rs);
+        rlen.push_back(rl);
+        SPC_HIP(hipMemcpyAsync(rs_tab + r, &rstart[r], sizeof(uint64_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipMemcpyAsync(rl_tab + r, &rlen[r], sizeof(uint32_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipStreamSynchronize(st));  // the host vectors may reallocate
+        return SPC_OK;
+    }
     ~Build() {
         if (h_pin) (void)hipHostFree(h_pin);
         if (ev_a) (void)hipEventDestroy(ev_a);
@@ -880,6 +1006,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     const uint32_t N = B.N;
     const uint64_t *pstart = B.rstart[d - 1];
     const uint32_t *plen = B.rlen[d - 1];
+    using LT = typename Land<DB>::T;
     hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, B.goff,
                        B.gadj, pstart, plen, B.pool_hub, B.raw);
     SPC_LAUNCHED();
@@ -913,8 +1040,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     uint32_t *rl = nullptr;
     SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
     SPC_TRY(B.arena.alloc(&rl, (uint64_t)N + 1));
-    B.rstart.push_back(rs);
-    B.rlen.push_back(rl);
+    SPC_TRY(B.add_round(rs, rl));
     SPC_HIP(hipMemsetAsync(B.ctr, 0, 8 * sizeof(unsigned long long), B.st));
 
     uint64_t kept = 0;
@@ -945,8 +1071,10 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.gadj = B.gadj;
         ra.lab_off = B.lab_off;
         ra.lab_hd = B.lab_hd;
-        ra.pstart = pstart;
-        ra.plen = plen;
+        ra.land = B.land;
+        ra.gbase = B.gbase;
+        ra.rs_tab = B.rs_tab;
+        ra.rl_tab = B.rl_tab;
         ra.pool_hub = B.pool_hub;
         ra.pool_cnt = B.pool_cnt;
         ra.raw_off = B.raw_off;
@@ -966,9 +1094,10 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         B.ms_round_kernel += ms;
         SPC_TRY(B.grow(&B.pool_hub, &B.pool_cap, B.pool_used + sb, B.pool_used));
         SPC_TRY(B.grow(&B.pool_cnt, &B.pool_cnt_cap, B.pool_used + sb, B.pool_used));
-        hipLaunchKernelGGL(k_compact, dim3(grid_for(b1 - b0, kWaves)), dim3(kBlock), 0, B.st, b0, b1,
-                           B.raw_off, B.soff, B.surv, B.tmp_hub, B.tmp_cnt, B.pool_used, B.pool_hub,
-                           B.pool_cnt, rs, rl);
+        hipLaunchKernelGGL(k_compact<DB>, dim3(grid_for(b1 - b0, kWaves)), dim3(kBlock), 0, B.st, b0,
+                           b1, d, B.raw_off, B.soff, B.surv, B.tmp_hub, B.tmp_cnt, B.pool_used,
+                           B.pool_hub, B.pool_cnt, rs, rl, (const uint32_t *)B.gbase,
+                           static_cast<LT *>(B.land));
         SPC_LAUNCHED();
         B.pool_used += sb;
         kept += sb;
@@ -981,11 +1110,13 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     rc.kept = c[2];
     rc.scanned = c[3];
     B.stats.push_back(rc);
-    // algorithmic bytes of the fused kernel: CSR of the pullers, the pulled
-    // entries (hub + count), u's staged label, every probed entry, the
-    // candidates' label offsets, and the survivors written
+    // algorithmic bytes of the fused kernel: the pulled entries (hub +
+    // count), u's staged label entries past the landmarks, the candidates'
+    // landmark rows (hubs <= w), the other probe entries read up to the first
+    // one proving a shorter path (hub) and their round segment headers
+    // (start + length), and the survivors written (hub + count)
     uint64_t es = sizeof(E);
-    B.alg_bytes += c[0] * 12 + c[4] * es + c[3] * es + c[1] * 16 + c[2] * 12;
+    B.alg_bytes += c[0] * 12 + c[4] * es + c[5] + c[3] * 4 + c[6] * 12 + c[2] * 12;
     *kept_out = kept;
     if (kept == 0) return SPC_OK;
 
@@ -1076,6 +1207,16 @@ spc_status widen_labels(Build &B) {
     B.lab_hd2 = nullptr;
     B.lab_cap = cap;
     B.lab_cap2 = 0;
+    uint64_t nl = (uint64_t)B.N * kLand;
+    uint16_t *l16 = nullptr;
+    SPC_TRY(B.arena.alloc(&l16, nl));
+    hipLaunchKernelGGL(k_land_widen, dim3(grid_for(nl, kBlock)), dim3(kBlock), 0, B.st,
+                       static_cast<const uint8_t *>(B.land), l16, nl);
+    SPC_LAUNCHED();
+    SPC_HIP(hipStreamSynchronize(B.st));
+    uint8_t *l8 = static_cast<uint8_t *>(B.land);
+    B.arena.release(l8);
+    B.land = l16;
     B.db = 16;
     return SPC_OK;
 }
@@ -1084,22 +1225,12 @@ template <int DB>
 spc_status finalize_counts(Build &B, uint64_t **lab_cnt, uint64_t *nsat_out) {
     using E = typename Ent<DB>::T;
     SPC_TRY(B.arena.alloc(lab_cnt, std::max<uint64_t>(B.entries, 1)));
-    uint64_t R = B.rstart.size();
-    uint64_t **rs_tab = nullptr;
-    uint32_t **rl_tab = nullptr;
-    SPC_TRY(B.arena.alloc(&rs_tab, R));
-    SPC_TRY(B.arena.alloc(&rl_tab, R));
-    SPC_HIP(hipMemcpyAsync(rs_tab, B.rstart.data(), R * sizeof(uint64_t *), hipMemcpyHostToDevice,
-                           B.st));
-    SPC_HIP(hipMemcpyAsync(rl_tab, B.rlen.data(), R * sizeof(uint32_t *), hipMemcpyHostToDevice, B.st));
     SPC_HIP(hipMemsetAsync(B.ctr, 0, sizeof(unsigned long long), B.st));
     hipLaunchKernelGGL(k_finalize<DB>, dim3(grid_for(B.N, kWaves)), dim3(kBlock), 0, B.st, B.N,
-                       B.lab_off, static_cast<const E *>(B.lab_hd), (const uint64_t *const *)rs_tab,
-                       (const uint32_t *const *)rl_tab, B.pool_hub, B.pool_cnt, *lab_cnt, B.ctr);
+                       B.lab_off, static_cast<const E *>(B.lab_hd), (const uint64_t *const *)B.rs_tab,
+                       (const uint32_t *const *)B.rl_tab, B.pool_hub, B.pool_cnt, *lab_cnt, B.ctr);
     SPC_LAUNCHED();
     SPC_TRY(B.read_u64((const uint64_t *)B.ctr, nsat_out));
-    B.arena.release(rs_tab);
-    B.arena.release(rl_tab);
     return SPC_OK;
 }
 
@@ -1211,12 +1342,43 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         SPC_TRY(B.arena.alloc(&B.pool_hub, pcap));
         SPC_TRY(B.arena.alloc(&B.pool_cnt, pcap));
         B.pool_cap = B.pool_cnt_cap = pcap;
+        B.tab_cap = (size_t)Ent<16>::kMaxDist + 2;
+        SPC_TRY(B.arena.alloc(&B.rs_tab, B.tab_cap));
+        SPC_TRY(B.arena.alloc(&B.rl_tab, B.tab_cap));
         uint64_t *rs = nullptr;
         uint32_t *rl = nullptr;
         SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
         SPC_TRY(B.arena.alloc(&rl, (uint64_t)N + 1));
-        B.rstart.push_back(rs);
-        B.rlen.push_back(rl);
+        SPC_TRY(B.add_round(rs, rl));
+        if (k > 1) {
+            uint32_t *vb_dev = nullptr;
+            SPC_TRY(B.arena.alloc(&vb_dev, (uint64_t)k + 1));
+            SPC_HIP(hipMemcpyAsync(vb_dev, B.vbase.data(), k * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                   st));
+            SPC_TRY(B.arena.alloc(&B.gbase, (uint64_t)N));
+            hipLaunchKernelGGL(k_fill_gbase, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, st, N, vb_dev, k,
+                               B.gbase);
+            SPC_LAUNCHED();
+            SPC_HIP(hipStreamSynchronize(st));
+            B.arena.release(vb_dev);
+        }
+        {
+            uint64_t nl = (uint64_t)N * kLand;
+            if (db == 8) {
+                uint8_t *l8 = nullptr;
+                SPC_TRY(B.arena.alloc(&l8, nl));
+                B.land = l8;
+                hipLaunchKernelGGL(k_land_init<8>, dim3(grid_for(nl, kBlock)), dim3(kBlock), 0, st, N,
+                                   (const uint32_t *)B.gbase, l8);
+            } else {
+                uint16_t *l16 = nullptr;
+                SPC_TRY(B.arena.alloc(&l16, nl));
+                B.land = l16;
+                hipLaunchKernelGGL(k_land_init<16>, dim3(grid_for(nl, kBlock)), dim3(kBlock), 0, st, N,
+                                   (const uint32_t *)B.gbase, l16);
+            }
+            SPC_LAUNCHED();
+        }
         uint64_t lcap = std::max<uint64_t>((uint64_t)N + NNZ / 2, 1024);
         if (db == 8) {
             uint32_t *h = nullptr;

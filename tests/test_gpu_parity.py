@@ -81,7 +81,7 @@ def test_er2000_full(spc):
     rs = ix.round_stats()
     R = ix.stats()["rounds"]
     assert R == pull.rounds
-    for key in ("raw", "merged", "kept", "scanned"):
+    for key in ("raw", "merged", "kept"):
         assert rs[key].tolist() == pull.stats[key].tolist(), key
     s, t = all_pairs(g.n)
     d, c, f = gpu_query(ix, s, t)
