@@ -120,6 +120,7 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         st = ix.stats()
+        st["_rounds"] = {k: v.tolist() for k, v in {**ix.round_stats(), **ix.round_profile()}.items()}
         ix.free()
         return dict(build_ms=(t1 - t0) * 1e3, query_ms=ev0.elapsed_time(ev1),
                     step_ms=(t2 - t0) * 1e3, stats=st)
@@ -139,6 +140,11 @@ def main():
     total_ms = (time.perf_counter() - tt0) * 1e3
 
     st = runs[-1]["stats"]
+    rs = st["_rounds"]
+    for r in range(len(rs["kept"])):
+        log("round %d: raw %d merged %d kept %d tail %d staged %d rowB %d hdr %d  %.1f ms" % (
+            r, rs["raw"][r], rs["merged"][r], rs["kept"][r], rs["scanned"][r], rs["staged"][r],
+            rs["row_bytes"][r], rs["headers"][r], rs["kernel_ms"][r]))
     entries = st["entries"]
     build_ms = float(np.mean([r["build_ms"] for r in runs]))
     query_ms = float(np.mean([r["query_ms"] for r in runs]))

@@ -234,6 +234,19 @@ __device__ __forceinline__ bool land_hit(uint64_t x, uint64_t y, uint32_t d) {
     return h;
 }
 
+__device__ __forceinline__ uint32_t land_count_le(uint32_t x, uint32_t lim) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) c += ((x >> (8 * i)) & 0xFFu) <= lim;
+    return c;
+}
+__device__ __forceinline__ uint32_t land_count_le(uint64_t x, uint32_t lim) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) c += (uint32_t)((x >> (16 * i)) & 0xFFFFu) <= lim;
+    return c;
+}
+
 template <int DB>
 __global__ void k_land_init(uint32_t N, const uint32_t *gbase, typename Land<DB>::T *land) {
     using LT = typename Land<DB>::T;
@@ -282,8 +295,10 @@ struct RoundArgs {
     uint32_t d, u_lo, u_hi;
     const uint64_t *goff;
     const uint32_t *gadj;
-    const uint64_t *lab_off;
+    const uint64_t *lab_off;         // L_{<=d-1}: staged for u
     const void *lab_hd;
+    const uint64_t *prev_off;        // L_{<=d-2}: probed for candidates w
+    const void *prev_hd;
     const void *land;                // landmark rows [N][kLand]
     const uint32_t *gbase;           // first rank of each vertex's graph, or null
     const uint64_t *const *rs_tab;   // round segments: start / length per vertex
@@ -330,13 +345,16 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     using LT = typename Land<DB>::T;
     using LW = typename Land<DB>::W;
     __shared__ E ltab[kLCap];
+    __shared__ E sarr[kLStage];  // u's entries of distance <= d-2 past the landmarks, by hub
     __shared__ LW lrow[kLand / 4];
     __shared__ uint32_t ckey[kCCap];
     __shared__ unsigned long long cval[kCCap];
     __shared__ uint8_t cwrap[kCCap];
     __shared__ uint32_t lhub[kULimit];
     __shared__ unsigned long long lcnt[kULimit];
-    __shared__ uint8_t lkeep[kULimit];
+    __shared__ uint8_t lkeep[kULimit];   // 0 pruned, 1 kept, 2 needs the tail check
+    __shared__ uint16_t lpre[kULimit];   // landmark entries of L_{<=d-2}(w)
+    __shared__ uint16_t tlist[kULimit];  // candidates that need the tail check
     __shared__ uint64_t nb_start[kBlock];
     __shared__ uint32_t nb_off[kBlock];
     __shared__ uint32_t red32[kWaves];
@@ -378,6 +396,20 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
         while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
     }
+    // u's entries of distance <= d-2 past the landmarks, hub-sorted (from
+    // the previous round's merged label), for probes that stream u's side
+    const E *pu = nullptr;
+    uint64_t npu = 0;
+    uint32_t nstu = 0;
+    if (d >= 3) {
+        const uint64_t q0 = a.prev_off[u];
+        const uint64_t qn = a.prev_off[u + 1] - q0;
+        const uint64_t qs = lower_bound_hub<DB>(static_cast<const E *>(a.prev_hd) + q0, qn, land_end);
+        pu = static_cast<const E *>(a.prev_hd) + q0 + qs;
+        npu = qn - qs;
+        nstu = npu < (uint64_t)kLStage ? (uint32_t)npu : (uint32_t)kLStage;
+        for (uint32_t i = tid; i < nstu; i += kBlock) sarr[i] = pu[i];
+    }
     LabelLookup<DB> look;
     look.tab = ltab;
     look.tail = hd + l0 + s0 + nst;
@@ -396,6 +428,10 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     uint32_t nout = 0;
     uint64_t st_raw = 0, st_merged = 0, st_kept = 0;
     uint32_t lo = 0, width = u;
+    if (raw_u > 2 * (uint64_t)kULimit) {  // first guess: about 2 pulls per distinct hub
+        uint64_t parts = (raw_u + 2 * kULimit - 1) / (2 * kULimit);
+        width = (uint32_t)(u / parts) > 0 ? (uint32_t)(u / parts) : 1;
+    }
 
     // 2-5, chunk by chunk over the hub range [0, u)
     while (lo < u) {
@@ -520,51 +556,133 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
             }
         }
 
-        // 4. prune probes, one wave per candidate
+        // 4. prune probes (nothing can prune before round 3: a common hub
+        //    with d_u + d_w < 2 would be u or w itself).
+        //  4a. landmark pass, 16 lanes per candidate (4 candidates per wave):
+        //      lane gl compares landmarks [16 gl, 16 gl + 16) of the two rows
+        //      and counts w's landmark entries of distance <= d-2 (the length
+        //      of the landmark prefix of L_{<=d-2}(w)).
+        const uint32_t grp = lane >> 4, gl = lane & 15;
         uint64_t my_tail = 0, my_hdr = 0, my_rowb = 0;
-        for (uint32_t i = wv; i < M; i += kWaves) {
-            const uint32_t w = lhub[i];
-            const uint32_t wl = w - base;  // w's rank within its graph
-            bool pruned = false;
-            if (d >= 2) {
-                // landmark part: hubs below land_end (and <= w)
+        if (d >= 3) {
+            LW uw[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) uw[q] = lrow[4 * gl + q];
+            for (uint32_t i0 = wv * 4; i0 < M; i0 += kBlock / 16) {
+                const uint32_t i = i0 + grp;
                 bool hit = false;
-                if (4 * lane <= wl) {
-                    LW roww = lands[(uint64_t)w * (kLand / 4) + lane];
-                    hit = land_hit(rowu, roww, d);
-                }
-                pruned = __ballot(hit) != 0;
-                my_rowb += (wl < (uint32_t)kLand ? wl + 1 : (uint32_t)kLand) * sizeof(LT);
-                // other hubs of w: entries of rounds 1..d-2 past the landmarks
-                if (!pruned && wl >= (uint32_t)kLand) {
-                    for (uint32_t r = 1; r + 2 <= d && !pruned; r++) {
-                        const uint64_t ps = a.rs_tab[r][w];
-                        const uint32_t ln = a.rl_tab[r][w];
-                        my_hdr++;
-                        if (ln == 0) continue;
-                        const uint32_t *ph = a.pool_hub + ps;
-                        const uint32_t p0 = lower_bound_u32(ph, ln, land_end);
-                        for (uint32_t j0 = p0; j0 < ln; j0 += 64) {
-                            const uint32_t j = j0 + lane;
-                            bool h2 = false;
-                            if (j < ln) {
-                                uint32_t du = look(ph[j]);
-                                h2 = du != kNone && du + r < d;
-                            }
-                            uint64_t m = __ballot(h2);
-                            if (m) {
-                                pruned = true;
-                                my_tail += (j0 - p0) + (uint64_t)__ffsll((long long)m);
-                                break;
-                            }
-                            my_tail += (ln - j0 < 64) ? (ln - j0) : 64;
+                uint32_t cnt = 0, wl = 0;
+                if (i < M) {
+                    wl = lhub[i] - base;
+                    if (16 * gl <= wl) {  // landmarks above w cannot be its hubs
+                        const LW *rw = lands + (uint64_t)lhub[i] * (kLand / 4) + 4 * gl;
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            LW x = rw[q];
+                            hit |= land_hit(uw[q], x, d);
+                            cnt += land_count_le(x, d - 2);
                         }
                     }
                 }
+                const uint64_t m = __ballot(hit);
+                const bool ghit = ((m >> (16 * grp)) & 0xFFFFull) != 0;
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 16);
+                if (i < M && gl == 0) {
+                    lkeep[i] = ghit ? 0 : (wl >= (uint32_t)kLand ? 2 : 1);
+                    lpre[i] = (uint16_t)cnt;
+                    my_rowb += (wl < (uint32_t)kLand ? wl + 1 : (uint32_t)kLand) * sizeof(LT);
+                }
             }
-            if (lane == 0) lkeep[i] = pruned ? 0 : 1;
+        } else {
+            for (uint32_t i = tid; i < M; i += kBlock) lkeep[i] = 1;
         }
-        if (lane == 0) {
+        __syncthreads();
+        //  4b. the other hubs of the surviving non-landmark candidates: their
+        //      entries of distance <= d-2 past the landmarks on both sides
+        //      (L_{<=d-2} is the previous round's merged label).  Either stream
+        //      w's entries and look each hub up in u's table, or stream u's
+        //      entries with hub < w (a common hub ranks at or above w) and
+        //      binary-search each in w's sorted label, whichever reads fewer
+        //      entries.  16 lanes per candidate.
+        uint32_t T = 0;
+        if (d >= 3) {
+            uint32_t f0 = (2 * tid < M && lkeep[2 * tid] == 2) ? 1 : 0;
+            uint32_t f1 = (2 * tid + 1 < M && lkeep[2 * tid + 1] == 2) ? 1 : 0;
+            uint32_t p = block_excl_scan<uint32_t>(f0 + f1, red32, T);
+            if (f0) tlist[p++] = (uint16_t)(2 * tid);
+            if (f1) tlist[p] = (uint16_t)(2 * tid + 1);
+            __syncthreads();
+        }
+        for (uint32_t t0 = wv * 4; t0 < T; t0 += kBlock / 16) {
+            const uint32_t ti = t0 + grp;
+            const bool gvalid = ti < T;
+            uint32_t i = 0, w = 0;
+            uint64_t q0 = 0, np = 0, p0 = 0;
+            if (gvalid) {
+                i = tlist[ti];
+                w = lhub[i];
+                q0 = a.prev_off[w];
+                np = a.prev_off[w + 1] - q0 - 1;  // the last entry is (w, 0)
+                p0 = lpre[i];
+            }
+            const E *pw = static_cast<const E *>(a.prev_hd) + q0;
+            const uint64_t nw = np - p0;
+            uint64_t cu = 0;
+            if (gvalid) {
+                if (nstu == npu || (nstu > 0 && e_hub<DB>(sarr[nstu - 1]) >= w))
+                    cu = lower_bound_hub<DB>(sarr, nstu, w);
+                else
+                    cu = nstu + lower_bound_hub<DB>(pu + nstu, npu - nstu, w);
+            }
+            uint32_t steps = 1;
+            while ((1ull << steps) <= nw) steps++;
+            const bool useu = cu * steps < nw;
+            const uint64_t len = useu ? cu : nw;
+            const uint32_t nit = (uint32_t)((len + 15) / 16);
+            uint32_t maxit = nit;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) maxit = max(maxit, (uint32_t)__shfl_xor(maxit, o, 64));
+            bool done = !gvalid, found = false;
+            uint64_t read = 0;
+            for (uint32_t it = 0; it < maxit; it++) {
+                bool h2 = false;
+                const bool act = !done && it < nit;
+                const uint64_t j = (uint64_t)it * 16 + gl;
+                if (act && j < len) {
+                    if (useu) {
+                        const E e = (j < nstu) ? sarr[j] : pu[j];
+                        const uint32_t h = e_hub<DB>(e);
+                        const uint64_t q = p0 + lower_bound_hub<DB>(pw + p0, nw, h);
+                        h2 = q < np && e_hub<DB>(pw[q]) == h && e_dist<DB>(e) + e_dist<DB>(pw[q]) < d;
+                    } else {
+                        const E e = pw[p0 + j];
+                        const uint32_t du = look(e_hub<DB>(e));
+                        h2 = du != kNone && du + e_dist<DB>(e) < d;
+                    }
+                }
+                const uint64_t m = __ballot(h2);
+                const uint32_t gm = (uint32_t)((m >> (16 * grp)) & 0xFFFFull);
+                if (act) {
+                    if (gm) {
+                        found = true;
+                        done = true;
+                        read += useu ? (uint64_t)(__ffs(gm)) * steps : (uint64_t)__ffs(gm);
+                    } else {
+                        uint64_t k = len - (uint64_t)it * 16;
+                        read += (k < 16 ? k : 16) * (useu ? steps : 1);
+                        if (it + 1 >= nit) done = true;
+                    }
+                }
+                if (__ballot(!done) == 0) break;
+            }
+            if (gvalid && gl == 0) {
+                lkeep[i] = found ? 0 : 1;
+                my_tail += read;
+                my_hdr++;
+            }
+        }
+        if (gl == 0) {
             atomicAdd(&s_tail, (unsigned long long)my_tail);
             atomicAdd(&s_hdr, (unsigned long long)my_hdr);
             atomicAdd(&s_rowb, (unsigned long long)my_rowb);
@@ -747,7 +865,7 @@ struct Build {
     // labels
     uint64_t *lab_off = nullptr, *lab_off2 = nullptr;
     void *lab_hd = nullptr, *lab_hd2 = nullptr;
-    uint64_t lab_cap = 0, lab_cap2 = 0, entries = 0;
+    uint64_t lab_cap = 0, lab_cap2 = 0, entries = 0, entries_prev = 0;
     int db = 8;
     // round pool
     uint32_t *pool_hub = nullptr;
@@ -1044,6 +1162,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     SPC_HIP(hipMemsetAsync(B.ctr, 0, 8 * sizeof(unsigned long long), B.st));
 
     uint64_t kept = 0;
+    double round_ms = 0;
     for (size_t bi = 0; bi + 1 < bounds.size(); bi++) {
         uint32_t b0 = bounds[bi], b1 = bounds[bi + 1];
         uint64_t r2[2];
@@ -1071,6 +1190,8 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.gadj = B.gadj;
         ra.lab_off = B.lab_off;
         ra.lab_hd = B.lab_hd;
+        ra.prev_off = B.lab_off2;
+        ra.prev_hd = B.lab_hd2;
         ra.land = B.land;
         ra.gbase = B.gbase;
         ra.rs_tab = B.rs_tab;
@@ -1092,6 +1213,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         float ms = 0;
         SPC_HIP(hipEventElapsedTime(&ms, B.ev_a, B.ev_b));
         B.ms_round_kernel += ms;
+        round_ms += ms;
         SPC_TRY(B.grow(&B.pool_hub, &B.pool_cap, B.pool_used + sb, B.pool_used));
         SPC_TRY(B.grow(&B.pool_cnt, &B.pool_cnt_cap, B.pool_used + sb, B.pool_used));
         hipLaunchKernelGGL(k_compact<DB>, dim3(grid_for(b1 - b0, kWaves)), dim3(kBlock), 0, B.st, b0,
@@ -1109,14 +1231,18 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     rc.merged = c[1];
     rc.kept = c[2];
     rc.scanned = c[3];
+    rc.staged = c[4];
+    rc.row_bytes = c[5];
+    rc.headers = c[6];
+    rc.kernel_ms = round_ms;
     B.stats.push_back(rc);
     // algorithmic bytes of the fused kernel: the pulled entries (hub +
     // count), u's staged label entries past the landmarks, the candidates'
     // landmark rows (hubs <= w), the other probe entries read up to the first
-    // one proving a shorter path (hub) and their round segment headers
-    // (start + length), and the survivors written (hub + count)
+    // one proving a shorter path and their label offsets, and the survivors
+    // written (hub + count)
     uint64_t es = sizeof(E);
-    B.alg_bytes += c[0] * 12 + c[4] * es + c[5] + c[3] * 4 + c[6] * 12 + c[2] * 12;
+    B.alg_bytes += c[0] * 12 + c[4] * es + c[5] + c[3] * es + c[6] * 16 + c[2] * 12;
     *kept_out = kept;
     if (kept == 0) return SPC_OK;
 
@@ -1138,6 +1264,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     std::swap(B.lab_off, B.lab_off2);
     std::swap(B.lab_hd, B.lab_hd2);
     std::swap(B.lab_cap, B.lab_cap2);
+    B.entries_prev = B.entries;
     B.entries = new_entries;
     return SPC_OK;
 }
@@ -1192,21 +1319,27 @@ spc_status rounds_loop(Build &B, uint32_t &d, uint32_t cap, bool auto_width, boo
     }
 }
 
-spc_status widen_labels(Build &B) {
+spc_status widen_buffer(Build &B, void **buf, uint64_t *cap, uint64_t n) {
     uint64_t *w = nullptr;
-    uint64_t cap = std::max<uint64_t>(B.entries, 1);
-    SPC_TRY(B.arena.alloc(&w, cap));
-    hipLaunchKernelGGL(k_widen, dim3(grid_for(B.entries, kBlock)), dim3(kBlock), 0, B.st,
-                       static_cast<const uint32_t *>(B.lab_hd), w, B.entries);
-    SPC_LAUNCHED();
+    uint64_t c = std::max<uint64_t>(n, 1);
+    SPC_TRY(B.arena.alloc(&w, c));
+    if (n) {
+        hipLaunchKernelGGL(k_widen, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st,
+                           static_cast<const uint32_t *>(*buf), w, n);
+        SPC_LAUNCHED();
+    }
     SPC_HIP(hipStreamSynchronize(B.st));
-    uint32_t *old = static_cast<uint32_t *>(B.lab_hd), *old2 = static_cast<uint32_t *>(B.lab_hd2);
+    uint32_t *old = static_cast<uint32_t *>(*buf);
     B.arena.release(old);
-    B.arena.release(old2);
-    B.lab_hd = w;
-    B.lab_hd2 = nullptr;
-    B.lab_cap = cap;
-    B.lab_cap2 = 0;
+    *buf = w;
+    *cap = c;
+    return SPC_OK;
+}
+
+// 8-bit -> 16-bit distances: both label buffers and the landmark rows
+spc_status widen_labels(Build &B) {
+    SPC_TRY(widen_buffer(B, &B.lab_hd, &B.lab_cap, B.entries));
+    SPC_TRY(widen_buffer(B, &B.lab_hd2, &B.lab_cap2, B.entries_prev));
     uint64_t nl = (uint64_t)B.N * kLand;
     uint16_t *l16 = nullptr;
     SPC_TRY(B.arena.alloc(&l16, nl));

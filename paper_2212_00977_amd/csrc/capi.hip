@@ -86,6 +86,20 @@ spc_status spc_round_stats(const spc_index *ix, uint32_t max_rounds, uint64_t *r
     return SPC_OK;
 }
 
+spc_status spc_round_profile(const spc_index *ix, uint32_t max_rounds, double *kernel_ms,
+                             uint64_t *staged, uint64_t *row_bytes, uint64_t *headers) {
+    if (!ix) return SPC_ERR_INVALID_ARG;
+    for (uint32_t r = 0; r < max_rounds; r++) {
+        spc::RoundCounters c;
+        if (r < ix->round_stats.size()) c = ix->round_stats[r];
+        if (kernel_ms) kernel_ms[r] = c.kernel_ms;
+        if (staged) staged[r] = c.staged;
+        if (row_bytes) row_bytes[r] = c.row_bytes;
+        if (headers) headers[r] = c.headers;
+    }
+    return SPC_OK;
+}
+
 spc_status spc_graph_entries(const spc_index *ix, uint32_t graph_id, uint32_t *n_out,
                              uint64_t *entries_out) {
     if (!ix || graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;

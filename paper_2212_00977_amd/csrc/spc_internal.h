@@ -224,6 +224,8 @@ spc_status radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 // ---------------------------------------------------------------------------
 struct RoundCounters {
     uint64_t raw = 0, merged = 0, kept = 0, scanned = 0;
+    uint64_t staged = 0, row_bytes = 0, headers = 0;
+    double kernel_ms = 0;  // fused round kernel time of this round
 };
 
 }  // namespace spc

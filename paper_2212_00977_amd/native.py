@@ -20,7 +20,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_free",
-           "spc_index_stats", "spc_round_stats", "spc_graph_entries", "spc_export_labels",
+           "spc_index_stats", "spc_round_stats", "spc_round_profile", "spc_graph_entries", "spc_export_labels",
            "spc_status_string"]
 
 
@@ -87,6 +87,8 @@ def load(path: str | None = None):
     L.spc_index_stats.restype = C.c_int
     L.spc_round_stats.argtypes = [vp, u32, vp, vp, vp, vp]
     L.spc_round_stats.restype = C.c_int
+    L.spc_round_profile.argtypes = [vp, u32, vp, vp, vp, vp]
+    L.spc_round_profile.restype = C.c_int
     L.spc_graph_entries.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(u64)]
     L.spc_graph_entries.restype = C.c_int
     L.spc_export_labels.argtypes = [vp, u32, vp, vp, vp, vp, vp, i32, vp]

@@ -139,6 +139,17 @@ class Index:
                "spc_round_stats")
         return arrs
 
+    def round_profile(self) -> dict:
+        R = self.stats()["rounds"] + 1
+        ms = np.zeros(R, dtype=np.float64)
+        arrs = {k: np.zeros(R, dtype=np.uint64) for k in ("staged", "row_bytes", "headers")}
+        _check(native.load().spc_round_profile(self.handle, R, ms.ctypes.data,
+                                               arrs["staged"].ctypes.data,
+                                               arrs["row_bytes"].ctypes.data,
+                                               arrs["headers"].ctypes.data), "spc_round_profile")
+        arrs["kernel_ms"] = ms
+        return arrs
+
     def graph_entries(self, graph_id: int = 0):
         n = C.c_uint32()
         e = C.c_uint64()
