@@ -299,6 +299,8 @@ struct RoundArgs {
     const void *lab_hd;
     const uint64_t *prev_off;        // L_{<=d-2}: probed for candidates w
     const void *prev_hd;
+    const uint32_t *lc_cur;          // landmark entries of L_{<=d-1}(v) / L_{<=d-2}(v)
+    const uint32_t *lc_prev;
     const void *land;                // landmark rows [N][kLand]
     const uint32_t *gbase;           // first rank of each vertex's graph, or null
     const uint64_t *const *rs_tab;   // round segments: start / length per vertex
@@ -353,7 +355,6 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     __shared__ uint32_t lhub[kULimit];
     __shared__ unsigned long long lcnt[kULimit];
     __shared__ uint8_t lkeep[kULimit];   // 0 pruned, 1 kept, 2 needs the tail check
-    __shared__ uint16_t lpre[kULimit];   // landmark entries of L_{<=d-2}(w)
     __shared__ uint16_t tlist[kULimit];  // candidates that need the tail check
     __shared__ uint64_t nb_start[kBlock];
     __shared__ uint32_t nb_off[kBlock];
@@ -363,6 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
 
     const E *hd = static_cast<const E *>(a.lab_hd);
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t grp = lane >> 4, gl = lane & 15;  // 16-lane groups
     const uint32_t u = a.u_hi - 1 - blockIdx.x;
     const uint64_t raw_u = a.raw_off[u + 1] - a.raw_off[u];
     if (raw_u == 0) {
@@ -376,12 +378,12 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     const uint32_t land_end = base + kLand;  // hubs below this are landmarks
     const LW *lands = static_cast<const LW *>(a.land);
 
-    // 1. stage u's landmark row and the rest of L_{<d}(u)
-    const LW rowu = lands[(uint64_t)u * (kLand / 4) + lane];
-    if (wv == 0) lrow[lane] = rowu;
+    // 1. stage u's landmark row and the rest of L_{<d}(u); the landmark
+    //    entries of a hub-sorted label are its first lc entries
+    if (wv == 0) lrow[lane] = lands[(uint64_t)u * (kLand / 4) + lane];
     const uint64_t l0 = a.lab_off[u];
     const uint64_t nL = a.lab_off[u + 1] - l0;
-    const uint64_t s0 = lower_bound_hub<DB>(hd + l0, nL, land_end);
+    const uint64_t s0 = a.lc_cur[u];
     const uint64_t nsp = nL - s0;
     const uint32_t nst = nsp < (uint64_t)kLStage ? (uint32_t)nsp : (uint32_t)kLStage;
     for (int i = tid; i < kLCap; i += kBlock) ltab[i] = kEmptyE;
@@ -403,10 +405,9 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     uint32_t nstu = 0;
     if (d >= 3) {
         const uint64_t q0 = a.prev_off[u];
-        const uint64_t qn = a.prev_off[u + 1] - q0;
-        const uint64_t qs = lower_bound_hub<DB>(static_cast<const E *>(a.prev_hd) + q0, qn, land_end);
+        const uint64_t qs = a.lc_prev[u];
         pu = static_cast<const E *>(a.prev_hd) + q0 + qs;
-        npu = qn - qs;
+        npu = a.prev_off[u + 1] - q0 - qs;
         nstu = npu < (uint64_t)kLStage ? (uint32_t)npu : (uint32_t)kLStage;
         for (uint32_t i = tid; i < nstu; i += kBlock) sarr[i] = pu[i];
     }
@@ -421,6 +422,15 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     auto held = [&](uint32_t w) -> bool {
         return (w < land_end) ? lrow_t[w - base] != kInfL : look(w) != kNone;
     };
+    // this lane's 16 landmarks of u, and whether any of them is within d-2
+    // (a landmark farther from u cannot prove d_u + d_w < d since d_w >= 1)
+    LW uw[4];
+    bool slice_useful = false;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        uw[q] = lrow[4 * gl + q];
+        slice_useful |= d >= 3 && land_count_le(uw[q], d - 2) > 0;
+    }
 
     const uint64_t g0 = a.goff[u];
     const uint32_t deg = (uint32_t)(a.goff[u + 1] - g0);
@@ -447,6 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         }
         __syncthreads();
         uint64_t chunk_raw = 0;
+        bool shrink = false;
         for (uint32_t nb0 = 0; nb0 < deg; nb0 += kBlock) {
             uint32_t nb = nb0 + tid;
             uint64_t sb = 0;
@@ -465,19 +476,31 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
             }
             uint32_t tot;
             uint32_t ex = block_excl_scan<uint32_t>(len, red32, tot);
+            // all pulls of the chunk are counted before any insert: a chunk
+            // that certainly overflows is narrowed right away
+            if (deg <= (uint32_t)kBlock && tot > 4u * kULimit && hi - lo > 1) {
+                shrink = true;
+                width = (uint32_t)(((uint64_t)(hi - lo) * (2 * kULimit)) / tot);
+                if (width == 0) width = 1;
+                break;
+            }
             nb_start[tid] = sb;
             nb_off[tid] = ex;
             __syncthreads();
             chunk_raw += tot;
+            uint32_t jl = 0;  // owner of k: last j with nb_off[j] <= k (monotone in k)
             for (uint32_t k = tid; k < tot; k += kBlock) {
                 if (*(volatile uint32_t *)&s_ovf) break;
-                uint32_t jl = 0, jh = kBlock - 1;  // owner: last j with nb_off[j] <= k
-                while (jl < jh) {
-                    uint32_t mid = (jl + jh + 1) >> 1;
-                    if (nb_off[mid] <= k)
-                        jl = mid;
-                    else
-                        jh = mid - 1;
+                if (jl + 1 < (uint32_t)kBlock && nb_off[jl + 1] <= k) {
+                    uint32_t lo2 = jl + 1, hi2 = kBlock - 1;
+                    while (lo2 < hi2) {
+                        uint32_t mid = (lo2 + hi2 + 1) >> 1;
+                        if (nb_off[mid] <= k)
+                            lo2 = mid;
+                        else
+                            hi2 = mid - 1;
+                    }
+                    jl = lo2;
                 }
                 uint64_t idx = nb_start[jl] + (k - nb_off[jl]);
                 uint32_t w = a.pool_hub[idx];
@@ -510,13 +533,18 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
             }
             __syncthreads();
         }
+        if (shrink) {
+            __syncthreads();
+            continue;
+        }
         if (s_ovf) {  // too many distinct hubs: retry a narrower range
             width = (hi - lo) > 1 ? (hi - lo) >> 1 : 1;
             __syncthreads();
             continue;
         }
 
-        // compact the table into a list
+        // compact the table into a list (any order: survivors are ranked by
+        // hub at the end)
         uint32_t nv = 0;
         for (int j = 0; j < kCCap / kBlock; j++) nv += ckey[tid * (kCCap / kBlock) + j] != kEmpty32;
         uint32_t M;
@@ -530,68 +558,35 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
                 ex++;
             }
         }
-        uint32_t P = 1;
-        while (P < M) P <<= 1;
-        for (uint32_t i = M + tid; i < P; i += kBlock) lhub[i] = kEmpty32;
         __syncthreads();
-
-        // 3. bitonic sort by hub
-        for (uint32_t kk = 2; kk <= P; kk <<= 1) {
-            for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = tid; i < P; i += kBlock) {
-                    uint32_t ixj = i ^ j;
-                    if (ixj > i) {
-                        bool asc = (i & kk) == 0;
-                        uint32_t x = lhub[i], y = lhub[ixj];
-                        if ((x > y) == asc) {
-                            lhub[i] = y;
-                            lhub[ixj] = x;
-                            unsigned long long t = lcnt[i];
-                            lcnt[i] = lcnt[ixj];
-                            lcnt[ixj] = t;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
 
         // 4. prune probes (nothing can prune before round 3: a common hub
         //    with d_u + d_w < 2 would be u or w itself).
         //  4a. landmark pass, 16 lanes per candidate (4 candidates per wave):
-        //      lane gl compares landmarks [16 gl, 16 gl + 16) of the two rows
-        //      and counts w's landmark entries of distance <= d-2 (the length
-        //      of the landmark prefix of L_{<=d-2}(w)).
-        const uint32_t grp = lane >> 4, gl = lane & 15;
+        //      lane gl compares landmarks [16 gl, 16 gl + 16) of the two rows,
+        //      reading w's slice only if u has a landmark within d-2 there.
         uint64_t my_tail = 0, my_hdr = 0, my_rowb = 0;
         if (d >= 3) {
-            LW uw[4];
-#pragma unroll
-            for (int q = 0; q < 4; q++) uw[q] = lrow[4 * gl + q];
             for (uint32_t i0 = wv * 4; i0 < M; i0 += kBlock / 16) {
                 const uint32_t i = i0 + grp;
                 bool hit = false;
-                uint32_t cnt = 0, wl = 0;
+                uint32_t wl = 0, loads = 0;
                 if (i < M) {
                     wl = lhub[i] - base;
-                    if (16 * gl <= wl) {  // landmarks above w cannot be its hubs
+                    if (slice_useful && 16 * gl <= wl) {  // landmarks above w are not its hubs
                         const LW *rw = lands + (uint64_t)lhub[i] * (kLand / 4) + 4 * gl;
 #pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            LW x = rw[q];
-                            hit |= land_hit(uw[q], x, d);
-                            cnt += land_count_le(x, d - 2);
-                        }
+                        for (int q = 0; q < 4; q++) hit |= land_hit(uw[q], rw[q], d);
+                        loads = 1;
                     }
                 }
                 const uint64_t m = __ballot(hit);
                 const bool ghit = ((m >> (16 * grp)) & 0xFFFFull) != 0;
 #pragma unroll
-                for (int o = 8; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 16);
+                for (int o = 8; o > 0; o >>= 1) loads += __shfl_xor(loads, o, 16);
                 if (i < M && gl == 0) {
                     lkeep[i] = ghit ? 0 : (wl >= (uint32_t)kLand ? 2 : 1);
-                    lpre[i] = (uint16_t)cnt;
-                    my_rowb += (wl < (uint32_t)kLand ? wl + 1 : (uint32_t)kLand) * sizeof(LT);
+                    my_rowb += (uint64_t)loads * 16 * sizeof(LT);
                 }
             }
         } else {
@@ -624,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
                 w = lhub[i];
                 q0 = a.prev_off[w];
                 np = a.prev_off[w + 1] - q0 - 1;  // the last entry is (w, 0)
-                p0 = lpre[i];
+                p0 = a.lc_prev[w];
             }
             const E *pw = static_cast<const E *>(a.prev_hd) + q0;
             const uint64_t nw = np - p0;
@@ -689,21 +684,31 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         }
         __syncthreads();
 
-        // 5. survivors in hub order
+        // 5. survivors: compact, then each goes to its rank by hub
         uint32_t i0 = tid * 2;
         uint32_t k0 = (i0 < M) ? lkeep[i0] : 0;
         uint32_t k1 = (i0 + 1 < M) ? lkeep[i0 + 1] : 0;
+        uint32_t h0 = k0 ? lhub[i0] : 0, h1 = k1 ? lhub[i0 + 1] : 0;
+        unsigned long long c0 = k0 ? lcnt[i0] : 0, c1 = k1 ? lcnt[i0 + 1] : 0;
         uint32_t S;
         uint32_t pos = block_excl_scan<uint32_t>(k0 + k1, red32, S);
-        uint64_t obase = tbase + nout;
         if (k0) {
-            a.tmp_hub[obase + pos] = lhub[i0];
-            a.tmp_cnt[obase + pos] = lcnt[i0];
+            lhub[pos] = h0;
+            lcnt[pos] = c0;
             pos++;
         }
         if (k1) {
-            a.tmp_hub[obase + pos] = lhub[i0 + 1];
-            a.tmp_cnt[obase + pos] = lcnt[i0 + 1];
+            lhub[pos] = h1;
+            lcnt[pos] = c1;
+        }
+        __syncthreads();
+        const uint64_t obase = tbase + nout;
+        for (uint32_t k = tid; k < S; k += kBlock) {
+            const uint32_t h = lhub[k];
+            uint32_t r = 0;
+            for (uint32_t j = 0; j < S; j++) r += lhub[j] < h;
+            a.tmp_hub[obase + r] = h;
+            a.tmp_cnt[obase + r] = lcnt[k];
         }
         nout += S;
         st_raw += chunk_raw;
@@ -768,13 +773,15 @@ __global__ void k_new_len(uint32_t N, const uint64_t *lab_off, const uint32_t *r
 
 // L_{<=d}(u) = merge of L_{<d}(u) and round d (disjoint hubs, both sorted).
 // Each element's output position is its own index plus the number of smaller
-// hubs in the other list.  One wave per vertex.
+// hubs in the other list.  Also the number of landmark entries of the merged
+// label (its landmark prefix).  One wave per vertex.
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_merge(uint32_t N, uint32_t d, const uint64_t *lab_off,
                                                   const typename Ent<DB>::T *lab_hd,
                                                   const uint64_t *rstart, const uint32_t *rlen,
                                                   const uint32_t *pool_hub, const uint64_t *new_off,
-                                                  typename Ent<DB>::T *new_hd) {
+                                                  typename Ent<DB>::T *new_hd, const uint32_t *gbase,
+                                                  const uint32_t *lc_in, uint32_t *lc_out) {
     using E = typename Ent<DB>::T;
     uint32_t u = blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (u >= N) return;
@@ -784,6 +791,10 @@ __global__ __launch_bounds__(kBlock) void k_merge(uint32_t N, uint32_t d, const 
     const E *A = lab_hd + a0;
     const uint32_t *B = pool_hub + rstart[u];
     E *out = new_hd + new_off[u];
+    if (lane == 0) {
+        uint32_t land_end = (gbase ? gbase[u] : 0) + kLand;
+        lc_out[u] = lc_in[u] + (nb ? lower_bound_u32(B, nb, land_end) : 0);
+    }
     if (nb == 0) {
         for (uint64_t i = lane; i < na; i += 64) out[i] = A[i];
         return;
@@ -796,6 +807,11 @@ __global__ __launch_bounds__(kBlock) void k_merge(uint32_t N, uint32_t d, const 
         uint32_t h = B[j];
         out[j + lower_bound_hub<DB>(A, na, h)] = e_make<DB>(h, d);
     }
+}
+
+__global__ void k_lc_init(uint32_t N, const uint32_t *gbase, uint32_t *lc) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < N) lc[v] = (v - (gbase ? gbase[v] : 0)) < (uint32_t)kLand ? 1u : 0u;
 }
 
 // Widen packed entries from 8-bit to 16-bit distances.
@@ -878,6 +894,7 @@ struct Build {
     size_t tab_cap = 0;
     void *land = nullptr;         // landmark rows [N][kLand]
     uint32_t *gbase = nullptr;    // per-rank graph base (batches only)
+    uint32_t *lc = nullptr, *lc2 = nullptr;  // landmark prefix lengths of the two label buffers
     // per-round scratch
     uint64_t *raw = nullptr, *raw_off = nullptr, *soff = nullptr, *nlen = nullptr;
     uint32_t *surv = nullptr;
@@ -1192,6 +1209,8 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.lab_hd = B.lab_hd;
         ra.prev_off = B.lab_off2;
         ra.prev_hd = B.lab_hd2;
+        ra.lc_cur = B.lc;
+        ra.lc_prev = B.lc2;
         ra.land = B.land;
         ra.gbase = B.gbase;
         ra.rs_tab = B.rs_tab;
@@ -1259,10 +1278,12 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     }
     hipLaunchKernelGGL(k_merge<DB>, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, d, B.lab_off,
                        static_cast<const E *>(B.lab_hd), rs, rl, B.pool_hub, B.lab_off2,
-                       static_cast<E *>(B.lab_hd2));
+                       static_cast<E *>(B.lab_hd2), (const uint32_t *)B.gbase,
+                       (const uint32_t *)B.lc, B.lc2);
     SPC_LAUNCHED();
     std::swap(B.lab_off, B.lab_off2);
     std::swap(B.lab_hd, B.lab_hd2);
+    std::swap(B.lc, B.lc2);
     std::swap(B.lab_cap, B.lab_cap2);
     B.entries_prev = B.entries;
     B.entries = new_entries;
@@ -1512,6 +1533,11 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
             }
             SPC_LAUNCHED();
         }
+        SPC_TRY(B.arena.alloc(&B.lc, (uint64_t)N + 1));
+        SPC_TRY(B.arena.alloc(&B.lc2, (uint64_t)N + 1));
+        hipLaunchKernelGGL(k_lc_init, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, st, N,
+                           (const uint32_t *)B.gbase, B.lc);
+        SPC_LAUNCHED();
         uint64_t lcap = std::max<uint64_t>((uint64_t)N + NNZ / 2, 1024);
         if (db == 8) {
             uint32_t *h = nullptr;
