@@ -80,6 +80,9 @@ def main():
                     help="shrink n by 2^k (smoke runs only; not the benchmark workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes three times (for scaling "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -95,6 +98,15 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
+
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": args.copy_calibration, "copies": 3}))
+        return
 
     log("generating graph")
     g = inputs.workload("chunglu", scale_down=args.scale_down)
@@ -121,6 +133,7 @@ def main():
         t2 = time.perf_counter()
         st = ix.stats()
         st["_rounds"] = {k: v.tolist() for k, v in {**ix.round_stats(), **ix.round_profile()}.items()}
+        st["_launches"] = ix.round_kernel_launches()
         ix.free()
         return dict(build_ms=(t1 - t0) * 1e3, query_ms=ev0.elapsed_time(ev1),
                     step_ms=(t2 - t0) * 1e3, stats=st)
@@ -151,7 +164,7 @@ def main():
     rk_ms = float(np.mean([r["stats"]["ms_round_kernel"] for r in runs]))
     alg = st["alg_bytes_round_kernel"]
     achieved = alg / (rk_ms * 1e-3) / 1e9 if rk_ms > 0 else 0.0
-    launches = None
+    launches = st["_launches"]
     traffic = measured_traffic(launches)
     out = {
         "metric": METRIC,
@@ -179,7 +192,9 @@ def main():
                                "round_kernel": rk_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_round", "alg_bytes_per_build": alg},
+                     "kernel": "k_round", "launches_per_build": launches,
+                     "avg_launch_ms": rk_ms / max(launches, 1),
+                     "alg_bytes_per_launch": alg / max(launches, 1)},
         "index_bytes": st["index_bytes"],
         "peak_build_bytes": st["peak_build_bytes"],
     }

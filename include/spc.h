@@ -106,6 +106,7 @@ typedef struct {
     double ms_total;          /* whole build on the device */
     double ms_round_kernel;   /* time inside the fused round kernel only */
     uint64_t alg_bytes_round_kernel; /* algorithmic bytes of the fused round kernel */
+    uint64_t round_kernel_launches;  /* dispatches of the fused round kernel */
 } spc_stats;
 
 /* Build the index of one graph (Alg. 2 rounds until a round adds no entry).

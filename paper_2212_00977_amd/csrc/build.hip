@@ -283,13 +283,25 @@ __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
 //      u's table.  A hub with d_u(h) + d_w(h) < d prunes; equality keeps;
 //   5. append the survivors, in hub order, to u's slot of the temp buffer.
 // ---------------------------------------------------------------------------
-constexpr int kLBits = 12;
+// LDS budget of the round kernel (about 39 KB with the defaults: four
+// workgroups per CU); measured faster than staging u's L_{<=d-2} part too
+#ifndef SPC_LBITS
+#define SPC_LBITS 12
+#endif
+#ifndef SPC_STAGE_PREV
+#define SPC_STAGE_PREV 0
+#endif
+constexpr int kLBits = SPC_LBITS;
 constexpr int kLCap = 1 << kLBits;   // L(u) hash slots
 constexpr int kLStage = kLCap / 2;   // staged entries (load <= 1/2)
 constexpr int kCBits = 10;
 constexpr int kCCap = 1 << kCBits;   // candidate hash slots
 constexpr int kULimit = kCCap / 2;   // distinct candidates per chunk
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+#ifndef SPC_ROUND_BLOCK
+#define SPC_ROUND_BLOCK 256
+#endif
+constexpr int kRoundBlock = SPC_ROUND_BLOCK;  // threads per puller workgroup
 
 struct RoundArgs {
     uint32_t d, u_lo, u_hi;
@@ -341,13 +353,15 @@ struct LabelLookup {
     }
 };
 
-template <int DB>
-__global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
+template <int DB, int RB>
+__global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
+    constexpr int RW = RB / 64;          // waves per workgroup
+    constexpr int PER = kULimit / RB;    // candidate slots per thread
     using E = typename Ent<DB>::T;
     using LT = typename Land<DB>::T;
     using LW = typename Land<DB>::W;
     __shared__ E ltab[kLCap];
-    __shared__ E sarr[kLStage];  // u's entries of distance <= d-2 past the landmarks, by hub
+    __shared__ E sarr[SPC_STAGE_PREV ? kLStage : 1];  // u's entries of distance <= d-2 past the landmarks, by hub
     __shared__ LW lrow[kLand / 4];
     __shared__ uint32_t ckey[kCCap];
     __shared__ unsigned long long cval[kCCap];
@@ -356,9 +370,9 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     __shared__ unsigned long long lcnt[kULimit];
     __shared__ uint8_t lkeep[kULimit];   // 0 pruned, 1 kept, 2 needs the tail check
     __shared__ uint16_t tlist[kULimit];  // candidates that need the tail check
-    __shared__ uint64_t nb_start[kBlock];
-    __shared__ uint32_t nb_off[kBlock];
-    __shared__ uint32_t red32[kWaves];
+    __shared__ uint64_t nb_start[RB];
+    __shared__ uint32_t nb_off[RB];
+    __shared__ uint32_t red32[RW];
     __shared__ uint32_t s_nuniq, s_ovf;
     __shared__ unsigned long long s_tail, s_hdr, s_rowb;
 
@@ -386,14 +400,14 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     const uint64_t s0 = a.lc_cur[u];
     const uint64_t nsp = nL - s0;
     const uint32_t nst = nsp < (uint64_t)kLStage ? (uint32_t)nsp : (uint32_t)kLStage;
-    for (int i = tid; i < kLCap; i += kBlock) ltab[i] = kEmptyE;
+    for (int i = tid; i < kLCap; i += RB) ltab[i] = kEmptyE;
     if (tid == 0) {
         s_tail = 0;
         s_hdr = 0;
         s_rowb = 0;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < nst; i += kBlock) {
+    for (uint32_t i = tid; i < nst; i += RB) {
         E e = hd[l0 + s0 + i];
         uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
         while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
@@ -408,8 +422,8 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         const uint64_t qs = a.lc_prev[u];
         pu = static_cast<const E *>(a.prev_hd) + q0 + qs;
         npu = a.prev_off[u + 1] - q0 - qs;
-        nstu = npu < (uint64_t)kLStage ? (uint32_t)npu : (uint32_t)kLStage;
-        for (uint32_t i = tid; i < nstu; i += kBlock) sarr[i] = pu[i];
+        nstu = SPC_STAGE_PREV ? (npu < (uint64_t)kLStage ? (uint32_t)npu : (uint32_t)kLStage) : 0;
+        for (uint32_t i = tid; i < nstu; i += RB) sarr[i] = pu[i];
     }
     LabelLookup<DB> look;
     look.tab = ltab;
@@ -446,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     // 2-5, chunk by chunk over the hub range [0, u)
     while (lo < u) {
         const uint32_t hi = (width >= u - lo) ? u : lo + width;
-        for (int i = tid; i < kCCap; i += kBlock) {
+        for (int i = tid; i < kCCap; i += RB) {
             ckey[i] = kEmpty32;
             cval[i] = 0;
             cwrap[i] = 0;
@@ -458,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         __syncthreads();
         uint64_t chunk_raw = 0;
         bool shrink = false;
-        for (uint32_t nb0 = 0; nb0 < deg; nb0 += kBlock) {
+        for (uint32_t nb0 = 0; nb0 < deg; nb0 += RB) {
             uint32_t nb = nb0 + tid;
             uint64_t sb = 0;
             uint32_t len = 0;
@@ -475,10 +489,10 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
                 }
             }
             uint32_t tot;
-            uint32_t ex = block_excl_scan<uint32_t>(len, red32, tot);
+            uint32_t ex = block_excl_scan<uint32_t, RW>(len, red32, tot);
             // all pulls of the chunk are counted before any insert: a chunk
             // that certainly overflows is narrowed right away
-            if (deg <= (uint32_t)kBlock && tot > 4u * kULimit && hi - lo > 1) {
+            if (deg <= (uint32_t)RB && tot > 4u * kULimit && hi - lo > 1) {
                 shrink = true;
                 width = (uint32_t)(((uint64_t)(hi - lo) * (2 * kULimit)) / tot);
                 if (width == 0) width = 1;
@@ -489,10 +503,10 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
             __syncthreads();
             chunk_raw += tot;
             uint32_t jl = 0;  // owner of k: last j with nb_off[j] <= k (monotone in k)
-            for (uint32_t k = tid; k < tot; k += kBlock) {
+            for (uint32_t k = tid; k < tot; k += RB) {
                 if (*(volatile uint32_t *)&s_ovf) break;
-                if (jl + 1 < (uint32_t)kBlock && nb_off[jl + 1] <= k) {
-                    uint32_t lo2 = jl + 1, hi2 = kBlock - 1;
+                if (jl + 1 < (uint32_t)RB && nb_off[jl + 1] <= k) {
+                    uint32_t lo2 = jl + 1, hi2 = RB - 1;
                     while (lo2 < hi2) {
                         uint32_t mid = (lo2 + hi2 + 1) >> 1;
                         if (nb_off[mid] <= k)
@@ -546,11 +560,11 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         // compact the table into a list (any order: survivors are ranked by
         // hub at the end)
         uint32_t nv = 0;
-        for (int j = 0; j < kCCap / kBlock; j++) nv += ckey[tid * (kCCap / kBlock) + j] != kEmpty32;
+        for (int j = 0; j < kCCap / RB; j++) nv += ckey[tid * (kCCap / RB) + j] != kEmpty32;
         uint32_t M;
-        uint32_t ex = block_excl_scan<uint32_t>(nv, red32, M);
-        for (int j = 0; j < kCCap / kBlock; j++) {
-            uint32_t s = tid * (kCCap / kBlock) + j;
+        uint32_t ex = block_excl_scan<uint32_t, RW>(nv, red32, M);
+        for (int j = 0; j < kCCap / RB; j++) {
+            uint32_t s = tid * (kCCap / RB) + j;
             uint32_t kk = ckey[s];
             if (kk != kEmpty32) {
                 lhub[ex] = kk;
@@ -567,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         //      reading w's slice only if u has a landmark within d-2 there.
         uint64_t my_tail = 0, my_hdr = 0, my_rowb = 0;
         if (d >= 3) {
-            for (uint32_t i0 = wv * 4; i0 < M; i0 += kBlock / 16) {
+            for (uint32_t i0 = wv * 4; i0 < M; i0 += RB / 16) {
                 const uint32_t i = i0 + grp;
                 bool hit = false;
                 uint32_t wl = 0, loads = 0;
@@ -590,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
                 }
             }
         } else {
-            for (uint32_t i = tid; i < M; i += kBlock) lkeep[i] = 1;
+            for (uint32_t i = tid; i < M; i += RB) lkeep[i] = 1;
         }
         __syncthreads();
         //  4b. the other hubs of the surviving non-landmark candidates: their
@@ -602,14 +616,20 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         //      entries.  16 lanes per candidate.
         uint32_t T = 0;
         if (d >= 3) {
-            uint32_t f0 = (2 * tid < M && lkeep[2 * tid] == 2) ? 1 : 0;
-            uint32_t f1 = (2 * tid + 1 < M && lkeep[2 * tid + 1] == 2) ? 1 : 0;
-            uint32_t p = block_excl_scan<uint32_t>(f0 + f1, red32, T);
-            if (f0) tlist[p++] = (uint16_t)(2 * tid);
-            if (f1) tlist[p] = (uint16_t)(2 * tid + 1);
+            uint32_t f[PER], nf = 0;
+#pragma unroll
+            for (int q = 0; q < PER; q++) {
+                uint32_t i = PER * tid + q;
+                f[q] = (i < M && lkeep[i] == 2) ? 1 : 0;
+                nf += f[q];
+            }
+            uint32_t p = block_excl_scan<uint32_t, RW>(nf, red32, T);
+#pragma unroll
+            for (int q = 0; q < PER; q++)
+                if (f[q]) tlist[p++] = (uint16_t)(PER * tid + q);
             __syncthreads();
         }
-        for (uint32_t t0 = wv * 4; t0 < T; t0 += kBlock / 16) {
+        for (uint32_t t0 = wv * 4; t0 < T; t0 += RB / 16) {
             const uint32_t ti = t0 + grp;
             const bool gvalid = ti < T;
             uint32_t i = 0, w = 0;
@@ -685,25 +705,28 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         __syncthreads();
 
         // 5. survivors: compact, then each goes to its rank by hub
-        uint32_t i0 = tid * 2;
-        uint32_t k0 = (i0 < M) ? lkeep[i0] : 0;
-        uint32_t k1 = (i0 + 1 < M) ? lkeep[i0 + 1] : 0;
-        uint32_t h0 = k0 ? lhub[i0] : 0, h1 = k1 ? lhub[i0 + 1] : 0;
-        unsigned long long c0 = k0 ? lcnt[i0] : 0, c1 = k1 ? lcnt[i0 + 1] : 0;
+        uint32_t kk[PER], hh[PER], nk = 0;
+        unsigned long long cc[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            uint32_t i = PER * tid + q;
+            kk[q] = (i < M) ? lkeep[i] : 0;
+            hh[q] = kk[q] ? lhub[i] : 0;
+            cc[q] = kk[q] ? lcnt[i] : 0;
+            nk += kk[q];
+        }
         uint32_t S;
-        uint32_t pos = block_excl_scan<uint32_t>(k0 + k1, red32, S);
-        if (k0) {
-            lhub[pos] = h0;
-            lcnt[pos] = c0;
-            pos++;
-        }
-        if (k1) {
-            lhub[pos] = h1;
-            lcnt[pos] = c1;
-        }
+        uint32_t pos = block_excl_scan<uint32_t, RW>(nk, red32, S);
+#pragma unroll
+        for (int q = 0; q < PER; q++)
+            if (kk[q]) {
+                lhub[pos] = hh[q];
+                lcnt[pos] = cc[q];
+                pos++;
+            }
         __syncthreads();
         const uint64_t obase = tbase + nout;
-        for (uint32_t k = tid; k < S; k += kBlock) {
+        for (uint32_t k = tid; k < S; k += RB) {
             const uint32_t h = lhub[k];
             uint32_t r = 0;
             for (uint32_t j = 0; j < S; j++) r += lhub[j] < h;
@@ -907,6 +930,7 @@ struct Build {
     std::vector<RoundCounters> stats;
     double ms_round_kernel = 0;
     uint64_t alg_bytes = 0;
+    uint64_t launches = 0;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
     Build(uint64_t budget, hipStream_t s) : arena(budget), st(s) {}
@@ -1223,8 +1247,9 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.surv = B.surv;
         ra.ctr = B.ctr;
         SPC_HIP(hipEventRecord(B.ev_a, B.st));
-        hipLaunchKernelGGL(k_round<DB>, dim3(b1 - b0), dim3(kBlock), 0, B.st, ra);
+        k_round<DB, kRoundBlock><<<dim3(b1 - b0), dim3(kRoundBlock), 0, B.st>>>(ra);
         SPC_LAUNCHED();
+        B.launches++;
         SPC_HIP(hipEventRecord(B.ev_b, B.st));
         SPC_TRY(scan_u32(B.surv + b0, B.soff, b1 - b0, B.ws, B.st));
         uint64_t sb;
@@ -1612,6 +1637,7 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     ix->ms_total = elapsed(ev[0], ev[3]);
     ix->ms_round_kernel = B.ms_round_kernel;
     ix->alg_bytes_round_kernel = B.alg_bytes;
+    ix->round_kernel_launches = B.launches;
     ix->lab_off = B.lab_off;
     ix->lab_hd = B.lab_hd;
     ix->lab_cnt = lab_cnt;

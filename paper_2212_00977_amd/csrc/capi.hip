@@ -69,6 +69,7 @@ spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
     out->ms_total = ix->ms_total;
     out->ms_round_kernel = ix->ms_round_kernel;
     out->alg_bytes_round_kernel = ix->alg_bytes_round_kernel;
+    out->round_kernel_launches = ix->round_kernel_launches;
     return SPC_OK;
 }
 

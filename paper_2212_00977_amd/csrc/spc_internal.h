@@ -63,9 +63,9 @@ __device__ __forceinline__ T wave_sum(T v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-// exclusive scan over the kBlock threads of a block; `total` gets the block
-// sum.  lds must hold kWaves values; every thread of the block must call it.
-template <typename T>
+// exclusive scan over the threads of a block of NW waves; `total` gets the
+// block sum.  lds must hold NW values; every thread of the block must call it.
+template <typename T, int NW = kWaves>
 __device__ __forceinline__ T block_excl_scan(T v, T *lds, T &total) {
     T inc = wave_incl_scan(v);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -73,7 +73,7 @@ __device__ __forceinline__ T block_excl_scan(T v, T *lds, T &total) {
     __syncthreads();
     T pre = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kWaves; i++) {
+    for (int i = 0; i < NW; i++) {
         T x = lds[i];
         pre += (i < w) ? x : (T)0;
         tot += x;
@@ -250,6 +250,7 @@ struct spc_index {
     uint64_t index_bytes = 0, peak_build_bytes = 0;
     double ms_order = 0, ms_rounds = 0, ms_finalize = 0, ms_total = 0, ms_round_kernel = 0;
     uint64_t alg_bytes_round_kernel = 0;
+    uint64_t round_kernel_launches = 0;
 };
 
 namespace spc {

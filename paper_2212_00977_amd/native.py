@@ -46,7 +46,8 @@ class SpcStats(C.Structure):
                 ("saturated_entries", C.c_uint64), ("index_bytes", C.c_uint64),
                 ("peak_build_bytes", C.c_uint64), ("ms_order", C.c_double),
                 ("ms_rounds", C.c_double), ("ms_finalize", C.c_double), ("ms_total", C.c_double),
-                ("ms_round_kernel", C.c_double), ("alg_bytes_round_kernel", C.c_uint64)]
+                ("ms_round_kernel", C.c_double), ("alg_bytes_round_kernel", C.c_uint64),
+                ("round_kernel_launches", C.c_uint64)]
 
 
 class SpcGraph(C.Structure):

@@ -139,6 +139,9 @@ class Index:
                "spc_round_stats")
         return arrs
 
+    def round_kernel_launches(self) -> int:
+        return int(self.stats()["round_kernel_launches"])
+
     def round_profile(self) -> dict:
         R = self.stats()["rounds"] + 1
         ms = np.zeros(R, dtype=np.float64)
