@@ -70,6 +70,40 @@ def cpu_baseline(g, seconds: float):
                       f"({e} entries, {dt:.1f} s) of the same graph"}
 
 
+def serve_runs(ix, n, args, sat_qps, log):
+    import numpy as np
+
+    """Open-loop served load on the resident index: Poisson request arrivals,
+    batch sizes log-uniform in [1, 65536], offered at a fraction of the
+    measured batch query rate; continuous batching vs one-at-a-time FIFO."""
+    from paper_2212_00977_amd import inputs, serve
+
+    mean_batch = 65536 / np.log(65537) - 0.5  # E[floor(exp(U[0, ln 65537)))]
+    levels = [0.25, 0.5, 0.75, 1.0, 1.25] if args.serve_sweep else [0.5]
+    res = []
+    for lv in levels:
+        rate = lv * sat_qps / mean_batch
+        count = min(2000, max(20, int(rate * max(args.serve_seconds, 1.0))))
+        reqs = serve.requests_from(inputs.poisson_requests(n, rate, count, seed=7 + int(100 * lv)))
+        srv = serve.Server(ix, io_budget_bytes=1 << 30, streams=4, max_batch=1 << 18)
+        srv.run(reqs[: min(10, len(reqs))])  # warm the streams and host buffers
+        st = srv.run(reqs).summary()
+        base = serve.fifo_baseline(ix, reqs).summary()
+        entry = {"offered_fraction": lv, "offered_requests_per_s": rate,
+                 "served": st, "fifo": base}
+        log(f"serve {lv:.2f}x: {st['queries_per_s']:.3g} q/s p50 {st['p50_ms']:.2f} ms "
+            f"p99 {st['p99_ms']:.2f} ms | fifo p50 {base['p50_ms']:.2f} p99 {base['p99_ms']:.2f}")
+        if args.serve_sweep:
+            print(json.dumps({"serve_level": entry}), flush=True)
+        res.append(entry)
+    r0 = res[0]
+    return {"offered_fraction": r0["offered_fraction"], "queries_per_s": r0["served"]["queries_per_s"],
+            "p50_ms": r0["served"]["p50_ms"], "p99_ms": r0["served"]["p99_ms"],
+            "fifo_p50_ms": r0["fifo"]["p50_ms"], "fifo_p99_ms": r0["fifo"]["p99_ms"],
+            "requests": r0["served"]["requests"], "deferred": r0["served"]["deferred"],
+            "launches": r0["served"]["launches"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +114,11 @@ def main():
                     help="shrink n by 2^k (smoke runs only; not the benchmark workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="length of the served-load run on the last index (0 = skip)")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="after the steps, sweep the offered load (0.25..1.25 x saturation) "
+                         "and print one JSON line per level")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -122,7 +161,7 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
 
-    def step():
+    def step(keep=False):
         t0 = time.perf_counter()
         ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
         t1 = time.perf_counter()
@@ -134,9 +173,11 @@ def main():
         st = ix.stats()
         st["_rounds"] = {k: v.tolist() for k, v in {**ix.round_stats(), **ix.round_profile()}.items()}
         st["_launches"] = ix.round_kernel_launches()
-        ix.free()
+        if not keep:
+            ix.free()
+            ix = None
         return dict(build_ms=(t1 - t0) * 1e3, query_ms=ev0.elapsed_time(ev1),
-                    step_ms=(t2 - t0) * 1e3, stats=st)
+                    step_ms=(t2 - t0) * 1e3, stats=st, index=ix)
 
     for i in range(args.warmup):
         r = step()
@@ -146,7 +187,7 @@ def main():
     runs = []
     tt0 = time.perf_counter()
     for i in range(args.steps):
-        r = step()
+        r = step(keep=(i == args.steps - 1))
         runs.append(r)
         log(f"step {i}: build {r['build_ms']:.1f} ms, query {r['query_ms']:.1f} ms")
     torch.cuda.synchronize()
@@ -198,6 +239,10 @@ def main():
         "index_bytes": st["index_bytes"],
         "peak_build_bytes": st["peak_build_bytes"],
     }
+    last_ix = runs[-1]["index"]
+    if args.serve_seconds > 0 or args.serve_sweep:
+        out["serve"] = serve_runs(last_ix, g.n, args, out["queries_per_s"], log)
+    last_ix.free()
     if args.scale_down:
         out["note"] = "scaled-down smoke run, not the benchmark workload"
     if not args.no_cpu_baseline:

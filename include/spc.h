@@ -133,8 +133,14 @@ spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_
                            const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
                            uint8_t *flags_out, void *stream);
 
-/* Release the index.  spc_free(NULL) is a no-op. */
+/* Release the index (waits for the device to finish work that may still
+ * read it).  Its device blocks go to the library's per-device block cache,
+ * where later builds reuse them.  spc_free(NULL) is a no-op. */
 void spc_free(spc_index *ix);
+
+/* Return every cached device block to the HIP runtime (all devices).  The
+ * cache is also flushed automatically when an allocation would fail. */
+void spc_release_cached_memory(void);
 
 /* Summary numbers of a finished build (host struct). */
 spc_status spc_index_stats(const spc_index *ix, spc_stats *out);

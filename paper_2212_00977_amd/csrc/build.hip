@@ -933,7 +933,7 @@ struct Build {
     uint64_t launches = 0;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
-    Build(uint64_t budget, hipStream_t s) : arena(budget), st(s) {}
+    Build(uint64_t budget, hipStream_t s) : arena(budget, s), st(s) {}
 
     // record round r's segment arrays (host list + device pointer tables)
     spc_status add_round(uint64_t *rs, uint32_t *rl) {
@@ -1495,9 +1495,12 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         ix->vbase.assign(B.vbase.begin(), B.vbase.end());
         ix->gn = B.gn;
         ix->round_stats.push_back(RoundCounters());
-        ix->index_bytes = B.arena.detach(ix->lab_off) + B.arena.detach(hd) +
-                          B.arena.detach(ix->lab_cnt) + B.arena.detach(ix->rank_of) +
-                          B.arena.detach(ix->order);
+        for (void *blk : {(void *)ix->lab_off, (void *)hd, (void *)ix->lab_cnt, (void *)ix->rank_of,
+                          (void *)ix->order}) {
+            uint64_t b = B.arena.detach(blk);
+            ix->blocks.emplace_back(blk, (size_t)b);
+            ix->index_bytes += b;
+        }
         *out = ix;
         return SPC_OK;
     }
@@ -1643,8 +1646,11 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     ix->lab_cnt = lab_cnt;
     ix->rank_of = B.rank_of;
     ix->order = B.order;
-    ix->index_bytes = B.arena.detach(B.lab_off) + B.arena.detach(B.lab_hd) + B.arena.detach(lab_cnt) +
-                      B.arena.detach(B.rank_of) + B.arena.detach(B.order);
+    for (void *blk : {(void *)B.lab_off, B.lab_hd, (void *)lab_cnt, (void *)B.rank_of, (void *)B.order}) {
+        uint64_t b = B.arena.detach(blk);
+        ix->blocks.emplace_back(blk, (size_t)b);
+        ix->index_bytes += b;
+    }
     *out = ix;
     return SPC_OK;
 }

@@ -41,13 +41,16 @@ spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_
 
 void spc_free(spc_index *ix) {
     if (!ix) return;
-    (void)hipFree(ix->lab_off);
-    (void)hipFree(ix->lab_hd);
-    (void)hipFree(ix->lab_cnt);
-    (void)hipFree(ix->rank_of);
-    (void)hipFree(ix->order);
+    int cur = 0;
+    bool switched = hipGetDevice(&cur) == hipSuccess && cur != ix->device &&
+                    hipSetDevice(ix->device) == hipSuccess;
+    (void)hipDeviceSynchronize();  // queries may still read the index
+    for (auto &b : ix->blocks) spc::cache_free(b.first, b.second);
+    if (switched) (void)hipSetDevice(cur);
     delete ix;
 }
+
+void spc_release_cached_memory(void) { spc::cache_flush(); }
 
 spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
     if (!ix || !out) return SPC_ERR_INVALID_ARG;

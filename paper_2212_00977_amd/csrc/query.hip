@@ -186,7 +186,7 @@ spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, ui
     uint32_t *d_hub = hub, *d_ord = order;
     uint16_t *d_dist = dist;
     uint64_t *d_cnt = count;
-    Arena tmp(0);
+    Arena tmp(0, st);
     if (!on_device) {
         if (off) SPC_TRY(tmp.alloc(&d_off, (uint64_t)n + 1));
         if (hub) SPC_TRY(tmp.alloc(&d_hub, ne));

@@ -145,32 +145,45 @@ __device__ __forceinline__ uint64_t lower_bound_hub(const typename Ent<DB>::T *a
 }
 
 // ---------------------------------------------------------------------------
+// Device block cache (memory.hip): freed blocks are kept per device and
+// reused by later allocations of a similar size, so repeated builds and
+// frees do not pay for large hipMalloc / hipFree calls.
+// ---------------------------------------------------------------------------
+// Returns a block of at least `bytes` bytes (size rounded to 256 B), from the
+// cache when a block of at most twice that size is there, else hipMalloc
+// (after flushing the cache if hipMalloc fails).  nullptr on failure.
+void *cache_alloc(size_t bytes, size_t *got);
+void cache_free(void *p, size_t bytes);
+void cache_flush();
+
+// ---------------------------------------------------------------------------
 // Device memory accounting (per build): every allocation is checked against
-// the caller's budget; whatever is still held when the arena dies is freed
-// unless it was handed over to the index.
+// the caller's budget; whatever is still held when the arena dies goes back
+// to the block cache unless it was handed over to the index.
 // ---------------------------------------------------------------------------
 class Arena {
   public:
-    explicit Arena(uint64_t budget) : budget_(budget) {}
+    // blocks go back to the shared cache only after `st` has drained, so no
+    // pending kernel of this arena's stream can still use them
+    Arena(uint64_t budget, hipStream_t st) : budget_(budget), st_(st) {}
     ~Arena() {
-        for (auto &kv : sizes_) (void)hipFree(kv.first);
+        if (!sizes_.empty()) (void)hipStreamSynchronize(st_);
+        for (auto &kv : sizes_) cache_free(kv.first, kv.second);
     }
     Arena(const Arena &) = delete;
     Arena &operator=(const Arena &) = delete;
 
     template <typename T>
     spc_status alloc(T **p, size_t count) {
-        void *q = nullptr;
         size_t bytes = count * sizeof(T);
         if (bytes == 0) bytes = 256;
         bytes = (bytes + 255) & ~size_t(255);
         if (budget_ && used_ + bytes > budget_) return SPC_ERR_OUT_OF_MEMORY;
-        if (hipMalloc(&q, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            return SPC_ERR_OUT_OF_MEMORY;
-        }
-        sizes_[q] = bytes;
-        used_ += bytes;
+        size_t got = 0;
+        void *q = cache_alloc(bytes, &got);
+        if (!q) return SPC_ERR_OUT_OF_MEMORY;
+        sizes_[q] = got;
+        used_ += got;
         if (used_ > peak_) peak_ = used_;
         *p = static_cast<T *>(q);
         return SPC_OK;
@@ -180,10 +193,11 @@ class Arena {
         if (!p) return;
         auto it = sizes_.find((void *)p);
         if (it != sizes_.end()) {
+            (void)hipStreamSynchronize(st_);
             used_ -= it->second;
+            cache_free(it->first, it->second);
             sizes_.erase(it);
         }
-        (void)hipFree((void *)p);
         p = nullptr;
     }
     // hand an allocation to the index: the arena stops tracking it
@@ -200,6 +214,7 @@ class Arena {
 
   private:
     uint64_t budget_;
+    hipStream_t st_;
     uint64_t used_ = 0, peak_ = 0;
     std::unordered_map<void *, size_t> sizes_;
 };
@@ -244,6 +259,8 @@ struct spc_index {
     uint64_t *lab_cnt = nullptr;  // [entries]
     uint32_t *rank_of = nullptr;  // vertex -> rank (union ids)
     uint32_t *order = nullptr;    // rank -> vertex (union ids)
+    // the index's device blocks and their sizes (returned to the block cache)
+    std::vector<std::pair<void *, size_t>> blocks;
     // graphs of a batch: vertex/rank range [vbase[i], vbase[i] + gn[i])
     std::vector<uint32_t> vbase, gn;
     std::vector<spc::RoundCounters> round_stats;

@@ -245,6 +245,23 @@ def queries(n: int, q: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return s, t
 
 
+def poisson_requests(n_vertices: int, rate_per_s: float, count: int, seed: int,
+                     max_batch: int = 65536, graph_id: int = 0) -> list:
+    """Open-loop Poisson arrivals; batch sizes log-uniform in [1, max_batch];
+    uniform (s, t) pairs.  Returns (id, s, t, arrival_s, graph_id) tuples."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_per_s, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    sizes = np.floor(np.exp(rng.uniform(0.0, np.log(max_batch + 1), size=count))).astype(np.int64)
+    sizes = np.clip(sizes, 1, max_batch)
+    reqs = []
+    for i in range(count):
+        s = rng.integers(0, n_vertices, size=sizes[i], dtype=np.int64).astype(np.uint32)
+        t = rng.integers(0, n_vertices, size=sizes[i], dtype=np.int64).astype(np.uint32)
+        reqs.append((i, s, t, float(arrivals[i]), graph_id))
+    return reqs
+
+
 # --------------------------------------------------------------------------
 # Named workloads
 # --------------------------------------------------------------------------

@@ -15,13 +15,13 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "lib")
 LIBPATH = os.path.join(LIBDIR, "libspc.so")
-SOURCES = ["primitives.hip", "build.hip", "query.hip", "capi.hip"]
+SOURCES = ["memory.hip", "primitives.hip", "build.hip", "query.hip", "capi.hip"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_free",
            "spc_index_stats", "spc_round_stats", "spc_round_profile", "spc_graph_entries", "spc_export_labels",
-           "spc_status_string"]
+           "spc_status_string", "spc_release_cached_memory"]
 
 
 def build_library(verbose: bool = False) -> str:
@@ -84,6 +84,8 @@ def load(path: str | None = None):
     L.spc_query_batch.restype = C.c_int
     L.spc_free.argtypes = [vp]
     L.spc_free.restype = None
+    L.spc_release_cached_memory.argtypes = []
+    L.spc_release_cached_memory.restype = None
     L.spc_index_stats.argtypes = [vp, C.POINTER(SpcStats)]
     L.spc_index_stats.restype = C.c_int
     L.spc_round_stats.argtypes = [vp, u32, vp, vp, vp, vp]
