@@ -104,6 +104,83 @@ def serve_runs(ix, n, args, sat_qps, log):
             "launches": r0["served"]["launches"]}
 
 
+def bench_batch(args, dev, log):
+    """512 independent R-MAT graphs (a,b,c,d = 0.57,0.19,0.19,0.05, edge factor
+    8, scales uniform in 10..16, seed 4): one batched build vs one plain build
+    per graph; then 10,000 queries per graph (uneven label lengths)."""
+    import numpy as np
+    import torch
+
+    from paper_2212_00977_amd import inputs, spc
+
+    log("generating graphs")
+    graphs = inputs.rmat_batch(args.batch_graphs, seed=4)
+    N = sum(g.n for g in graphs)
+    M = sum(g.m for g in graphs)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    # inputs resident in HBM before timing
+    dev_graphs = []
+    for g in graphs:
+        dev_graphs.append(inputs.Graph(g.n, torch.from_numpy(g.off.view(np.int64)).to(dev),
+                                       torch.from_numpy(g.adj.view(np.int32)).to(dev), g.name))
+    qs = [inputs.queries(g.n, 10000, seed=1000 + i) for i, g in enumerate(graphs)]
+    s_d = [torch.from_numpy(s.view(np.int32)).to(dev) for s, _ in qs]
+    t_d = [torch.from_numpy(t.view(np.int32)).to(dev) for _, t in qs]
+    torch.cuda.synchronize()
+
+    def batched():
+        t0 = time.perf_counter()
+        ix = spc.build_index_batch(dev_graphs, device=dev, stream=stream)
+        t1 = time.perf_counter()
+        return ix, (t1 - t0) * 1e3
+
+    def plain():
+        t0 = time.perf_counter()
+        entries = 0
+        for g in dev_graphs:
+            ix = spc.build_index(g.off, g.adj, device=dev, stream=stream)
+            entries += ix.stats()["entries"]
+            ix.free()
+        return entries, (time.perf_counter() - t0) * 1e3
+
+    for _ in range(args.warmup):
+        ix, _ = batched()
+        ix.free()
+    runs = []
+    for i in range(args.steps):
+        ix, ms = batched()
+        runs.append(ms)
+        log(f"batched build {i}: {ms:.1f} ms")
+        if i < args.steps - 1:
+            ix.free()
+    st = ix.stats()
+    entries = st["entries"]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for gi in range(len(graphs)):
+        ix.query(s_d[gi], t_d[gi], graph_id=gi, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    qms = ev0.elapsed_time(ev1)
+    ix.free()
+    pe, pms = plain()
+    log(f"plain per-graph builds: {pms:.1f} ms ({pe} entries)")
+    bms = float(np.mean(runs))
+    out = {"metric": METRIC, "value": entries / (bms * 1e-3), "unit": "label entries/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": bms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+           "data": "synthetic",
+           "config": {"workload": f"{len(graphs)} R-MAT graphs, scales 10..16, ef 8, seed 4, "
+                                  "one batched build + 10,000 queries per graph",
+                      "graphs": len(graphs), "n": N, "m": M, "entries": entries,
+                      "rounds": st["rounds"], "parallelism": "single-gpu"},
+           "batched_build_ms": bms, "plain_build_ms": pms,
+           "plain_entries_per_s": pe / (pms * 1e-3), "batched_speedup": pms / bms,
+           "query_ms": qms, "queries_per_s": 10000 * len(graphs) / (qms * 1e-3)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +196,10 @@ def main():
     ap.add_argument("--serve-sweep", action="store_true",
                     help="after the steps, sweep the offered load (0.25..1.25 x saturation) "
                          "and print one JSON line per level")
+    ap.add_argument("--workload", default="chunglu", choices=["chunglu", "rmat_batch"],
+                    help="chunglu: the benchmark line; rmat_batch: 512 R-MAT graphs built as one "
+                         "batch vs one build per graph (separate JSON line)")
+    ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -146,6 +227,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": args.copy_calibration, "copies": 3}))
         return
+
+    if args.workload == "rmat_batch":
+        return bench_batch(args, dev, log)
 
     log("generating graph")
     g = inputs.workload("chunglu", scale_down=args.scale_down)
