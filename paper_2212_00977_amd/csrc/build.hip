@@ -8,10 +8,10 @@
 //              label sorted by hub; rebuilt each round by merging the round's
 //              entries in (double-buffered), so probes always stream sorted
 //              labels and the final index needs no sort
-//   rounds     pool_hub u32[], pool_cnt u64[]: every round's entries, appended
-//              round after round; round r of vertex v is the hub-sorted
-//              segment pool[rstart[r][v] .. + rlen[r][v])
-//   counts     lab_cnt u64[entries], filled at the end from the round pool
+//   rounds     one allocation per round: rhub[r] u32[], rcnt[r] u64[]; round
+//              r of vertex v is the hub-sorted segment at rstart[r][v],
+//              rlen[r][v] of those arrays
+//   counts     lab_cnt u64[entries], filled at the end from the rounds' counts
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -315,9 +315,9 @@ struct RoundArgs {
     const uint32_t *lc_prev;
     const void *land;                // landmark rows [N][kLand]
     const uint32_t *gbase;           // first rank of each vertex's graph, or null
-    const uint64_t *const *rs_tab;   // round segments: start / length per vertex
-    const uint32_t *const *rl_tab;
-    const uint32_t *pool_hub;
+    const uint64_t *pstart;          // round d-1: segment start / length per vertex
+    const uint32_t *plen;
+    const uint32_t *pool_hub;        // round d-1 entries
     const uint64_t *pool_cnt;
     const uint64_t *raw_off;  // exclusive prefix of raw over all vertices
     uint32_t *tmp_hub;
@@ -478,9 +478,9 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
             uint32_t len = 0;
             if (nb < deg) {
                 uint32_t v = a.gadj[g0 + nb];
-                uint32_t ln = a.rl_tab[d - 1][v];
+                uint32_t ln = a.plen[v];
                 if (v >= lo && ln) {  // hubs of v's segment are <= v
-                    uint64_t ps = a.rs_tab[d - 1][v];
+                    uint64_t ps = a.pstart[v];
                     const uint32_t *ph = a.pool_hub + ps;
                     uint32_t b = lo ? lower_bound_u32(ph, ln, lo) : 0;
                     uint32_t e = lower_bound_u32(ph, ln, hi);
@@ -846,14 +846,15 @@ __global__ void k_widen(const uint32_t *src, uint64_t *dst, uint64_t n) {
     }
 }
 
-// Count of every final entry, from its round's segment in the pool.
+// Count of every final entry by searching its hub in its round's segment
+// (any distance width).
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_finalize(uint32_t N, const uint64_t *lab_off,
                                                      const typename Ent<DB>::T *lab_hd,
                                                      const uint64_t *const *rstart_tab,
                                                      const uint32_t *const *rlen_tab,
-                                                     const uint32_t *pool_hub,
-                                                     const uint64_t *pool_cnt, uint64_t *lab_cnt,
+                                                     const uint32_t *const *hub_tab,
+                                                     const uint64_t *const *cnt_tab, uint64_t *lab_cnt,
                                                      unsigned long long *nsat) {
     uint32_t u = blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (u >= N) return;
@@ -865,10 +866,58 @@ __global__ __launch_bounds__(kBlock) void k_finalize(uint32_t N, const uint64_t 
         uint32_t r = e_dist<DB>(e), h = e_hub<DB>(e);
         uint64_t ps = rstart_tab[r][u];
         uint32_t ln = rlen_tab[r][u];
-        uint32_t p = lower_bound_u32(pool_hub + ps, ln, h);
-        uint64_t c = pool_cnt[ps + p];
+        uint32_t p = lower_bound_u32(hub_tab[r] + ps, ln, h);
+        uint64_t c = cnt_tab[r][ps + p];
         lab_cnt[a0 + i] = c;
         sat += (c == kSat);
+    }
+    sat = wave_sum(sat);
+    if (lane == 0 && sat) atomicAdd(nsat, (unsigned long long)sat);
+}
+
+// Count of every final entry by rank (8-bit distances): a label and each of
+// its round segments are sorted by hub, so the j-th entry of distance r in
+// L(u) is the j-th entry of u's round-r segment.  One wave per vertex walks
+// L(u) in chunks of 64, ranking lanes of equal distance with ballots and
+// keeping a running count per distance in LDS.
+__global__ __launch_bounds__(kBlock) void k_finalize_rank(uint32_t N, uint32_t R,
+                                                          const uint64_t *lab_off,
+                                                          const uint32_t *lab_hd,
+                                                          const uint64_t *const *rstart_tab,
+                                                          const uint64_t *const *cnt_tab,
+                                                          uint64_t *lab_cnt, unsigned long long *nsat) {
+    __shared__ uint32_t seen[kWaves][256];
+    __shared__ uint64_t seg[kWaves][256];
+    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t u = blockIdx.x * kWaves + wv;
+    if (u >= N) return;
+    for (uint32_t r = lane; r < 256; r += 64) {
+        seen[wv][r] = 0;
+        seg[wv][r] = r < R ? rstart_tab[r][u] : 0;
+    }
+    wave_lds_sync();
+    const uint64_t a0 = lab_off[u], na = lab_off[u + 1] - a0;
+    uint32_t sat = 0;
+    for (uint64_t i0 = 0; i0 < na; i0 += 64) {
+        const uint64_t i = i0 + lane;
+        const bool valid = i < na;
+        const uint32_t r = valid ? e_dist<8>(lab_hd[a0 + i]) : 0;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const uint64_t bb = __ballot((r >> b) & 1);
+            peers &= ((r >> b) & 1) ? bb : ~bb;
+        }
+        const uint32_t rank = __popcll(peers & lanemask_lt());
+        const uint32_t base = seen[wv][r];
+        if (valid) {
+            const uint64_t c = cnt_tab[r][seg[wv][r] + base + rank];
+            lab_cnt[a0 + i] = c;
+            sat += (c == kSat);
+        }
+        wave_lds_sync();
+        if (valid && (peers & lanemask_lt()) == 0) seen[wv][r] = base + (uint32_t)__popcll(peers);
+        wave_lds_sync();
     }
     sat = wave_sum(sat);
     if (lane == 0 && sat) atomicAdd(nsat, (unsigned long long)sat);
@@ -906,14 +955,16 @@ struct Build {
     void *lab_hd = nullptr, *lab_hd2 = nullptr;
     uint64_t lab_cap = 0, lab_cap2 = 0, entries = 0, entries_prev = 0;
     int db = 8;
-    // round pool
-    uint32_t *pool_hub = nullptr;
-    uint64_t *pool_cnt = nullptr;
-    uint64_t pool_cap = 0, pool_cnt_cap = 0, pool_used = 0;
+    // rounds: entries (one allocation per round) and per-vertex segments
+    std::vector<uint32_t *> rhub;
+    std::vector<uint64_t *> rcnt;
+    std::vector<uint64_t> rcap, rused;
     std::vector<uint64_t *> rstart;
     std::vector<uint32_t *> rlen;
-    uint64_t **rs_tab = nullptr;  // device copies of rstart / rlen pointers
+    uint64_t **rs_tab = nullptr;  // device copies of the per-round pointers
     uint32_t **rl_tab = nullptr;
+    uint32_t **hub_tab = nullptr;
+    uint64_t **cnt_tab = nullptr;
     size_t tab_cap = 0;
     void *land = nullptr;         // landmark rows [N][kLand]
     uint32_t *gbase = nullptr;    // per-rank graph base (batches only)
@@ -941,15 +992,48 @@ struct Build {
         if (r >= tab_cap) return SPC_ERR_DIST_RANGE;
         rstart.push_back(rs);
         rlen.push_back(rl);
+        rhub.push_back(nullptr);
+        rcnt.push_back(nullptr);
+        rcap.push_back(0);
+        rused.push_back(0);
         SPC_HIP(hipMemcpyAsync(rs_tab + r, &rstart[r], sizeof(uint64_t *), hipMemcpyHostToDevice, st));
         SPC_HIP(hipMemcpyAsync(rl_tab + r, &rlen[r], sizeof(uint32_t *), hipMemcpyHostToDevice, st));
         SPC_HIP(hipStreamSynchronize(st));  // the host vectors may reallocate
         return SPC_OK;
     }
-    ~Build() {
-        if (h_pin) (void)hipHostFree(h_pin);
-        if (ev_a) (void)hipEventDestroy(ev_a);
-        if (ev_b) (void)hipEventDestroy(ev_b);
+    // round r's arrays at exactly their used size
+    spc_status shrink_round(size_t r) {
+        uint64_t n = std::max<uint64_t>(rused[r], 1);
+        uint32_t *h = nullptr;
+        uint64_t *c = nullptr;
+        SPC_TRY(arena.alloc(&h, n));
+        SPC_TRY(arena.alloc(&c, n));
+        if (rused[r]) {
+            SPC_HIP(hipMemcpyAsync(h, rhub[r], rused[r] * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+            SPC_HIP(hipMemcpyAsync(c, rcnt[r], rused[r] * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+        }
+        arena.release(rhub[r]);
+        arena.release(rcnt[r]);
+        rhub[r] = h;
+        rcnt[r] = c;
+        rcap[r] = n;
+        SPC_HIP(hipMemcpyAsync(hub_tab + r, &rhub[r], sizeof(uint32_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipMemcpyAsync(cnt_tab + r, &rcnt[r], sizeof(uint64_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipStreamSynchronize(st));
+        return SPC_OK;
+    }
+    // room for `need` entries in round r's arrays (kept entries are copied)
+    spc_status grow_round(size_t r, uint64_t need) {
+        if (need <= rcap[r]) return SPC_OK;
+        uint64_t nc = need;
+        uint64_t c1 = rcap[r], c2 = rcap[r];
+        SPC_TRY(grow(&rhub[r], &c1, nc, rused[r]));
+        SPC_TRY(grow(&rcnt[r], &c2, nc, rused[r]));
+        rcap[r] = std::min(c1, c2);
+        SPC_HIP(hipMemcpyAsync(hub_tab + r, &rhub[r], sizeof(uint32_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipMemcpyAsync(cnt_tab + r, &rcnt[r], sizeof(uint64_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipStreamSynchronize(st));
+        return SPC_OK;
     }
 
     spc_status read_u64(const uint64_t *dev, uint64_t *out, size_t count = 1) {
@@ -1167,7 +1251,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     const uint32_t *plen = B.rlen[d - 1];
     using LT = typename Land<DB>::T;
     hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, B.goff,
-                       B.gadj, pstart, plen, B.pool_hub, B.raw);
+                       B.gadj, pstart, plen, B.rhub[d - 1], B.raw);
     SPC_LAUNCHED();
     SPC_TRY(scan_u64(B.raw, B.raw_off, N, B.ws, B.st));
     uint64_t total_raw;
@@ -1237,10 +1321,10 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.lc_prev = B.lc2;
         ra.land = B.land;
         ra.gbase = B.gbase;
-        ra.rs_tab = B.rs_tab;
-        ra.rl_tab = B.rl_tab;
-        ra.pool_hub = B.pool_hub;
-        ra.pool_cnt = B.pool_cnt;
+        ra.pstart = pstart;
+        ra.plen = plen;
+        ra.pool_hub = B.rhub[d - 1];
+        ra.pool_cnt = B.rcnt[d - 1];
         ra.raw_off = B.raw_off;
         ra.tmp_hub = B.tmp_hub;
         ra.tmp_cnt = B.tmp_cnt;
@@ -1258,16 +1342,25 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         SPC_HIP(hipEventElapsedTime(&ms, B.ev_a, B.ev_b));
         B.ms_round_kernel += ms;
         round_ms += ms;
-        SPC_TRY(B.grow(&B.pool_hub, &B.pool_cap, B.pool_used + sb, B.pool_used));
-        SPC_TRY(B.grow(&B.pool_cnt, &B.pool_cnt_cap, B.pool_used + sb, B.pool_used));
+        if (B.rcap[d] < B.rused[d] + sb) {
+            // first batch: size the round from its survivor density; later
+            // batches grow by half
+            uint64_t want = B.rused[d] + sb;
+            if (bi == 0 && bounds.size() > 2 && r2[1] > r2[0])
+                want = std::max<uint64_t>(want, (uint64_t)((double)sb * total_raw / (r2[1] - r2[0]) * 1.1));
+            else if (bi > 0)
+                want = std::max<uint64_t>(want, B.rcap[d] + B.rcap[d] / 2);
+            SPC_TRY(B.grow_round(d, want));
+        }
         hipLaunchKernelGGL(k_compact<DB>, dim3(grid_for(b1 - b0, kWaves)), dim3(kBlock), 0, B.st, b0,
-                           b1, d, B.raw_off, B.soff, B.surv, B.tmp_hub, B.tmp_cnt, B.pool_used,
-                           B.pool_hub, B.pool_cnt, rs, rl, (const uint32_t *)B.gbase,
+                           b1, d, B.raw_off, B.soff, B.surv, B.tmp_hub, B.tmp_cnt, B.rused[d],
+                           B.rhub[d], B.rcnt[d], rs, rl, (const uint32_t *)B.gbase,
                            static_cast<LT *>(B.land));
         SPC_LAUNCHED();
-        B.pool_used += sb;
+        B.rused[d] += sb;
         kept += sb;
     }
+    if (B.rcap[d] > B.rused[d] + B.rused[d] / 8 + (1u << 20)) SPC_TRY(B.shrink_round(d));
     uint64_t c[8];
     SPC_TRY(B.read_u64((const uint64_t *)B.ctr, c, 8));
     RoundCounters rc;
@@ -1302,7 +1395,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         B.lab_hd2 = p2;
     }
     hipLaunchKernelGGL(k_merge<DB>, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, d, B.lab_off,
-                       static_cast<const E *>(B.lab_hd), rs, rl, B.pool_hub, B.lab_off2,
+                       static_cast<const E *>(B.lab_hd), rs, rl, B.rhub[d], B.lab_off2,
                        static_cast<E *>(B.lab_hd2), (const uint32_t *)B.gbase,
                        (const uint32_t *)B.lc, B.lc2);
     SPC_LAUNCHED();
@@ -1333,7 +1426,7 @@ spc_status rounds_loop(Build &B, uint32_t &d, uint32_t cap, bool auto_width, boo
             // truncated iff round cap+1 would still pull candidates
             const uint32_t N = B.N;
             hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N,
-                               B.goff, B.gadj, B.rstart[d - 1], B.rlen[d - 1], B.pool_hub, B.raw);
+                               B.goff, B.gadj, B.rstart[d - 1], B.rlen[d - 1], B.rhub[d - 1], B.raw);
             SPC_LAUNCHED();
             SPC_TRY(scan_u64(B.raw, B.raw_off, N, B.ws, B.st));
             uint64_t tr;
@@ -1403,11 +1496,32 @@ spc_status widen_labels(Build &B) {
 template <int DB>
 spc_status finalize_counts(Build &B, uint64_t **lab_cnt, uint64_t *nsat_out) {
     using E = typename Ent<DB>::T;
+    // the older label buffer is not needed any more; with 8-bit distances
+    // neither are the rounds' hub arrays (counts are placed by rank)
+    {
+        E *old = static_cast<E *>(B.lab_hd2);
+        B.arena.release(old);
+        B.lab_hd2 = nullptr;
+        B.lab_cap2 = 0;
+    }
+    const uint32_t R = (uint32_t)B.rstart.size();
+    const bool by_rank = DB == 8 && R <= 256;
+    if (by_rank)
+        for (auto &h : B.rhub) B.arena.release(h);
     SPC_TRY(B.arena.alloc(lab_cnt, std::max<uint64_t>(B.entries, 1)));
     SPC_HIP(hipMemsetAsync(B.ctr, 0, sizeof(unsigned long long), B.st));
-    hipLaunchKernelGGL(k_finalize<DB>, dim3(grid_for(B.N, kWaves)), dim3(kBlock), 0, B.st, B.N,
-                       B.lab_off, static_cast<const E *>(B.lab_hd), (const uint64_t *const *)B.rs_tab,
-                       (const uint32_t *const *)B.rl_tab, B.pool_hub, B.pool_cnt, *lab_cnt, B.ctr);
+    if (by_rank) {
+        hipLaunchKernelGGL(k_finalize_rank, dim3(grid_for(B.N, kWaves)), dim3(kBlock), 0, B.st, B.N, R,
+                           B.lab_off, static_cast<const uint32_t *>(B.lab_hd),
+                           (const uint64_t *const *)B.rs_tab, (const uint64_t *const *)B.cnt_tab,
+                           *lab_cnt, B.ctr);
+    } else {
+        hipLaunchKernelGGL(k_finalize<DB>, dim3(grid_for(B.N, kWaves)), dim3(kBlock), 0, B.st, B.N,
+                           B.lab_off, static_cast<const E *>(B.lab_hd),
+                           (const uint64_t *const *)B.rs_tab, (const uint32_t *const *)B.rl_tab,
+                           (const uint32_t *const *)B.hub_tab, (const uint64_t *const *)B.cnt_tab,
+                           *lab_cnt, B.ctr);
+    }
     SPC_LAUNCHED();
     SPC_TRY(B.read_u64((const uint64_t *)B.ctr, nsat_out));
     return SPC_OK;
@@ -1520,18 +1634,18 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     SPC_TRY(B.arena.alloc(&B.lab_off, (uint64_t)N + 1));
     SPC_TRY(B.arena.alloc(&B.lab_off2, (uint64_t)N + 1));
     {
-        uint64_t pcap = (uint64_t)N + std::max<uint64_t>(NNZ, 1024);
-        SPC_TRY(B.arena.alloc(&B.pool_hub, pcap));
-        SPC_TRY(B.arena.alloc(&B.pool_cnt, pcap));
-        B.pool_cap = B.pool_cnt_cap = pcap;
         B.tab_cap = (size_t)Ent<16>::kMaxDist + 2;
         SPC_TRY(B.arena.alloc(&B.rs_tab, B.tab_cap));
         SPC_TRY(B.arena.alloc(&B.rl_tab, B.tab_cap));
+        SPC_TRY(B.arena.alloc(&B.hub_tab, B.tab_cap));
+        SPC_TRY(B.arena.alloc(&B.cnt_tab, B.tab_cap));
         uint64_t *rs = nullptr;
         uint32_t *rl = nullptr;
         SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
         SPC_TRY(B.arena.alloc(&rl, (uint64_t)N + 1));
         SPC_TRY(B.add_round(rs, rl));
+        SPC_TRY(B.grow_round(0, N));
+        B.rused[0] = N;
         if (k > 1) {
             uint32_t *vb_dev = nullptr;
             SPC_TRY(B.arena.alloc(&vb_dev, (uint64_t)k + 1));
@@ -1572,17 +1686,16 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
             SPC_TRY(B.arena.alloc(&h, lcap));
             B.lab_hd = h;
             hipLaunchKernelGGL(k_round0<8>, dim3(grid_for((uint64_t)N + 1, kBlock)), dim3(kBlock), 0,
-                               st, N, B.pool_hub, B.pool_cnt, rs, rl, B.lab_off, h);
+                               st, N, B.rhub[0], B.rcnt[0], rs, rl, B.lab_off, h);
         } else {
             uint64_t *h = nullptr;
             SPC_TRY(B.arena.alloc(&h, lcap));
             B.lab_hd = h;
             hipLaunchKernelGGL(k_round0<16>, dim3(grid_for((uint64_t)N + 1, kBlock)), dim3(kBlock), 0,
-                               st, N, B.pool_hub, B.pool_cnt, rs, rl, B.lab_off, h);
+                               st, N, B.rhub[0], B.rcnt[0], rs, rl, B.lab_off, h);
         }
         SPC_LAUNCHED();
         B.lab_cap = lcap;
-        B.pool_used = N;
         B.entries = N;
         RoundCounters r0;
         r0.kept = N;

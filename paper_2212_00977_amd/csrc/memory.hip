@@ -37,7 +37,7 @@ void *cache_alloc(size_t bytes, size_t *got) {
         std::lock_guard<std::mutex> lk(g_mu);
         DeviceCache &c = cache_for_current();
         auto it = c.free_blocks.lower_bound(bytes);
-        if (it != c.free_blocks.end() && it->first <= 2 * bytes) {
+        if (it != c.free_blocks.end() && it->first <= bytes + bytes / 2) {
             void *p = it->second;
             *got = it->first;
             c.free_blocks.erase(it);

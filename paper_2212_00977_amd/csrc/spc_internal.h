@@ -83,6 +83,13 @@ __device__ __forceinline__ T block_excl_scan(T v, T *lds, T &total) {
     return pre + inc - v;
 }
 
+// wave-scope ordering of LDS accesses (a wave's lanes exchange through LDS)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Packed label entry: hub in the high bits, distance in the low bits, so the
 // packed value sorts by hub.  8-bit distances use a u32 (hub < 2^24),
 // 16-bit distances a u64.
@@ -150,7 +157,7 @@ __device__ __forceinline__ uint64_t lower_bound_hub(const typename Ent<DB>::T *a
 // frees do not pay for large hipMalloc / hipFree calls.
 // ---------------------------------------------------------------------------
 // Returns a block of at least `bytes` bytes (size rounded to 256 B), from the
-// cache when a block of at most twice that size is there, else hipMalloc
+// cache when a block of at most 1.5 times that size is there, else hipMalloc
 // (after flushing the cache if hipMalloc fails).  nullptr on failure.
 void *cache_alloc(size_t bytes, size_t *got);
 void cache_free(void *p, size_t bytes);
