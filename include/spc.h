@@ -158,10 +158,12 @@ spc_status spc_round_stats(const spc_index *ix, uint32_t max_rounds, uint64_t *r
 
 /* Per-round cost profile of the build, same indexing as spc_round_stats:
  * time inside the fused round kernel (ms), label entries of the pullers
- * staged on chip, landmark-row bytes read by prune probes, and round
- * segment headers read by prune probes.  Host arrays; any may be NULL. */
+ * staged on chip, landmark-row bytes read by prune probes, round segment
+ * headers read by prune probes, and the device bytes the build held at the
+ * round's high-water mark.  Host arrays; any may be NULL. */
 spc_status spc_round_profile(const spc_index *ix, uint32_t max_rounds, double *kernel_ms,
-                             uint64_t *staged, uint64_t *row_bytes, uint64_t *headers);
+                             uint64_t *staged, uint64_t *row_bytes, uint64_t *headers,
+                             uint64_t *mem_peak);
 
 /* Number of label entries of graph `graph_id` (host out). */
 spc_status spc_graph_entries(const spc_index *ix, uint32_t graph_id, uint32_t *n_out,

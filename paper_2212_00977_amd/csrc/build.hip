@@ -15,7 +15,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -939,6 +941,10 @@ inline int bit_width(uint64_t x) {
 // ---------------------------------------------------------------------------
 // Host-side build state
 // ---------------------------------------------------------------------------
+// rounds that may insert at least this many entries grow in place (mapped
+// address ranges); smaller ones are copied when they grow
+constexpr uint64_t kVmmMinEntries = 1ull << 24;
+
 struct Build {
     Arena arena;
     hipStream_t st;
@@ -961,6 +967,9 @@ struct Build {
     std::vector<uint64_t> rcap, rused;
     std::vector<uint64_t *> rstart;
     std::vector<uint32_t *> rlen;
+    bool vmm = false;              // round arrays grow in place (virtual memory API)
+    uint64_t dev_bytes = 0;        // device memory size (bounds reservations)
+    std::vector<std::unique_ptr<VArray>> vhub, vcnt;
     uint64_t **rs_tab = nullptr;  // device copies of the per-round pointers
     uint32_t **rl_tab = nullptr;
     uint32_t **hub_tab = nullptr;
@@ -985,6 +994,9 @@ struct Build {
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 
     Build(uint64_t budget, hipStream_t s) : arena(budget, s), st(s) {}
+    ~Build() {
+        (void)hipStreamSynchronize(st);  // before the round arrays are unmapped
+    }
 
     // record round r's segment arrays (host list + device pointer tables)
     spc_status add_round(uint64_t *rs, uint32_t *rl) {
@@ -994,6 +1006,8 @@ struct Build {
         rlen.push_back(rl);
         rhub.push_back(nullptr);
         rcnt.push_back(nullptr);
+        vhub.emplace_back();
+        vcnt.emplace_back();
         rcap.push_back(0);
         rused.push_back(0);
         SPC_HIP(hipMemcpyAsync(rs_tab + r, &rstart[r], sizeof(uint64_t *), hipMemcpyHostToDevice, st));
@@ -1001,8 +1015,62 @@ struct Build {
         SPC_HIP(hipStreamSynchronize(st));  // the host vectors may reallocate
         return SPC_OK;
     }
+    // address space for round r's arrays, up to `max_entries` (in-place
+    // growth only)
+    spc_status reserve_round(size_t r, uint64_t max_entries) {
+        if (!vmm || max_entries < kVmmMinEntries) return SPC_OK;  // small rounds copy cheaply
+        uint64_t m = std::max<uint64_t>(std::min(max_entries, dev_bytes / sizeof(uint32_t)), 1);
+        std::unique_ptr<VArray> h(new (std::nothrow) VArray()), c(new (std::nothrow) VArray());
+        if (!h || !c) return SPC_ERR_OUT_OF_MEMORY;
+        SPC_TRY(h->reserve(m * sizeof(uint32_t)));
+        SPC_TRY(c->reserve(std::min<uint64_t>(m, dev_bytes / sizeof(uint64_t) + 1) * sizeof(uint64_t)));
+        vhub[r] = std::move(h);
+        vcnt[r] = std::move(c);
+        rhub[r] = static_cast<uint32_t *>(vhub[r]->ptr());
+        rcnt[r] = static_cast<uint64_t *>(vcnt[r]->ptr());
+        rcap[r] = 0;
+        SPC_HIP(hipMemcpyAsync(hub_tab + r, &rhub[r], sizeof(uint32_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipMemcpyAsync(cnt_tab + r, &rcnt[r], sizeof(uint64_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipStreamSynchronize(st));
+        return SPC_OK;
+    }
+    // round r's entries from its mapped ranges into ordinary allocations
+    spc_status demote_round(size_t r) {
+        uint64_t n = std::max<uint64_t>(rused[r], 1);
+        uint32_t *h = nullptr;
+        uint64_t *c = nullptr;
+        SPC_TRY(arena.alloc(&h, n));
+        SPC_TRY(arena.alloc(&c, n));
+        if (rused[r]) {
+            SPC_HIP(hipMemcpyAsync(h, rhub[r], rused[r] * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+            SPC_HIP(hipMemcpyAsync(c, rcnt[r], rused[r] * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+        }
+        SPC_HIP(hipStreamSynchronize(st));
+        arena.uncharge(vhub[r]->mapped() + vcnt[r]->mapped());
+        vhub[r].reset();
+        vcnt[r].reset();
+        rhub[r] = h;
+        rcnt[r] = c;
+        rcap[r] = n;
+        SPC_HIP(hipMemcpyAsync(hub_tab + r, &rhub[r], sizeof(uint32_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipMemcpyAsync(cnt_tab + r, &rcnt[r], sizeof(uint64_t *), hipMemcpyHostToDevice, st));
+        SPC_HIP(hipStreamSynchronize(st));
+        return SPC_OK;
+    }
+    // give back round r's hub array
+    void release_round_hub(size_t r) {
+        if (vhub[r]) {
+            (void)hipStreamSynchronize(st);
+            arena.uncharge(vhub[r]->mapped());
+            vhub[r].reset();
+            rhub[r] = nullptr;
+        } else {
+            arena.release(rhub[r]);
+        }
+    }
     // round r's arrays at exactly their used size
     spc_status shrink_round(size_t r) {
+        if (vhub[r]) return SPC_OK;  // mapped in bounded pieces already
         uint64_t n = std::max<uint64_t>(rused[r], 1);
         uint32_t *h = nullptr;
         uint64_t *c = nullptr;
@@ -1025,6 +1093,25 @@ struct Build {
     // room for `need` entries in round r's arrays (kept entries are copied)
     spc_status grow_round(size_t r, uint64_t need) {
         if (need <= rcap[r]) return SPC_OK;
+        if (vhub[r]) {
+            size_t a = 0, b = 0;
+            spc_status s = vhub[r]->ensure(need * sizeof(uint32_t), &a);
+            SPC_TRY(arena.charge(a));
+            if (s == SPC_OK) {
+                s = vcnt[r]->ensure(need * sizeof(uint64_t), &b);
+                SPC_TRY(arena.charge(b));
+            }
+            if (s == SPC_OK) {
+                rcap[r] = std::min<uint64_t>(vhub[r]->mapped() / sizeof(uint32_t),
+                                             vcnt[r]->mapped() / sizeof(uint64_t));
+                return SPC_OK;
+            }
+            if (s != SPC_ERR_DEVICE) return s;
+            // the runtime refused a mapping: move the round into ordinary
+            // allocations and grow by copying from here on
+            SPC_TRY(demote_round(r));
+            vmm = false;
+        }
         uint64_t nc = need;
         uint64_t c1 = rcap[r], c2 = rcap[r];
         SPC_TRY(grow(&rhub[r], &c1, nc, rused[r]));
@@ -1250,6 +1337,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     const uint64_t *pstart = B.rstart[d - 1];
     const uint32_t *plen = B.rlen[d - 1];
     using LT = typename Land<DB>::T;
+    B.arena.begin_window();
     hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, B.goff,
                        B.gadj, pstart, plen, B.rhub[d - 1], B.raw);
     SPC_LAUNCHED();
@@ -1284,6 +1372,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
     SPC_TRY(B.arena.alloc(&rl, (uint64_t)N + 1));
     SPC_TRY(B.add_round(rs, rl));
+    SPC_TRY(B.reserve_round(d, total_raw));  // survivors are a subset of the pulls
     SPC_HIP(hipMemsetAsync(B.ctr, 0, 8 * sizeof(unsigned long long), B.st));
 
     uint64_t kept = 0;
@@ -1343,13 +1432,17 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         B.ms_round_kernel += ms;
         round_ms += ms;
         if (B.rcap[d] < B.rused[d] + sb) {
-            // first batch: size the round from its survivor density; later
-            // batches grow by half
+            // copied growth: the first batch sizes the round from its
+            // survivor density, later batches grow by half; in-place growth
+            // maps what is needed
             uint64_t want = B.rused[d] + sb;
-            if (bi == 0 && bounds.size() > 2 && r2[1] > r2[0])
-                want = std::max<uint64_t>(want, (uint64_t)((double)sb * total_raw / (r2[1] - r2[0]) * 1.1));
-            else if (bi > 0)
-                want = std::max<uint64_t>(want, B.rcap[d] + B.rcap[d] / 2);
+            if (!B.vhub[d]) {
+                if (bi == 0 && bounds.size() > 2 && r2[1] > r2[0])
+                    want = std::max<uint64_t>(want,
+                                              (uint64_t)((double)sb * total_raw / (r2[1] - r2[0]) * 1.1));
+                else if (bi > 0)
+                    want = std::max<uint64_t>(want, B.rcap[d] + B.rcap[d] / 2);
+            }
             SPC_TRY(B.grow_round(d, want));
         }
         hipLaunchKernelGGL(k_compact<DB>, dim3(grid_for(b1 - b0, kWaves)), dim3(kBlock), 0, B.st, b0,
@@ -1372,6 +1465,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     rc.row_bytes = c[5];
     rc.headers = c[6];
     rc.kernel_ms = round_ms;
+    rc.mem_peak = B.arena.window_peak();
     B.stats.push_back(rc);
     // algorithmic bytes of the fused kernel: the pulled entries (hub +
     // count), u's staged label entries past the landmarks, the candidates'
@@ -1389,10 +1483,15 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     SPC_LAUNCHED();
     SPC_TRY(scan_u64(B.nlen, B.lab_off2, N, B.ws, B.st));
     uint64_t new_entries = B.entries + kept;
-    {
+    if (B.lab_cap2 < new_entries) {
+        // the older buffer (distances <= d-2) is dead once the round kernel
+        // has run: free it first, then take exactly the merged size
         E *p2 = static_cast<E *>(B.lab_hd2);
-        SPC_TRY(B.grow(&p2, &B.lab_cap2, new_entries, 0));
+        B.arena.release(p2);
+        B.lab_cap2 = 0;
+        SPC_TRY(B.arena.alloc(&p2, new_entries));
         B.lab_hd2 = p2;
+        B.lab_cap2 = new_entries;
     }
     hipLaunchKernelGGL(k_merge<DB>, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, d, B.lab_off,
                        static_cast<const E *>(B.lab_hd), rs, rl, B.rhub[d], B.lab_off2,
@@ -1405,6 +1504,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     std::swap(B.lab_cap, B.lab_cap2);
     B.entries_prev = B.entries;
     B.entries = new_entries;
+    B.stats.back().mem_peak = B.arena.window_peak();
     return SPC_OK;
 }
 
@@ -1507,7 +1607,7 @@ spc_status finalize_counts(Build &B, uint64_t **lab_cnt, uint64_t *nsat_out) {
     const uint32_t R = (uint32_t)B.rstart.size();
     const bool by_rank = DB == 8 && R <= 256;
     if (by_rank)
-        for (auto &h : B.rhub) B.arena.release(h);
+        for (size_t r = 0; r < B.rhub.size(); r++) B.release_round_hub(r);
     SPC_TRY(B.arena.alloc(lab_cnt, std::max<uint64_t>(B.entries, 1)));
     SPC_HIP(hipMemsetAsync(B.ctr, 0, sizeof(unsigned long long), B.st));
     if (by_rank) {
@@ -1565,6 +1665,14 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     int dev = 0;
     SPC_HIP(hipGetDevice(&dev));
     Build B(o->mem_budget, st);
+    {
+        size_t fr = 0, tot = 0;
+        SPC_HIP(hipMemGetInfo(&fr, &tot));
+        B.dev_bytes = tot;
+        // SPC_VMM=0 in the environment turns in-place growth off
+        const char *ev = std::getenv("SPC_VMM");
+        B.vmm = vmm_supported() && !(ev && ev[0] == '0');
+    }
     B.N = (uint32_t)N64;
     B.NNZ = NNZ;
     B.k = k;
@@ -1644,6 +1752,7 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
         SPC_TRY(B.arena.alloc(&rl, (uint64_t)N + 1));
         SPC_TRY(B.add_round(rs, rl));
+        SPC_TRY(B.reserve_round(0, N));
         SPC_TRY(B.grow_round(0, N));
         B.rused[0] = N;
         if (k > 1) {

@@ -1,6 +1,8 @@
-// Per-device cache of device memory blocks.
+// Per-device cache of device memory blocks, and growable arrays on the
+// virtual memory API.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -37,7 +39,7 @@ void *cache_alloc(size_t bytes, size_t *got) {
         std::lock_guard<std::mutex> lk(g_mu);
         DeviceCache &c = cache_for_current();
         auto it = c.free_blocks.lower_bound(bytes);
-        if (it != c.free_blocks.end() && it->first <= bytes + bytes / 2) {
+        if (it != c.free_blocks.end() && it->first <= bytes + bytes / 8) {
             void *p = it->second;
             *got = it->first;
             c.free_blocks.erase(it);
@@ -69,6 +71,122 @@ void cache_free(void *p, size_t bytes) {
 void cache_flush() {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &c : g_cache) flush_locked(c);
+}
+
+// ---------------------------------------------------------------------------
+bool vmm_supported() {
+    static std::mutex mu;
+    static std::vector<int> known;  // per device: -1 unknown, 0 no, 1 yes
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((size_t)dev >= known.size()) known.resize((size_t)dev + 1, -1);
+    if (known[(size_t)dev] < 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeVirtualMemoryManagementSupported, dev) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            v = 0;
+        }
+        known[(size_t)dev] = v ? 1 : 0;
+    }
+    return known[(size_t)dev] == 1;
+}
+
+namespace {
+hipMemAllocationProp device_prop(int dev) {
+    hipMemAllocationProp p{};
+    p.type = hipMemAllocationTypePinned;
+    p.location.type = hipMemLocationTypeDevice;
+    p.location.id = dev;
+    return p;
+}
+constexpr size_t kPieceMin = size_t(64) << 20;  // mapping piece bounds
+constexpr size_t kPieceMax = size_t(2) << 30;
+// pieces start and end on 2 MiB boundaries (the large-page size), whatever
+// smaller granularity the runtime reports
+constexpr size_t kPieceAlign = size_t(2) << 20;
+}  // namespace
+
+spc_status VArray::reserve(size_t max_bytes) {
+    reset();
+    if (hipGetDevice(&device_) != hipSuccess) return SPC_ERR_DEVICE;
+    hipMemAllocationProp prop = device_prop(device_);
+    if (hipMemGetAllocationGranularity(&gran_, &prop, hipMemAllocationGranularityRecommended) !=
+            hipSuccess ||
+        gran_ == 0) {
+        (void)hipGetLastError();
+        return SPC_ERR_DEVICE;
+    }
+    gran_ = (std::max(gran_, kPieceAlign) + kPieceAlign - 1) / kPieceAlign * kPieceAlign;
+    size_t bytes = (std::max<size_t>(max_bytes, 1) + gran_ - 1) / gran_ * gran_;
+    void *p = nullptr;
+    if (hipMemAddressReserve(&p, bytes, 0, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return SPC_ERR_OUT_OF_MEMORY;
+    }
+    base_ = p;
+    reserved_ = bytes;
+    mapped_ = 0;
+    return SPC_OK;
+}
+
+spc_status VArray::ensure(size_t bytes, size_t *added) {
+    *added = 0;
+    if (bytes <= mapped_) return SPC_OK;
+    if (!base_ || bytes > reserved_) return SPC_ERR_INVALID_ARG;
+    hipMemAllocationProp prop = device_prop(device_);
+    while (mapped_ < bytes) {
+        // pieces grow with the array (at most an eighth of it, within
+        // bounds), so an array takes few pieces and little slack
+        size_t piece = std::max(bytes - mapped_, std::min(std::max(kPieceMin, mapped_ / 8), kPieceMax));
+        piece = (piece + gran_ - 1) / gran_ * gran_;
+        piece = std::min(piece, reserved_ - mapped_);
+        hipMemGenericAllocationHandle_t h{};
+        if (hipMemCreate(&h, piece, &prop, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            cache_flush();
+            if (hipMemCreate(&h, piece, &prop, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                return SPC_ERR_OUT_OF_MEMORY;
+            }
+        }
+        char *at = static_cast<char *>(base_) + mapped_;
+        if (hipMemMap(at, piece, 0, h, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipMemRelease(h);
+            return SPC_ERR_DEVICE;
+        }
+        // access is granted over the whole mapped prefix: the runtime
+        // rejects some ranges that start past the reservation's base
+        hipMemAccessDesc acc{};
+        acc.location = prop.location;
+        acc.flags = hipMemAccessFlagsProtReadWrite;
+        if (hipMemSetAccess(base_, mapped_ + piece, &acc, 1) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipMemUnmap(at, piece);
+            (void)hipMemRelease(h);
+            return SPC_ERR_DEVICE;
+        }
+        pieces_.emplace_back(h, piece);
+        mapped_ += piece;
+        *added += piece;
+    }
+    return SPC_OK;
+}
+
+void VArray::reset() {
+    if (!base_) return;
+    size_t off = 0;
+    for (auto &pc : pieces_) {
+        (void)hipMemUnmap(static_cast<char *>(base_) + off, pc.second);
+        (void)hipMemRelease(pc.first);
+        off += pc.second;
+    }
+    pieces_.clear();
+    (void)hipMemAddressFree(base_, reserved_);
+    base_ = nullptr;
+    reserved_ = mapped_ = 0;
 }
 
 }  // namespace spc

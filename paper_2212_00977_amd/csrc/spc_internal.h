@@ -163,6 +163,34 @@ void *cache_alloc(size_t bytes, size_t *got);
 void cache_free(void *p, size_t bytes);
 void cache_flush();
 
+// Growable device array on the virtual memory API: an address range is
+// reserved once and physical memory is mapped behind it piece by piece, so
+// growing copies nothing and the address never moves.  The owner makes sure
+// no kernel still uses the range before reset().
+class VArray {
+  public:
+    VArray() = default;
+    ~VArray() { reset(); }
+    VArray(const VArray &) = delete;
+    VArray &operator=(const VArray &) = delete;
+    // reserve `max_bytes` of address space on the current device
+    spc_status reserve(size_t max_bytes);
+    // map physical memory until at least `bytes` are backed; *added = bytes
+    // newly mapped
+    spc_status ensure(size_t bytes, size_t *added);
+    void reset();  // unmap and release everything, free the range
+    void *ptr() const { return base_; }
+    size_t mapped() const { return mapped_; }
+
+  private:
+    void *base_ = nullptr;
+    size_t reserved_ = 0, mapped_ = 0, gran_ = 0;
+    int device_ = 0;
+    std::vector<std::pair<hipMemGenericAllocationHandle_t, size_t>> pieces_;  // handle, bytes
+};
+// whether the current device supports the virtual memory API
+bool vmm_supported();
+
 // ---------------------------------------------------------------------------
 // Device memory accounting (per build): every allocation is checked against
 // the caller's budget; whatever is still held when the arena dies goes back
@@ -191,10 +219,22 @@ class Arena {
         if (!q) return SPC_ERR_OUT_OF_MEMORY;
         sizes_[q] = got;
         used_ += got;
-        if (used_ > peak_) peak_ = used_;
+        note_peak();
         *p = static_cast<T *>(q);
         return SPC_OK;
     }
+    // account for memory mapped outside the arena (VArray pieces)
+    spc_status charge(uint64_t bytes) {
+        if (budget_ && used_ + bytes > budget_) return SPC_ERR_OUT_OF_MEMORY;
+        used_ += bytes;
+        note_peak();
+        return SPC_OK;
+    }
+    void uncharge(uint64_t bytes) { used_ -= bytes < used_ ? bytes : used_; }
+    bool fits(uint64_t bytes) const { return !budget_ || used_ + bytes <= budget_; }
+    // high-water mark since the last begin_window()
+    void begin_window() { wpeak_ = used_; }
+    uint64_t window_peak() const { return wpeak_; }
     template <typename T>
     void release(T *&p) {
         if (!p) return;
@@ -220,9 +260,13 @@ class Arena {
     uint64_t peak() const { return peak_; }
 
   private:
+    void note_peak() {
+        if (used_ > peak_) peak_ = used_;
+        if (used_ > wpeak_) wpeak_ = used_;
+    }
     uint64_t budget_;
     hipStream_t st_;
-    uint64_t used_ = 0, peak_ = 0;
+    uint64_t used_ = 0, peak_ = 0, wpeak_ = 0;
     std::unordered_map<void *, size_t> sizes_;
 };
 
@@ -247,7 +291,8 @@ spc_status radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 struct RoundCounters {
     uint64_t raw = 0, merged = 0, kept = 0, scanned = 0;
     uint64_t staged = 0, row_bytes = 0, headers = 0;
-    double kernel_ms = 0;  // fused round kernel time of this round
+    uint64_t mem_peak = 0;  // device bytes held by the build at the round's high-water mark
+    double kernel_ms = 0;   // fused round kernel time of this round
 };
 
 }  // namespace spc

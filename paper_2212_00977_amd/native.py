@@ -90,7 +90,7 @@ def load(path: str | None = None):
     L.spc_index_stats.restype = C.c_int
     L.spc_round_stats.argtypes = [vp, u32, vp, vp, vp, vp]
     L.spc_round_stats.restype = C.c_int
-    L.spc_round_profile.argtypes = [vp, u32, vp, vp, vp, vp]
+    L.spc_round_profile.argtypes = [vp, u32, vp, vp, vp, vp, vp]
     L.spc_round_profile.restype = C.c_int
     L.spc_graph_entries.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(u64)]
     L.spc_graph_entries.restype = C.c_int

@@ -145,11 +145,13 @@ class Index:
     def round_profile(self) -> dict:
         R = self.stats()["rounds"] + 1
         ms = np.zeros(R, dtype=np.float64)
-        arrs = {k: np.zeros(R, dtype=np.uint64) for k in ("staged", "row_bytes", "headers")}
+        arrs = {k: np.zeros(R, dtype=np.uint64) for k in ("staged", "row_bytes", "headers",
+                                                           "mem_peak")}
         _check(native.load().spc_round_profile(self.handle, R, ms.ctypes.data,
                                                arrs["staged"].ctypes.data,
                                                arrs["row_bytes"].ctypes.data,
-                                               arrs["headers"].ctypes.data), "spc_round_profile")
+                                               arrs["headers"].ctypes.data,
+                                               arrs["mem_peak"].ctypes.data), "spc_round_profile")
         arrs["kernel_ms"] = ms
         return arrs
 
