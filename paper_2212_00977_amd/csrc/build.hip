@@ -321,6 +321,7 @@ struct RoundArgs {
     const uint32_t *plen;
     const uint32_t *pool_hub;        // round d-1 entries
     const uint64_t *pool_cnt;
+    uint32_t *cur, *nxt;             // per adjacency slot: segment positions at lo / hi
     const uint64_t *raw_off;  // exclusive prefix of raw over all vertices
     uint32_t *tmp_hub;
     uint64_t *tmp_cnt;
@@ -330,6 +331,23 @@ struct RoundArgs {
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t h, int bits) {
     return (h * 0x9E3779B1u) >> (32 - bits);
+}
+
+// first position p in [c, n) with a[p] >= key, where every position below c
+// holds a smaller value: exponential steps from c, then a binary search
+__device__ __forceinline__ uint32_t gallop_u32(const uint32_t *a, uint32_t c, uint32_t n, uint32_t key) {
+    uint32_t lo = c, step = 1, end = n;
+    while (lo < n) {
+        const uint32_t p = lo + step - 1;
+        if (p >= n) break;
+        if (a[p] >= key) {
+            end = p;
+            break;
+        }
+        lo = p + 1;
+        step <<= 1;
+    }
+    return lo + lower_bound_u32(a + lo, end - lo, key);
 }
 
 template <int DB>
@@ -453,15 +471,65 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
     const uint64_t tbase = a.raw_off[u] - a.raw_off[a.u_lo];
     uint32_t nout = 0;
     uint64_t st_raw = 0, st_merged = 0, st_kept = 0;
+    // Chunks of the hub range [0, u).  Every neighbour keeps a cursor into
+    // its round d-1 segment (first entry with hub >= lo), so a chunk costs one
+    // galloping search per neighbour; a chunk is sized from its exact pull
+    // count and the pulls-per-distinct-candidate ratio seen so far, so that
+    // the candidate table rarely overflows.
+    constexpr uint32_t kTarget = kULimit * 3 / 4;  // distinct candidates aimed at
+    const bool one_group = deg <= (uint32_t)RB;   // cursors live in registers
+    uint32_t my_v = 0, my_ln = 0, my_c = 0, my_e = 0;
+    uint64_t my_ps = 0;
+    if (one_group && tid < deg) {
+        my_v = a.gadj[g0 + tid];
+        my_ln = a.plen[my_v];
+        my_ps = my_ln ? a.pstart[my_v] : 0;
+    }
+    float ratio = 2.0f;      // pulls per distinct candidate
+    bool may_widen = true;   // false from an overflow until a chunk completes
     uint32_t lo = 0, width = u;
-    if (raw_u > 2 * (uint64_t)kULimit) {  // first guess: about 2 pulls per distinct hub
-        uint64_t parts = (raw_u + 2 * kULimit - 1) / (2 * kULimit);
+    if (raw_u > (uint64_t)(2 * kTarget)) {
+        uint64_t parts = (raw_u + 2 * kTarget - 1) / (2 * kTarget);
         width = (uint32_t)(u / parts) > 0 ? (uint32_t)(u / parts) : 1;
     }
 
-    // 2-5, chunk by chunk over the hub range [0, u)
+    // 2-5, chunk by chunk
     while (lo < u) {
-        const uint32_t hi = (width >= u - lo) ? u : lo + width;
+        // A. size the chunk.  With cursors in registers the exact pull count
+        //    of [lo, hi) is cheap: the range is narrowed or widened once so
+        //    that the expected distinct count fits.  Wider pullers take the
+        //    width learned from the previous chunk.
+        uint32_t hi = (width >= u - lo) ? u : lo + width, tot = 0;
+        if (one_group) {
+            for (int it = 0;; it++) {
+                hi = (width >= u - lo) ? u : lo + width;
+                uint32_t t = 0;
+                if (tid < deg) {
+                    // hubs of v's segment are <= v
+                    my_e = (my_v >= lo && my_c < my_ln) ? gallop_u32(a.pool_hub + my_ps, my_c, my_ln, hi)
+                                                        : my_c;
+                    t = my_e - my_c;
+                }
+                block_excl_scan<uint32_t, RW>(t, red32, tot);
+                if (it == 1) break;
+                const float expect = (float)tot / ratio;
+                if (expect > 1.25f * kTarget && hi - lo > 1) {
+                    uint32_t w2 = (uint32_t)((float)(hi - lo) * ((float)kTarget / expect));
+                    width = w2 ? w2 : 1;
+                    continue;
+                }
+                if (may_widen && expect < 0.5f * kTarget && hi < u) {
+                    float f = expect > 1.0f ? (float)kTarget / expect : 8.0f;
+                    f = f > 8.0f ? 8.0f : f;
+                    uint64_t w2 = (uint64_t)((double)(hi - lo) * f);
+                    width = w2 >= (uint64_t)(u - lo) ? u - lo : (uint32_t)w2;
+                    continue;
+                }
+                break;
+            }
+        }
+
+        // B. pull: Label Elimination, then Label Merging in the table
         for (int i = tid; i < kCCap; i += RB) {
             ckey[i] = kEmpty32;
             cval[i] = 0;
@@ -472,40 +540,32 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
             s_ovf = 0;
         }
         __syncthreads();
-        uint64_t chunk_raw = 0;
-        bool shrink = false;
         for (uint32_t nb0 = 0; nb0 < deg; nb0 += RB) {
-            uint32_t nb = nb0 + tid;
+            const uint32_t nb = nb0 + tid;
             uint64_t sb = 0;
             uint32_t len = 0;
             if (nb < deg) {
-                uint32_t v = a.gadj[g0 + nb];
-                uint32_t ln = a.plen[v];
-                if (v >= lo && ln) {  // hubs of v's segment are <= v
-                    uint64_t ps = a.pstart[v];
-                    const uint32_t *ph = a.pool_hub + ps;
-                    uint32_t b = lo ? lower_bound_u32(ph, ln, lo) : 0;
-                    uint32_t e = lower_bound_u32(ph, ln, hi);
-                    sb = ps + b;
-                    len = e - b;
+                uint32_t c = my_c, e = my_e;
+                uint64_t ps = my_ps;
+                if (!one_group) {
+                    const uint32_t v = a.gadj[g0 + nb];
+                    const uint32_t ln = a.plen[v];
+                    ps = ln ? a.pstart[v] : 0;
+                    c = lo ? a.cur[g0 + nb] : 0;
+                    e = (v >= lo && c < ln) ? gallop_u32(a.pool_hub + ps, c, ln, hi) : c;
+                    a.nxt[g0 + nb] = e;
                 }
+                sb = ps + c;
+                len = e - c;
             }
-            uint32_t tot;
-            uint32_t ex = block_excl_scan<uint32_t, RW>(len, red32, tot);
-            // all pulls of the chunk are counted before any insert: a chunk
-            // that certainly overflows is narrowed right away
-            if (deg <= (uint32_t)RB && tot > 4u * kULimit && hi - lo > 1) {
-                shrink = true;
-                width = (uint32_t)(((uint64_t)(hi - lo) * (2 * kULimit)) / tot);
-                if (width == 0) width = 1;
-                break;
-            }
+            uint32_t gt;
+            const uint32_t ex = block_excl_scan<uint32_t, RW>(len, red32, gt);
+            if (!one_group) tot += gt;
             nb_start[tid] = sb;
             nb_off[tid] = ex;
             __syncthreads();
-            chunk_raw += tot;
             uint32_t jl = 0;  // owner of k: last j with nb_off[j] <= k (monotone in k)
-            for (uint32_t k = tid; k < tot; k += RB) {
+            for (uint32_t k = tid; k < gt; k += RB) {
                 if (*(volatile uint32_t *)&s_ovf) break;
                 if (jl + 1 < (uint32_t)RB && nb_off[jl + 1] <= k) {
                     uint32_t lo2 = jl + 1, hi2 = RB - 1;
@@ -549,15 +609,25 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
             }
             __syncthreads();
         }
-        if (shrink) {
-            __syncthreads();
-            continue;
-        }
-        if (s_ovf) {  // too many distinct hubs: retry a narrower range
+        if (s_ovf) {
+            // too many distinct hubs after all: at least s_nuniq of them came
+            // from at most tot pulls, so the ratio is lowered to match and
+            // the range only narrows until a chunk completes (a range of one
+            // hub always fits)
+            const float r = (float)tot / (float)(s_nuniq > 0 ? s_nuniq : 1);
+            ratio = r < ratio ? r : ratio;
+            may_widen = false;
             width = (hi - lo) > 1 ? (hi - lo) >> 1 : 1;
             __syncthreads();
             continue;
         }
+        // the chunk is complete: advance the cursors
+        if (one_group) {
+            my_c = my_e;
+        } else {
+            for (uint32_t nb = tid; nb < deg; nb += RB) a.cur[g0 + nb] = a.nxt[g0 + nb];
+        }
+        const uint64_t chunk_raw = tot;
 
         // compact the table into a list (any order: survivors are ranked by
         // hub at the end)
@@ -740,7 +810,14 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
         st_merged += M;
         st_kept += S;
         lo = hi;
-        if (M < (uint32_t)kULimit / 4 && width < 0x40000000u) width <<= 1;
+        if (M) ratio = (float)chunk_raw / (float)M;
+        if (!one_group) {  // next width from this chunk's distinct count
+            float f = M ? (float)kTarget / (float)M : 4.0f;
+            f = f > 4.0f ? 4.0f : (f < 0.5f ? 0.5f : f);
+            uint64_t w2 = (uint64_t)((double)width * f);
+            width = w2 < 1 ? 1 : (w2 > 0x7FFFFFFFull ? 0x7FFFFFFFu : (uint32_t)w2);
+        }
+        may_widen = true;
         __syncthreads();
     }
     if (tid == 0) {
@@ -981,6 +1058,7 @@ struct Build {
     // per-round scratch
     uint64_t *raw = nullptr, *raw_off = nullptr, *soff = nullptr, *nlen = nullptr;
     uint32_t *surv = nullptr;
+    uint32_t *cur = nullptr, *nxt = nullptr;  // per adjacency slot (round kernel cursors)
     uint32_t *tmp_hub = nullptr;
     uint64_t *tmp_cnt = nullptr;
     uint64_t tmp_cap = 0;
@@ -1418,6 +1496,8 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.tmp_hub = B.tmp_hub;
         ra.tmp_cnt = B.tmp_cnt;
         ra.surv = B.surv;
+        ra.cur = B.cur;
+        ra.nxt = B.nxt;
         ra.ctr = B.ctr;
         SPC_HIP(hipEventRecord(B.ev_a, B.st));
         k_round<DB, kRoundBlock><<<dim3(b1 - b0), dim3(kRoundBlock), 0, B.st>>>(ra);
@@ -1604,6 +1684,8 @@ spc_status finalize_counts(Build &B, uint64_t **lab_cnt, uint64_t *nsat_out) {
         B.lab_hd2 = nullptr;
         B.lab_cap2 = 0;
     }
+    B.arena.release(B.cur);
+    B.arena.release(B.nxt);
     const uint32_t R = (uint32_t)B.rstart.size();
     const bool by_rank = DB == 8 && R <= 256;
     if (by_rank)
@@ -1739,6 +1821,8 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     SPC_TRY(B.arena.alloc(&B.soff, (uint64_t)N + 1));
     SPC_TRY(B.arena.alloc(&B.nlen, (uint64_t)N + 1));
     SPC_TRY(B.arena.alloc(&B.surv, (uint64_t)N + 1));
+    SPC_TRY(B.arena.alloc(&B.cur, std::max<uint64_t>(NNZ, 1)));
+    SPC_TRY(B.arena.alloc(&B.nxt, std::max<uint64_t>(NNZ, 1)));
     SPC_TRY(B.arena.alloc(&B.lab_off, (uint64_t)N + 1));
     SPC_TRY(B.arena.alloc(&B.lab_off2, (uint64_t)N + 1));
     {
