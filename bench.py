@@ -104,6 +104,134 @@ def serve_runs(ix, n, args, sat_qps, log):
             "launches": r0["served"]["launches"]}
 
 
+def bench_served(args, dev, log):
+    """Served load on a resident index: R-MAT scale 21 (a,b,c,d = 0.57,0.19,
+    0.19,0.05, edge factor 16, seed 5).  Saturation = served throughput of a
+    burst of requests all arriving at once; then Poisson arrivals at 0.25 ..
+    1.25 x saturation (batch sizes log-uniform in [1, 65536], uniform pairs),
+    continuous batching vs one request at a time (FIFO), latency from each
+    request's scheduled arrival."""
+    import numpy as np
+    import torch
+
+    from paper_2212_00977_amd import inputs, serve, spc
+
+    scale = 21 - args.scale_down
+    log(f"generating R-MAT scale {scale}")
+    g = inputs.rmat(scale, 16, seed=5)
+    off_d = torch.from_numpy(g.off.view(np.int64)).to(dev)
+    adj_d = torch.from_numpy(g.adj.view(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    st = ix.stats()
+    log(f"build {build_ms:.0f} ms, {st['entries']} entries, peak {st['peak_build_bytes'] / 2**30:.1f} GiB")
+    del off_d, adj_d
+    spc.release_cached_memory()
+    torch.cuda.empty_cache()
+
+    mean_batch = 65536 / np.log(65537) - 0.5
+    srv_kw = dict(io_budget_bytes=1 << 30, streams=4, max_batch=1 << 18)
+    # saturation: a burst (every request at t = 0)
+    burst = serve.requests_from(inputs.poisson_requests(g.n, 1e9, args.serve_requests // 2, seed=6))
+    for r in burst:
+        r.arrival = 0.0
+    srv = serve.Server(ix, **srv_kw)
+    srv.run(burst[:20])  # warm the streams and pinned host buffers
+    serve.fifo_baseline(ix, burst[:20])
+    sat = srv.run(burst).summary()
+    sat_qps = sat["queries_per_s"]
+    log(f"saturation: {sat_qps:.3g} q/s over {sat['requests']} requests")
+    levels = []
+    for lv in (0.25, 0.5, 0.75, 1.0, 1.25):
+        rate = lv * sat_qps / mean_batch
+        reqs = serve.requests_from(inputs.poisson_requests(g.n, rate, args.serve_requests,
+                                                           seed=7 + int(100 * lv)))
+        served = srv.run(reqs).summary()
+        fifo = serve.fifo_baseline(ix, reqs).summary()
+        log(f"{lv:.2f}x: served {served['queries_per_s']:.3g} q/s p50 {served['p50_ms']:.2f} ms "
+            f"p99 {served['p99_ms']:.2f} ms deferred {served['deferred']} | fifo p50 "
+            f"{fifo['p50_ms']:.2f} p99 {fifo['p99_ms']:.2f}")
+        levels.append({"offered_fraction": lv, "offered_requests_per_s": rate, "served": served,
+                       "fifo": fifo})
+    ix.free()
+    one = levels[3]["served"]
+    out = {"metric": METRIC, "value": one["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+           "steps": len(levels), "warmup": 1, "ms_per_step": one["makespan_s"] * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+           "data": "synthetic",
+           "config": {"workload": f"served SPC queries on a resident R-MAT scale {scale} index "
+                                  "(ef 16, seed 5); Poisson requests, batch sizes log-uniform "
+                                  "in 1..65536; value = served q/s at 1.0x saturation",
+                      "n": g.n, "m": g.m, "entries": st["entries"], "rounds": st["rounds"],
+                      "requests_per_level": args.serve_requests, "parallelism": "single-gpu"},
+           "p50_ms": one["p50_ms"], "p99_ms": one["p99_ms"],
+           "build_ms": build_ms, "build_entries_per_s": st["entries"] / (build_ms * 1e-3),
+           "index_bytes": st["index_bytes"], "peak_build_bytes": st["peak_build_bytes"],
+           "saturation": sat, "levels": levels}
+    print(json.dumps(out), flush=True)
+
+
+def bench_grid(args, dev, log):
+    """High-diameter workload: k x k 4-neighbour grid, 5% of edges deleted
+    uniformly (seed 3), largest component, degree order with seeded random
+    ties.  With a round cap D the index is L_{<=D}: answers up to D are
+    exact, longer ones carry the horizon flag."""
+    import numpy as np
+    import torch
+
+    from paper_2212_00977_amd import inputs, spc
+
+    k = args.grid_k
+    log(f"generating grid {k}x{k}")
+    g = inputs.grid_lcc(k, 0.05, seed=3)
+    off_d = torch.from_numpy(g.off.view(np.int64)).to(dev)
+    adj_d = torch.from_numpy(g.adj.view(np.int32)).to(dev)
+    tie_d = torch.from_numpy(g.tie_key.view(np.int64)).to(dev)
+    s_np, t_np = inputs.queries(g.n, args.queries, seed=3)
+    s_d = torch.from_numpy(s_np.view(np.int32)).to(dev)
+    t_d = torch.from_numpy(t_np.view(np.int32)).to(dev)
+    stream = torch.cuda.current_stream()
+    opts = spc.BuildOptions(round_cap=args.round_cap)
+    torch.cuda.synchronize()
+    runs = []
+    for i in range(args.warmup + args.steps):
+        t0 = time.perf_counter()
+        ix = spc.build_index(off_d, adj_d, tie_key=tie_d, opts=opts, device=dev, stream=stream)
+        bms = (time.perf_counter() - t0) * 1e3
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        dist, cnt, flg = ix.query(s_d, t_d, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        qms = ev0.elapsed_time(ev1)
+        st = ix.stats()
+        log(f"{'warmup' if i < args.warmup else 'step'} {i}: build {bms:.0f} ms, query {qms:.1f} ms, "
+            f"entries {st['entries']}, rounds {st['rounds']}")
+        if i >= args.warmup:
+            runs.append((bms, qms))
+        f = flg.cpu().numpy()
+        ix.free()
+    bms = float(np.mean([r[0] for r in runs]))
+    qms = float(np.mean([r[1] for r in runs]))
+    horizon = int(((f & spc.FLAG_HORIZON) != 0).sum())
+    out = {"metric": METRIC, "value": st["entries"] / (bms * 1e-3), "unit": "label entries/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": bms + qms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+           "data": "synthetic",
+           "config": {"workload": f"grid {k}x{k}, 5% edges deleted, LCC, seed 3, random ties, "
+                                  f"round cap {args.round_cap or 'none'}, {args.queries} queries",
+                      "n": g.n, "m": g.m, "entries": st["entries"], "rounds": st["rounds"],
+                      "truncated": bool(st["truncated"]), "dist_bits": st["dist_bits"],
+                      "parallelism": "single-gpu"},
+           "build_ms": bms, "query_ms": qms, "queries_per_s": args.queries / (qms * 1e-3),
+           "queries_beyond_horizon": horizon, "index_bytes": st["index_bytes"],
+           "peak_build_bytes": st["peak_build_bytes"]}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args, dev, log):
     """512 independent R-MAT graphs (a,b,c,d = 0.57,0.19,0.19,0.05, edge factor
     8, scales uniform in 10..16, seed 4): one batched build vs one plain build
@@ -196,9 +324,16 @@ def main():
     ap.add_argument("--serve-sweep", action="store_true",
                     help="after the steps, sweep the offered load (0.25..1.25 x saturation) "
                          "and print one JSON line per level")
-    ap.add_argument("--workload", default="chunglu", choices=["chunglu", "rmat_batch"],
+    ap.add_argument("--workload", default="chunglu", choices=["chunglu", "rmat_batch", "rmat_served", "grid"],
                     help="chunglu: the benchmark line; rmat_batch: 512 R-MAT graphs built as one "
-                         "batch vs one build per graph (separate JSON line)")
+                         "batch vs one build per graph; rmat_served: offered-load sweep on a "
+                         "resident R-MAT scale-21 index; grid: k x k grid with a round "
+                         "cap (separate JSON lines)")
+    ap.add_argument("--grid-k", type=int, default=2048, help="grid side (grid workload)")
+    ap.add_argument("--round-cap", type=int, default=64,
+                    help="round cap D for the grid workload (0 = complete index)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests per offered-load level (rmat_served)")
     ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (for scaling "
@@ -230,6 +365,10 @@ def main():
 
     if args.workload == "rmat_batch":
         return bench_batch(args, dev, log)
+    if args.workload == "rmat_served":
+        return bench_served(args, dev, log)
+    if args.workload == "grid":
+        return bench_grid(args, dev, log)
 
     log("generating graph")
     g = inputs.workload("chunglu", scale_down=args.scale_down)

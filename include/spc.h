@@ -113,7 +113,8 @@ typedef struct {
  * g, opts and out must be non-NULL.  Returns SPC_ERR_INVALID_ARG for a
  * malformed graph (ids >= n, self loops, asymmetric or duplicate entries when
  * validate is set, order not a permutation), SPC_ERR_UNSUPPORTED when
- * n >= 2^24 with 8-bit labels, SPC_ERR_DIST_RANGE as documented above. */
+ * n >= 2^24 - 1 with dist_bits = 8, n > 2^26 - 1024 (all graphs of a batch
+ * together) or nnz > 2^32 - 2^20, SPC_ERR_DIST_RANGE as documented above. */
 spc_status spc_build_index(const spc_graph *g, const spc_build_opts *opts, void *stream,
                            spc_index **out);
 
@@ -139,7 +140,8 @@ spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_
 void spc_free(spc_index *ix);
 
 /* Return every cached device block to the HIP runtime (all devices).  The
- * cache is also flushed automatically when an allocation would fail. */
+ * cache is also flushed automatically when an allocation would fail, and
+ * trimmed to a quarter of the device's memory after every build and free. */
 void spc_release_cached_memory(void);
 
 /* Summary numbers of a finished build (host struct). */

@@ -252,15 +252,18 @@ __device__ __forceinline__ uint32_t land_count_le(uint64_t x, uint32_t lim) {
 template <int DB>
 __global__ void k_land_init(uint32_t N, const uint32_t *gbase, typename Land<DB>::T *land) {
     using LT = typename Land<DB>::T;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (uint64_t)N * kLand) return;
-    uint32_t v = (uint32_t)(i / kLand), l = (uint32_t)(i % kLand);
-    uint32_t base = gbase ? gbase[v] : 0;
-    land[i] = (v - base == l) ? (LT)0 : (LT)~(LT)0;
+    const uint64_t n = (uint64_t)N * kLand;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t v = (uint32_t)(i / kLand), l = (uint32_t)(i % kLand);
+        uint32_t base = gbase ? gbase[v] : 0;
+        land[i] = (v - base == l) ? (LT)0 : (LT)~(LT)0;
+    }
 }
 __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i] == 0xFF ? (uint16_t)0xFFFF : (uint16_t)src[i];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] == 0xFF ? (uint16_t)0xFFFF : (uint16_t)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -918,8 +921,8 @@ __global__ void k_lc_init(uint32_t N, const uint32_t *gbase, uint32_t *lc) {
 
 // Widen packed entries from 8-bit to 16-bit distances.
 __global__ void k_widen(const uint32_t *src, uint64_t *dst, uint64_t n) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t e = src[i];
         dst[i] = e_make<16>(e_hub<8>(e), e_dist<8>(e));
     }
@@ -1005,6 +1008,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize_rank(uint32_t N, uint32_t R
 inline uint32_t grid_for(uint64_t items, uint32_t per_block) {
     return (uint32_t)((items + per_block - 1) / per_block);
 }
+// grid of a grid-stride kernel over `items` (one per thread): a launch's
+// work-item count must stay below 2^32
+inline uint32_t grid_stride(uint64_t items) {
+    uint64_t b = (items + kBlock - 1) / kBlock;
+    return (uint32_t)(b < (1u << 20) ? (b ? b : 1) : (1u << 20));
+}
 
 inline int bit_width(uint64_t x) {
     int b = 0;
@@ -1018,6 +1027,9 @@ inline int bit_width(uint64_t x) {
 // ---------------------------------------------------------------------------
 // Host-side build state
 // ---------------------------------------------------------------------------
+constexpr uint64_t kMaxVertices = (1ull << 26) - 1024;
+constexpr uint64_t kMaxAdjacency = (1ull << 32) - (1ull << 20);
+
 // rounds that may insert at least this many entries grow in place (mapped
 // address ranges); smaller ones are copied when they grow
 constexpr uint64_t kVmmMinEntries = 1ull << 24;
@@ -1406,6 +1418,9 @@ spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_ti
 
 // largest temp buffer (entries) one batch of pullers may use
 constexpr uint64_t kTempMax = 1ull << 27;
+// pullers per round-kernel launch (one workgroup each: the launch's
+// work-item count stays below 2^32)
+constexpr uint32_t kBatchVerts = 1u << 22;
 
 // One distance round d >= 1.  Returns the number of entries it inserted.
 template <int DB>
@@ -1428,7 +1443,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
 
     // batches of pullers whose temp space fits
     std::vector<uint32_t> bounds{0};
-    if (total_raw <= kTempMax) {
+    if (total_raw <= kTempMax && N <= kBatchVerts) {
         bounds.push_back(N);
     } else {
         std::vector<uint64_t> ro((size_t)N + 1);
@@ -1440,6 +1455,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
             uint64_t lim = ro[b0] + kTempMax;
             uint32_t b1 = (uint32_t)(std::upper_bound(ro.begin() + b0 + 1, ro.end(), lim) - ro.begin()) - 1;
             if (b1 <= b0) b1 = b0 + 1;
+            if (b1 - b0 > kBatchVerts) b1 = b0 + kBatchVerts;
             bounds.push_back(b1);
             b0 = b1;
         }
@@ -1643,7 +1659,7 @@ spc_status widen_buffer(Build &B, void **buf, uint64_t *cap, uint64_t n) {
     uint64_t c = std::max<uint64_t>(n, 1);
     SPC_TRY(B.arena.alloc(&w, c));
     if (n) {
-        hipLaunchKernelGGL(k_widen, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st,
+        hipLaunchKernelGGL(k_widen, dim3(grid_stride(n)), dim3(kBlock), 0, B.st,
                            static_cast<const uint32_t *>(*buf), w, n);
         SPC_LAUNCHED();
     }
@@ -1662,7 +1678,7 @@ spc_status widen_labels(Build &B) {
     uint64_t nl = (uint64_t)B.N * kLand;
     uint16_t *l16 = nullptr;
     SPC_TRY(B.arena.alloc(&l16, nl));
-    hipLaunchKernelGGL(k_land_widen, dim3(grid_for(nl, kBlock)), dim3(kBlock), 0, B.st,
+    hipLaunchKernelGGL(k_land_widen, dim3(grid_stride(nl)), dim3(kBlock), 0, B.st,
                        static_cast<const uint8_t *>(B.land), l16, nl);
     SPC_LAUNCHED();
     SPC_HIP(hipStreamSynchronize(B.st));
@@ -1736,7 +1752,9 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     }
     if ((n_order && n_order != k) || (n_tie && n_tie != k) || (n_dev && n_dev != k))
         return SPC_ERR_INVALID_ARG;
-    if (N64 >= 0xFFFFFFFFull) return SPC_ERR_UNSUPPORTED;
+    // one wave per vertex in several kernels, one work-item per adjacency
+    // slot in others: a launch's work-item count must stay below 2^32
+    if (N64 > kMaxVertices || NNZ > kMaxAdjacency) return SPC_ERR_UNSUPPORTED;
     int db = (o->dist_bits == 16) ? 16 : 8;
     if (db == 8 && N64 > Ent<8>::kMaxHub - 1) {
         if (o->dist_bits == 8) return SPC_ERR_UNSUPPORTED;
@@ -1857,13 +1875,13 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
                 uint8_t *l8 = nullptr;
                 SPC_TRY(B.arena.alloc(&l8, nl));
                 B.land = l8;
-                hipLaunchKernelGGL(k_land_init<8>, dim3(grid_for(nl, kBlock)), dim3(kBlock), 0, st, N,
+                hipLaunchKernelGGL(k_land_init<8>, dim3(grid_stride(nl)), dim3(kBlock), 0, st, N,
                                    (const uint32_t *)B.gbase, l8);
             } else {
                 uint16_t *l16 = nullptr;
                 SPC_TRY(B.arena.alloc(&l16, nl));
                 B.land = l16;
-                hipLaunchKernelGGL(k_land_init<16>, dim3(grid_for(nl, kBlock)), dim3(kBlock), 0, st, N,
+                hipLaunchKernelGGL(k_land_init<16>, dim3(grid_stride(nl)), dim3(kBlock), 0, st, N,
                                    (const uint32_t *)B.gbase, l16);
             }
             SPC_LAUNCHED();

@@ -6,6 +6,19 @@
 
 #include "spc_internal.h"
 
+namespace {
+// The block cache keeps at most a quarter of the current device's memory
+// after a build or a free: enough for the next build of a similar graph,
+// the rest goes back to the runtime for other allocators.
+void trim_cache() {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+        spc::cache_trim(tot / 4);
+    else
+        (void)hipGetLastError();
+}
+}  // namespace
+
 extern "C" {
 
 const char *spc_status_string(spc_status s) {
@@ -23,13 +36,17 @@ const char *spc_status_string(spc_status s) {
 spc_status spc_build_index(const spc_graph *g, const spc_build_opts *opts, void *stream,
                            spc_index **out) {
     if (!g || !opts || !out) return SPC_ERR_INVALID_ARG;
-    return spc::build_impl(g, 1, opts, static_cast<hipStream_t>(stream), out);
+    spc_status s = spc::build_impl(g, 1, opts, static_cast<hipStream_t>(stream), out);
+    trim_cache();
+    return s;
 }
 
 spc_status spc_build_index_batch(const spc_graph *gs, uint32_t k, const spc_build_opts *opts,
                                  void *stream, spc_index **out) {
     if (!gs || k == 0 || !opts || !out) return SPC_ERR_INVALID_ARG;
-    return spc::build_impl(gs, k, opts, static_cast<hipStream_t>(stream), out);
+    spc_status s = spc::build_impl(gs, k, opts, static_cast<hipStream_t>(stream), out);
+    trim_cache();
+    return s;
 }
 
 spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
@@ -46,6 +63,7 @@ void spc_free(spc_index *ix) {
                     hipSetDevice(ix->device) == hipSuccess;
     (void)hipDeviceSynchronize();  // queries may still read the index
     for (auto &b : ix->blocks) spc::cache_free(b.first, b.second);
+    trim_cache();
     if (switched) (void)hipSetDevice(cur);
     delete ix;
 }

@@ -15,6 +15,7 @@ namespace {
 
 struct DeviceCache {
     std::multimap<size_t, void *> free_blocks;  // size -> block
+    size_t bytes = 0;                           // total held
 };
 
 std::mutex g_mu;
@@ -30,6 +31,7 @@ DeviceCache &cache_for_current() {
 void flush_locked(DeviceCache &c) {
     for (auto &kv : c.free_blocks) (void)hipFree(kv.second);
     c.free_blocks.clear();
+    c.bytes = 0;
 }
 
 }  // namespace
@@ -42,6 +44,7 @@ void *cache_alloc(size_t bytes, size_t *got) {
         if (it != c.free_blocks.end() && it->first <= bytes + bytes / 8) {
             void *p = it->second;
             *got = it->first;
+            c.bytes -= it->first;
             c.free_blocks.erase(it);
             return p;
         }
@@ -65,7 +68,20 @@ void *cache_alloc(size_t bytes, size_t *got) {
 void cache_free(void *p, size_t bytes) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    cache_for_current().free_blocks.emplace(bytes, p);
+    DeviceCache &c = cache_for_current();
+    c.free_blocks.emplace(bytes, p);
+    c.bytes += bytes;
+}
+
+void cache_trim(size_t max_bytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCache &c = cache_for_current();
+    while (c.bytes > max_bytes && !c.free_blocks.empty()) {
+        auto it = std::prev(c.free_blocks.end());  // largest first
+        (void)hipFree(it->second);
+        c.bytes -= it->first;
+        c.free_blocks.erase(it);
+    }
 }
 
 void cache_flush() {

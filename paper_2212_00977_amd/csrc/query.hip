@@ -11,6 +11,8 @@
 // the other list's tile cannot move past it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "spc_internal.h"
@@ -162,13 +164,26 @@ spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
     a.dist_out = dist_out;
     a.count_out = count_out;
     a.flags_out = flags_out;
-    uint64_t blocks = (nq + kWaves - 1) / kWaves;
-    if (blocks > 0x7FFFFFFFull) return SPC_ERR_INVALID_ARG;
-    if (ix->dist_bits == 8)
-        hipLaunchKernelGGL(k_query<8>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_query<16>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, a);
-    SPC_LAUNCHED();
+    // one wave per query: launches of at most 2^24 queries keep the
+    // work-item count of each below 2^32
+    constexpr uint64_t kChunk = 1ull << 24;
+    const size_t dsz = ix->dist_bits == 8 ? 1 : 2;
+    for (uint64_t q0 = 0; q0 < nq; q0 += kChunk) {
+        const uint64_t nc = std::min(kChunk, nq - q0);
+        QueryArgs c = a;
+        c.s = s + q0;
+        c.t = t + q0;
+        c.nq = nc;
+        c.dist_out = static_cast<char *>(dist_out) + q0 * dsz;
+        c.count_out = count_out + q0;
+        c.flags_out = flags_out ? flags_out + q0 : nullptr;
+        const uint32_t blocks = (uint32_t)((nc + kWaves - 1) / kWaves);
+        if (ix->dist_bits == 8)
+            hipLaunchKernelGGL(k_query<8>, dim3(blocks), dim3(kBlock), 0, st, c);
+        else
+            hipLaunchKernelGGL(k_query<16>, dim3(blocks), dim3(kBlock), 0, st, c);
+        SPC_LAUNCHED();
+    }
     return SPC_OK;
 }
 
@@ -199,17 +214,21 @@ spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, ui
                            ix->lab_off, vb, n, d_off);
         SPC_LAUNCHED();
     }
-    if ((hub || dist || count) && ne) {
+    // entries in launches of at most 2^30 (one work-item each)
+    constexpr uint64_t kChunk = 1ull << 30;
+    for (uint64_t i0 = 0; (hub || dist || count) && i0 < ne; i0 += kChunk) {
+        const uint64_t nc = std::min(kChunk, ne - i0);
+        uint32_t *h = hub ? d_hub + i0 : nullptr;
+        uint16_t *dd = dist ? d_dist + i0 : nullptr;
+        uint64_t *cc = count ? d_cnt + i0 : nullptr;
         if (ix->dist_bits == 8)
-            hipLaunchKernelGGL(k_export_ent<8>, dim3(grid1(ne)), dim3(kBlock), 0, st,
-                               static_cast<const uint32_t *>(ix->lab_hd), ix->lab_cnt, e0, ne, vb,
-                               hub ? d_hub : nullptr, dist ? d_dist : nullptr,
-                               count ? d_cnt : nullptr);
+            hipLaunchKernelGGL(k_export_ent<8>, dim3(grid1(nc)), dim3(kBlock), 0, st,
+                               static_cast<const uint32_t *>(ix->lab_hd), ix->lab_cnt, e0 + i0, nc,
+                               vb, h, dd, cc);
         else
-            hipLaunchKernelGGL(k_export_ent<16>, dim3(grid1(ne)), dim3(kBlock), 0, st,
-                               static_cast<const uint64_t *>(ix->lab_hd), ix->lab_cnt, e0, ne, vb,
-                               hub ? d_hub : nullptr, dist ? d_dist : nullptr,
-                               count ? d_cnt : nullptr);
+            hipLaunchKernelGGL(k_export_ent<16>, dim3(grid1(nc)), dim3(kBlock), 0, st,
+                               static_cast<const uint64_t *>(ix->lab_hd), ix->lab_cnt, e0 + i0, nc,
+                               vb, h, dd, cc);
         SPC_LAUNCHED();
     }
     if (order && n) {

@@ -162,6 +162,9 @@ __device__ __forceinline__ uint64_t lower_bound_hub(const typename Ent<DB>::T *a
 void *cache_alloc(size_t bytes, size_t *got);
 void cache_free(void *p, size_t bytes);
 void cache_flush();
+// free the largest cached blocks of the current device until at most
+// max_bytes stay cached
+void cache_trim(size_t max_bytes);
 
 // Growable device array on the virtual memory API: an address range is
 // reserved once and physical memory is mapped behind it piece by piece, so

@@ -263,6 +263,12 @@ def build_index_batch(graphs, opts: BuildOptions | None = None, device=None, str
     return Index(h, device)
 
 
+def release_cached_memory():
+    """Return the library's cached device blocks (freed build buffers) to
+    the device allocator."""
+    native.load().spc_release_cached_memory()
+
+
 def as_u64(count_tensor) -> np.ndarray:
     """Host uint64 view of a count tensor (int64 bit pattern)."""
     return count_tensor.cpu().numpy().view(np.uint64)
