@@ -1581,13 +1581,20 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     uint64_t new_entries = B.entries + kept;
     if (B.lab_cap2 < new_entries) {
         // the older buffer (distances <= d-2) is dead once the round kernel
-        // has run: free it first, then take exactly the merged size
+        // has run: free it first, then take the merged size, plus an eighth
+        // when the labels grew by less than 1/16 this round (the two
+        // buffers alternate, so slowly growing labels reuse them for many
+        // rounds; a fast-growing index gets no slack)
         E *p2 = static_cast<E *>(B.lab_hd2);
         B.arena.release(p2);
         B.lab_cap2 = 0;
-        SPC_TRY(B.arena.alloc(&p2, new_entries));
+        uint64_t cap = new_entries + (kept < B.entries / 16 ? new_entries / 8 : 0);
+        if (B.arena.alloc(&p2, cap) != SPC_OK) {
+            cap = new_entries;
+            SPC_TRY(B.arena.alloc(&p2, cap));
+        }
         B.lab_hd2 = p2;
-        B.lab_cap2 = new_entries;
+        B.lab_cap2 = cap;
     }
     hipLaunchKernelGGL(k_merge<DB>, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, d, B.lab_off,
                        static_cast<const E *>(B.lab_hd), rs, rl, B.rhub[d], B.lab_off2,

@@ -117,7 +117,7 @@ hipMemAllocationProp device_prop(int dev) {
     p.location.id = dev;
     return p;
 }
-constexpr size_t kPieceMin = size_t(64) << 20;  // mapping piece bounds
+constexpr size_t kPieceMin = size_t(2) << 20;  // mapping piece bounds
 constexpr size_t kPieceMax = size_t(2) << 30;
 // pieces start and end on 2 MiB boundaries (the large-page size), whatever
 // smaller granularity the runtime reports
