@@ -1,14 +1,13 @@
 // SPC queries over the finished index (Eq. con:spc1 and con:spc2) and label
 // export, gfx950.
 //
-// A query (s, t) merges the hub-sorted labels L(s) and L(t): the common hubs
+// A query (s, t) joins the hub-sorted labels L(s) and L(t): the common hubs
 // with the least d_s + d_t form H, and the answer is the saturating sum of
-// count_s * count_t over H.  One wave per query walks both labels in tiles of
-// 64 entries (coalesced loads); each lane looks its L(s) entry's hub up in
-// the current L(t) tile with a 6-step binary search over lane shuffles, and
-// the tile whose last hub is smaller advances (both on a tie).  Every pair of
-// equal hubs meets exactly once: while one of them is in the current tile,
-// the other list's tile cannot move past it.
+// count_s * count_t over H.  One wave per query: L(s) is staged in LDS a
+// slice at a time and the part of L(t) in the slice's hub range is streamed
+// past it, several tiles per round of loads, each entry binary-searched in
+// LDS.  The loads of a round are independent, so a query waits for a few
+// memory round trips per slice rather than one per tile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,13 +34,18 @@ struct QueryArgs {
     uint8_t *flags_out;
 };
 
+constexpr uint32_t kQStage = 512;  // L(s) entries staged per wave
+constexpr int kQTiles = 4;         // L(t) tiles of 64 requested together
+
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     using E = typename Ent<DB>::T;
     using DT = typename std::conditional<DB == 8, uint8_t, uint16_t>::type;
+    __shared__ E stage[kWaves][kQStage];
     const uint64_t q = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (q >= a.nq) return;
     const uint32_t lane = threadIdx.x & 63;
+    E *st = stage[threadIdx.x >> 6];
     const E *hd = static_cast<const E *>(a.lab_hd);
     const uint32_t s = a.s[q], t = a.t[q];
     const DT kInf = (DT)~(DT)0;
@@ -59,36 +63,87 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     uint32_t best = 0xFFFFFFFFu;
     uint64_t sum = 0;
     uint64_t ia = 0, ib = 0;
+    // L(s) is taken kQStage entries at a time into LDS (one round of
+    // independent loads); the entries of L(t) whose hubs fall in the staged
+    // hub range are streamed kQTiles tiles at a time and each is binary-
+    // searched in the staged part.  Hub ranges of consecutive stages abut,
+    // so every common hub is met exactly once.
     while (ia < na && ib < nb) {
-        const bool va = ia + lane < na, vb = ib + lane < nb;
-        const E ea = va ? hd[as + ia + lane] : (E)~(E)0;
-        const E eb = vb ? hd[bs + ib + lane] : (E)~(E)0;
-        const uint32_t ha = va ? e_hub<DB>(ea) : 0xFFFFFFFFu;
-        const uint32_t hb = vb ? e_hub<DB>(eb) : 0xFFFFFFFFu;
-        // lower bound of ha among the 64 hubs of the B tile
-        uint32_t p = 0;
+        const uint32_t cnt = (uint32_t)((na - ia) < kQStage ? (na - ia) : kQStage);
+        E nxt = (E)~(E)0;
 #pragma unroll
-        for (uint32_t step = 32; step > 0; step >>= 1) {
-            uint32_t x = __shfl(hb, (int)(p + step - 1), 64);
-            if (x < ha) p += step;
+        for (uint32_t j = 0; j < kQStage / 64; j++) {
+            const uint32_t k = j * 64 + lane;
+            if (k < cnt) st[k] = hd[as + ia + k];
         }
-        const uint32_t pc = p < 64 ? p : 63;
-        const uint32_t hp = __shfl(hb, (int)pc, 64);
-        const E ep = __shfl(eb, (int)pc, 64);
-        if (va && p < 64 && hp == ha) {
-            uint32_t dd = e_dist<DB>(ea) + e_dist<DB>(ep);
-            if (dd <= best) {
-                uint64_t c = sat_mul(a.lab_cnt[as + ia + lane], a.lab_cnt[bs + ib + pc]);
-                sum = (dd < best) ? c : sat_add(sum, c);
-                best = dd;
+        if (lane == 0 && ia + cnt < na) nxt = hd[as + ia + cnt];
+        wave_lds_sync();
+        // staged hubs are [first, hub_hi): up to the next stage's first hub
+        const uint32_t hub_hi = (ia + cnt < na) ? e_hub<DB>((E)__shfl(nxt, 0, 64))
+                                                : e_hub<DB>(st[cnt - 1]) + 1;
+        bool more = true;
+        while (more && ib < nb) {
+            E eb[kQTiles];
+#pragma unroll
+            for (int j = 0; j < kQTiles; j++) {
+                const uint64_t i = ib + (uint64_t)j * 64 + lane;
+                eb[j] = i < nb ? hd[bs + i] : (E)~(E)0;
             }
+            uint32_t pos[kQTiles];
+            bool in[kQTiles];
+            uint32_t n_in = 0;
+#pragma unroll
+            for (int j = 0; j < kQTiles; j++) {
+                const uint64_t i = ib + (uint64_t)j * 64 + lane;
+                in[j] = i < nb && e_hub<DB>(eb[j]) < hub_hi;
+                n_in += (uint32_t)__popcll(__ballot(in[j]));
+                pos[j] = 0;
+            }
+            // lower bound of each streamed hub among the staged hubs; the
+            // searches of a lane's tiles interleave
+            for (uint32_t step = kQStage / 2; step > 0; step >>= 1) {
+#pragma unroll
+                for (int j = 0; j < kQTiles; j++) {
+                    const uint32_t c = pos[j] + step;
+                    if (in[j] && c <= cnt && e_hub<DB>(st[c - 1]) < e_hub<DB>(eb[j])) pos[j] = c;
+                }
+            }
+            uint32_t dd[kQTiles];
+            uint32_t gmin = best;
+#pragma unroll
+            for (int j = 0; j < kQTiles; j++) {
+                dd[j] = 0xFFFFFFFFu;
+                if (in[j] && pos[j] < cnt && e_hub<DB>(st[pos[j]]) == e_hub<DB>(eb[j]))
+                    dd[j] = e_dist<DB>(st[pos[j]]) + e_dist<DB>(eb[j]);
+                gmin = dd[j] < gmin ? dd[j] : gmin;
+            }
+            // counts of this lane's matches at its least distance, loaded
+            // together
+            if (gmin != 0xFFFFFFFFu && gmin <= best) {
+                uint64_t cs[kQTiles], ct[kQTiles];
+#pragma unroll
+                for (int j = 0; j < kQTiles; j++) {
+                    cs[j] = 0;
+                    ct[j] = 0;
+                    if (dd[j] == gmin) {
+                        cs[j] = a.lab_cnt[as + ia + pos[j]];
+                        ct[j] = a.lab_cnt[bs + ib + (uint64_t)j * 64 + lane];
+                    }
+                }
+                if (gmin < best) {
+                    sum = 0;
+                    best = gmin;
+                }
+#pragma unroll
+                for (int j = 0; j < kQTiles; j++)
+                    if (dd[j] == gmin) sum = sat_add(sum, sat_mul(cs[j], ct[j]));
+            }
+            // L(t) is sorted: the in-range entries are a prefix
+            ib += n_in;
+            more = n_in == (uint32_t)(kQTiles * 64);
         }
-        const uint64_t la = (na - ia < 64) ? na - ia - 1 : 63;
-        const uint64_t lb = (nb - ib < 64) ? nb - ib - 1 : 63;
-        const uint32_t lasta = __shfl(ha, (int)la, 64);
-        const uint32_t lastb = __shfl(hb, (int)lb, 64);
-        if (lasta <= lastb) ia += 64;
-        if (lastb <= lasta) ib += 64;
+        ia += cnt;
+        wave_lds_sync();  // the stage is rewritten next
     }
     // wave reduction: least distance, then the saturating sum at it
     uint32_t mn = best;
