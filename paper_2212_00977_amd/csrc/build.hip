@@ -336,6 +336,24 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t h, int bits) {
     return (h * 0x9E3779B1u) >> (32 - bits);
 }
 
+// first position p in [0, n) with hub(a[p]) >= key (packed entries sorted by
+// hub): exponential steps from 0, then a binary search
+template <int DB>
+__device__ __forceinline__ uint64_t gallop_hub(const typename Ent<DB>::T *a, uint64_t n, uint32_t key) {
+    uint64_t lo = 0, step = 1, end = n;
+    while (lo < n) {
+        const uint64_t p = lo + step - 1;
+        if (p >= n) break;
+        if (e_hub<DB>(a[p]) >= key) {
+            end = p;
+            break;
+        }
+        lo = p + 1;
+        step <<= 1;
+    }
+    return lo + lower_bound_hub<DB>(a + lo, end - lo, key);
+}
+
 // first position p in [c, n) with a[p] >= key, where every position below c
 // holds a smaller value: exponential steps from c, then a binary search
 __device__ __forceinline__ uint32_t gallop_u32(const uint32_t *a, uint32_t c, uint32_t n, uint32_t key) {
@@ -392,7 +410,11 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
     __shared__ uint32_t lhub[kULimit];
     __shared__ unsigned long long lcnt[kULimit];
     __shared__ uint8_t lkeep[kULimit];   // 0 pruned, 1 kept, 2 needs the tail check
-    __shared__ uint16_t tlist[kULimit];  // candidates that need the tail check
+    // candidates that need the tail check (probe phase); during the pull the
+    // same bytes hold the chunk's slice of u's unstaged label
+    __shared__ __align__(8) uint16_t tlist[kULimit];
+    constexpr uint32_t kWin = kULimit * sizeof(uint16_t) / sizeof(E);
+    E *win = reinterpret_cast<E *>(tlist);
     __shared__ uint64_t nb_start[RB];
     __shared__ uint32_t nb_off[RB];
     __shared__ uint32_t red32[RW];
@@ -455,9 +477,18 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
     look.x = (nst < nsp) ? e_hub<DB>(hd[l0 + s0 + nst]) : 0xFFFFFFFFu;
     __syncthreads();
     const LT *lrow_t = reinterpret_cast<const LT *>(lrow);
-    // is hub w already held by u (at a distance < d)?
+    // is hub w of the current chunk already held by u (at a distance < d)?
+    // Hubs past the staged part are searched in the chunk's slice of the
+    // rest of u's label: [wbase, wbase + wlen) of look.tail, copied to the
+    // LDS window when it fits
+    uint64_t tcur = 0, tend = 0, wbase = 0, wlen = 0;
+    bool inwin = false;
     auto held = [&](uint32_t w) -> bool {
-        return (w < land_end) ? lrow_t[w - base] != kInfL : look(w) != kNone;
+        if (w < land_end) return lrow_t[w - base] != kInfL;
+        if (w < look.x) return look(w) != kNone;
+        const E *t = inwin ? win : look.tail + wbase;
+        const uint64_t p = lower_bound_hub<DB>(t, wlen, w);
+        return p < wlen && e_hub<DB>(t[p]) == w;
     };
     // this lane's 16 landmarks of u, and whether any of them is within d-2
     // (a landmark farther from u cannot prove d_u + d_w < d since d_w >= 1)
@@ -537,6 +568,20 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
             ckey[i] = kEmpty32;
             cval[i] = 0;
             cwrap[i] = 0;
+        }
+        // u's unstaged entries with hubs in [lo, hi): from the tail cursor
+        // (first entry with hub >= lo) to the first with hub >= hi
+        wbase = tcur;
+        wlen = 0;
+        inwin = false;
+        tend = tcur;
+        if (look.ntail > tcur && hi > look.x) {
+            tend = tcur + gallop_hub<DB>(look.tail + tcur, look.ntail - tcur, hi);
+            wlen = tend - tcur;
+            if (wlen <= kWin) {
+                for (uint32_t i = tid; i < (uint32_t)wlen; i += RB) win[i] = look.tail[tcur + i];
+                inwin = true;
+            }
         }
         if (tid == 0) {
             s_nuniq = 0;
@@ -625,6 +670,7 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
             continue;
         }
         // the chunk is complete: advance the cursors
+        tcur = tend;
         if (one_group) {
             my_c = my_e;
         } else {
