@@ -131,6 +131,9 @@ def bench_served(args, dev, log):
     del off_d, adj_d
     spc.release_cached_memory()
     torch.cuda.empty_cache()
+    ts, tt = inputs.queries(g.n, 1_000_000, seed=3)
+    qcfg = ix.tune_queries(ts, tt, stream=stream)
+    log(f"query autotuner: configuration {qcfg} {spc.query_configs()[qcfg]}")
 
     mean_batch = 65536 / np.log(65537) - 0.5
     srv_kw = dict(io_budget_bytes=1 << 30, streams=4, max_batch=1 << 18)
@@ -169,6 +172,7 @@ def bench_served(args, dev, log):
                       "requests_per_level": args.serve_requests, "parallelism": "single-gpu"},
            "p50_ms": one["p50_ms"], "p99_ms": one["p99_ms"],
            "build_ms": build_ms, "build_entries_per_s": st["entries"] / (build_ms * 1e-3),
+           "query_config": dict(zip(("stage", "tiles"), spc.query_configs()[qcfg])),
            "index_bytes": st["index_bytes"], "peak_build_bytes": st["peak_build_bytes"],
            "saturation": sat, "levels": levels}
     print(json.dumps(out), flush=True)
@@ -382,12 +386,16 @@ def main():
     flg_o = torch.empty(args.queries, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # a separate sample for the query autotuner (untimed)
+    ts_np, tt_np = inputs.queries(g.n, min(args.queries, 1_000_000), seed=3)
     torch.cuda.synchronize()
+    qcfg = [None]
 
     def step(keep=False):
         t0 = time.perf_counter()
         ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
         t1 = time.perf_counter()
+        ix.set_query_config(qcfg[0])
         ev0.record(stream)
         ix.query(s_d, t_d, stream=stream, out=(dist_o, cnt_o, flg_o))
         ev1.record(stream)
@@ -402,6 +410,12 @@ def main():
         return dict(build_ms=(t1 - t0) * 1e3, query_ms=ev0.elapsed_time(ev1),
                     step_ms=(t2 - t0) * 1e3, stats=st, index=ix)
 
+    # query autotuner, before any timed work: one build, every launch
+    # configuration timed on a separate sample
+    ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
+    qcfg[0] = ix.tune_queries(ts_np, tt_np, stream=stream)
+    ix.free()
+    log(f"query autotuner: configuration {qcfg[0]} {spc.query_configs()[qcfg[0]]}")
     for i in range(args.warmup):
         r = step()
         log(f"warmup {i}: build {r['build_ms']:.1f} ms, query {r['query_ms']:.1f} ms, "
@@ -450,6 +464,7 @@ def main():
                    "parallelism": "single-gpu"},
         "build_ms": build_ms,
         "query_ms": query_ms,
+        "query_config": dict(zip(("stage", "tiles"), spc.query_configs()[qcfg[0]])),
         "queries_per_s": args.queries / (query_ms * 1e-3),
         "build_breakdown_ms": {"order": st["ms_order"], "rounds": st["ms_rounds"],
                                "finalize": st["ms_finalize"], "device_total": st["ms_total"],

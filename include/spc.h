@@ -107,6 +107,8 @@ typedef struct {
     double ms_round_kernel;   /* time inside the fused round kernel only */
     uint64_t alg_bytes_round_kernel; /* algorithmic bytes of the fused round kernel */
     uint64_t round_kernel_launches;  /* dispatches of the fused round kernel */
+    uint32_t query_config;           /* query launch configuration in use */
+    uint32_t reserved;
 } spc_stats;
 
 /* Build the index of one graph (Alg. 2 rounds until a round adds no entry).
@@ -179,6 +181,31 @@ spc_status spc_graph_entries(const spc_index *ix, uint32_t graph_id, uint32_t *n
 spc_status spc_export_labels(const spc_index *ix, uint32_t graph_id, uint64_t *off,
                              uint32_t *hub, uint16_t *dist, uint64_t *count, uint32_t *order,
                              int32_t on_device, void *stream);
+
+/* Query launch configurations.  The query kernel stages slices of L(s) in
+ * LDS and streams L(t) past them; a configuration fixes the slice length
+ * (stage, entries) and the L(t) tiles of 64 requested per round of loads
+ * (tiles).  spc_query_config_count() configurations exist, numbered from 0
+ * (the default of a new index).  spc_query_config_info returns
+ * SPC_ERR_INVALID_ARG for a number out of range; either output may be NULL. */
+uint32_t spc_query_config_count(void);
+spc_status spc_query_config_info(uint32_t cfg, uint32_t *stage, uint32_t *tiles);
+
+/* Autotuner ("Query Evaluation in Parallel": queries are independent, so
+ * any launch shape gives the same answers): run the nq sample queries s, t
+ * (device pointers, ids of graph graph_id) once per configuration, twice
+ * each, timed with events on `stream`; check that every configuration's
+ * answers equal configuration 0's (SPC_ERR_DEVICE if not); keep the fastest
+ * as the index's configuration and return its number in *cfg_out (may be
+ * NULL).  Allocates scratch device memory for the outputs, synchronises
+ * `stream`, and must not run concurrently with queries on the same index. */
+spc_status spc_tune_queries(spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                            uint64_t nq, void *stream, uint32_t *cfg_out);
+
+/* Set the index's query configuration (e.g. one tuned on another index of
+ * the same workload).  SPC_ERR_INVALID_ARG for ix NULL or cfg out of range;
+ * must not run concurrently with queries on the same index. */
+spc_status spc_set_query_config(spc_index *ix, uint32_t cfg);
 
 /* Static string for a status code. */
 const char *spc_status_string(spc_status s);

@@ -91,6 +91,24 @@ spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
     out->ms_round_kernel = ix->ms_round_kernel;
     out->alg_bytes_round_kernel = ix->alg_bytes_round_kernel;
     out->round_kernel_launches = ix->round_kernel_launches;
+    out->query_config = ix->query_cfg;
+    return SPC_OK;
+}
+
+uint32_t spc_query_config_count(void) { return spc::query_cfg_count(); }
+
+spc_status spc_query_config_info(uint32_t cfg, uint32_t *stage, uint32_t *tiles) {
+    return spc::query_cfg_info(cfg, stage, tiles);
+}
+
+spc_status spc_tune_queries(spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                            uint64_t nq, void *stream, uint32_t *cfg_out) {
+    return spc::tune_queries_impl(ix, graph_id, s, t, nq, static_cast<hipStream_t>(stream), cfg_out);
+}
+
+spc_status spc_set_query_config(spc_index *ix, uint32_t cfg) {
+    if (!ix || cfg >= spc::query_cfg_count()) return SPC_ERR_INVALID_ARG;
+    ix->query_cfg = cfg;
     return SPC_OK;
 }
 

@@ -34,10 +34,9 @@ struct QueryArgs {
     uint8_t *flags_out;
 };
 
-constexpr uint32_t kQStage = 512;  // L(s) entries staged per wave
-constexpr int kQTiles = 4;         // L(t) tiles of 64 requested together
-
-template <int DB>
+// kQStage: L(s) entries staged per wave; kQTiles: L(t) tiles of 64
+// requested together.  The pair is a launch configuration (see kQueryCfg).
+template <int DB, uint32_t kQStage, int kQTiles>
 __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     using E = typename Ent<DB>::T;
     using DT = typename std::conditional<DB == 8, uint8_t, uint16_t>::type;
@@ -196,12 +195,140 @@ __global__ void k_export_order(const uint32_t *order, uint32_t vbase, uint32_t n
 
 inline uint32_t grid1(uint64_t items) { return (uint32_t)((items + kBlock - 1) / kBlock); }
 
+// Query launch configurations (staged L(s) entries, L(t) tiles per round of
+// loads); spc_tune_queries picks one per index by timing them all.
+struct QueryCfg {
+    uint32_t stage, tiles;
+};
+constexpr QueryCfg kQueryCfg[] = {{512, 2}, {512, 1}, {512, 4}, {256, 1}, {256, 2},
+                                  {1024, 1}, {1024, 2}, {2048, 1}};
+constexpr uint32_t kQueryCfgs = sizeof(kQueryCfg) / sizeof(kQueryCfg[0]);
+
+template <int DB>
+void launch_cfg(uint32_t cfg, dim3 g, hipStream_t st, const QueryArgs &c) {
+    switch (cfg) {
+        case 1: hipLaunchKernelGGL((k_query<DB, 512, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 2: hipLaunchKernelGGL((k_query<DB, 512, 4>), g, dim3(kBlock), 0, st, c); break;
+        case 3: hipLaunchKernelGGL((k_query<DB, 256, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 4: hipLaunchKernelGGL((k_query<DB, 256, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 5: hipLaunchKernelGGL((k_query<DB, 1024, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 6: hipLaunchKernelGGL((k_query<DB, 1024, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 7: hipLaunchKernelGGL((k_query<DB, 2048, 1>), g, dim3(kBlock), 0, st, c); break;
+        default: hipLaunchKernelGGL((k_query<DB, 512, 2>), g, dim3(kBlock), 0, st, c); break;
+    }
+}
+
+spc_status launch_query(uint32_t dist_bits, uint32_t cfg, const QueryArgs &c, hipStream_t st) {
+    const dim3 g((uint32_t)((c.nq + kWaves - 1) / kWaves));
+    if (dist_bits == 8)
+        launch_cfg<8>(cfg, g, st, c);
+    else
+        launch_cfg<16>(cfg, g, st, c);
+    SPC_LAUNCHED();
+    return SPC_OK;
+}
+
+}  // namespace
+
+namespace {
+
+__global__ void k_same(const uint8_t *a, const uint8_t *b, uint64_t n, unsigned int *diff) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        if (a[i] != b[i]) atomicOr(diff, 1u);
+}
+
+spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                     uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
+                     uint32_t cfg, hipStream_t st);
+
 }  // namespace
 
 spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                       uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
                       hipStream_t st) {
     if (!ix) return SPC_ERR_INVALID_ARG;
+    return query_run(ix, graph_id, s, t, nq, dist_out, count_out, flags_out, ix->query_cfg, st);
+}
+
+uint32_t query_cfg_count() { return kQueryCfgs; }
+
+spc_status query_cfg_info(uint32_t cfg, uint32_t *stage, uint32_t *tiles) {
+    if (cfg >= kQueryCfgs) return SPC_ERR_INVALID_ARG;
+    if (stage) *stage = kQueryCfg[cfg].stage;
+    if (tiles) *tiles = kQueryCfg[cfg].tiles;
+    return SPC_OK;
+}
+
+spc_status tune_queries_impl(spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                             uint64_t nq, hipStream_t st, uint32_t *cfg_out) {
+    if (!ix || graph_id >= ix->gn.size() || !s || !t || nq == 0) return SPC_ERR_INVALID_ARG;
+    const size_t dsz = ix->dist_bits == 8 ? 1 : 2;
+    // one output set per side of the comparison, in one block:
+    // dist | count | flags, reference then candidate
+    const uint64_t per = (nq * (dsz + 8 + 1) + 255) & ~uint64_t(255);
+    Arena tmp(0, st);
+    uint8_t *buf = nullptr;
+    unsigned int *diff = nullptr;
+    SPC_TRY(tmp.alloc(&buf, 2 * per + 16));
+    SPC_TRY(tmp.alloc(&diff, 1));
+    auto outs = [&](int side, void **d, uint64_t **c, uint8_t **f) {
+        uint8_t *b = buf + side * per;
+        *c = reinterpret_cast<uint64_t *>(b);  // counts first: 8-byte aligned
+        *d = b + nq * 8;
+        *f = b + nq * (8 + dsz);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SPC_HIP(hipEventCreate(&e0));
+    SPC_HIP(hipEventCreate(&e1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    float best_ms = 0;
+    uint32_t best = ix->query_cfg;
+    for (uint32_t cfg = 0; cfg < kQueryCfgs; cfg++) {
+        void *d;
+        uint64_t *c;
+        uint8_t *f;
+        outs(cfg == 0 ? 0 : 1, &d, &c, &f);
+        float ms = 0;
+        for (int rep = 0; rep < 2; rep++) {  // the first run warms caches
+            SPC_HIP(hipEventRecord(e0, st));
+            SPC_TRY(query_run(ix, graph_id, s, t, nq, d, c, f, cfg, st));
+            SPC_HIP(hipEventRecord(e1, st));
+            SPC_HIP(hipEventSynchronize(e1));
+            SPC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (cfg > 0) {  // every configuration must give the same answers
+            SPC_HIP(hipMemsetAsync(diff, 0, sizeof(unsigned int), st));
+            const uint64_t used = nq * (dsz + 8 + 1);  // the padding is not compared
+            hipLaunchKernelGGL(k_same, dim3(grid1(used) < 4096 ? grid1(used) : 4096), dim3(kBlock), 0, st,
+                               buf, buf + per, used, diff);
+            SPC_LAUNCHED();
+            unsigned int h = 0;
+            SPC_HIP(hipMemcpyAsync(&h, diff, sizeof(h), hipMemcpyDeviceToHost, st));
+            SPC_HIP(hipStreamSynchronize(st));
+            if (h) return SPC_ERR_DEVICE;
+        }
+        if (cfg == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = cfg;
+        }
+    }
+    ix->query_cfg = best;
+    if (cfg_out) *cfg_out = best;
+    return SPC_OK;
+}
+
+namespace {
+
+spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                     uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
+                     uint32_t cfg, hipStream_t st) {
     if (graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
     if (nq == 0) return SPC_OK;
     if (!s || !t || !dist_out || !count_out) return SPC_ERR_INVALID_ARG;
@@ -232,15 +359,12 @@ spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
         c.dist_out = static_cast<char *>(dist_out) + q0 * dsz;
         c.count_out = count_out + q0;
         c.flags_out = flags_out ? flags_out + q0 : nullptr;
-        const uint32_t blocks = (uint32_t)((nc + kWaves - 1) / kWaves);
-        if (ix->dist_bits == 8)
-            hipLaunchKernelGGL(k_query<8>, dim3(blocks), dim3(kBlock), 0, st, c);
-        else
-            hipLaunchKernelGGL(k_query<16>, dim3(blocks), dim3(kBlock), 0, st, c);
-        SPC_LAUNCHED();
+        SPC_TRY(launch_query(ix->dist_bits, cfg, c, st));
     }
     return SPC_OK;
 }
+
+}  // namespace
 
 spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, uint32_t *hub,
                        uint16_t *dist, uint64_t *count, uint32_t *order, int32_t on_device,

@@ -323,6 +323,7 @@ struct spc_index {
     double ms_order = 0, ms_rounds = 0, ms_finalize = 0, ms_total = 0, ms_round_kernel = 0;
     uint64_t alg_bytes_round_kernel = 0;
     uint64_t round_kernel_launches = 0;
+    uint32_t query_cfg = 0;  // query launch configuration (query.hip)
 };
 
 namespace spc {
@@ -333,6 +334,10 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *opt
 spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                       uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
                       hipStream_t st);
+spc_status tune_queries_impl(spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                             uint64_t nq, hipStream_t st, uint32_t *cfg_out);
+uint32_t query_cfg_count();
+spc_status query_cfg_info(uint32_t cfg, uint32_t *stage, uint32_t *tiles);
 spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, uint32_t *hub,
                        uint16_t *dist, uint64_t *count, uint32_t *order, int32_t on_device,
                        hipStream_t st);

@@ -21,7 +21,8 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_free",
            "spc_index_stats", "spc_round_stats", "spc_round_profile", "spc_graph_entries", "spc_export_labels",
-           "spc_status_string", "spc_release_cached_memory"]
+           "spc_status_string", "spc_release_cached_memory", "spc_query_config_count",
+           "spc_query_config_info", "spc_tune_queries", "spc_set_query_config"]
 
 
 def build_library(verbose: bool = False) -> str:
@@ -47,7 +48,8 @@ class SpcStats(C.Structure):
                 ("peak_build_bytes", C.c_uint64), ("ms_order", C.c_double),
                 ("ms_rounds", C.c_double), ("ms_finalize", C.c_double), ("ms_total", C.c_double),
                 ("ms_round_kernel", C.c_double), ("alg_bytes_round_kernel", C.c_uint64),
-                ("round_kernel_launches", C.c_uint64)]
+                ("round_kernel_launches", C.c_uint64), ("query_config", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class SpcGraph(C.Structure):
@@ -96,6 +98,14 @@ def load(path: str | None = None):
     L.spc_graph_entries.restype = C.c_int
     L.spc_export_labels.argtypes = [vp, u32, vp, vp, vp, vp, vp, i32, vp]
     L.spc_export_labels.restype = C.c_int
+    L.spc_query_config_count.argtypes = []
+    L.spc_query_config_count.restype = u32
+    L.spc_query_config_info.argtypes = [u32, C.POINTER(u32), C.POINTER(u32)]
+    L.spc_query_config_info.restype = C.c_int
+    L.spc_tune_queries.argtypes = [vp, u32, vp, vp, u64, vp, C.POINTER(u32)]
+    L.spc_tune_queries.restype = C.c_int
+    L.spc_set_query_config.argtypes = [vp, u32]
+    L.spc_set_query_config.restype = C.c_int
     L.spc_status_string.argtypes = [C.c_int]
     L.spc_status_string.restype = C.c_char_p
     _lib = L

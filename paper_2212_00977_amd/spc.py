@@ -188,6 +188,28 @@ class Index:
         self._keep = (s_t, t_t)  # inputs stay alive until the next call
         return dist[:nq], cnt[:nq], (flags[:nq] if flags is not None else None)
 
+    def tune_queries(self, s, t, graph_id: int = 0, stream=None) -> int:
+        """Autotune the query launch configuration on the sample pairs (s, t):
+        every configuration is timed (and checked to agree); the fastest is
+        kept for this index.  Returns its number."""
+        torch = _torch()
+        s_t = _dev(s, np.uint32, torch.int32, self.device)
+        t_t = _dev(t, np.uint32, torch.int32, self.device)
+        if int(s_t.shape[0]) != int(t_t.shape[0]):
+            raise ValueError("s and t differ in length")
+        cfg = C.c_uint32()
+        _check(native.load().spc_tune_queries(self.handle, graph_id, s_t.data_ptr(), t_t.data_ptr(),
+                                              int(s_t.shape[0]), _stream_handle(stream),
+                                              C.byref(cfg)), "spc_tune_queries")
+        return cfg.value
+
+    def set_query_config(self, cfg: int):
+        _check(native.load().spc_set_query_config(self.handle, int(cfg)), "spc_set_query_config")
+
+    @property
+    def query_config(self) -> int:
+        return int(self.stats()["query_config"])
+
     @property
     def dist_bits(self) -> int:
         if self._stats is None:
@@ -261,6 +283,17 @@ def build_index_batch(graphs, opts: BuildOptions | None = None, device=None, str
                                              C.byref(h))
     _check(rc, "spc_build_index_batch")
     return Index(h, device)
+
+
+def query_configs() -> list:
+    """(stage, tiles) of every query launch configuration, by number."""
+    lib = native.load()
+    out = []
+    for i in range(lib.spc_query_config_count()):
+        st, tl = C.c_uint32(), C.c_uint32()
+        _check(lib.spc_query_config_info(i, C.byref(st), C.byref(tl)), "spc_query_config_info")
+        out.append((st.value, tl.value))
+    return out
 
 
 def release_cached_memory():

@@ -54,6 +54,8 @@ def test_null_arguments_rejected_on_host(lib):
     assert lib.spc_round_stats(None, 1, None, None, None, None) == 1
     assert lib.spc_round_profile(None, 1, None, None, None, None, None) == 1
     assert lib.spc_export_labels(None, 0, None, None, None, None, None, 0, None) == 1
+    assert lib.spc_tune_queries(None, 0, None, None, 1, None, None) == 1
+    assert lib.spc_set_query_config(None, 0) == 1
     lib.spc_free(None)  # no-op
     assert out.value is None
 
@@ -74,3 +76,16 @@ def test_bad_options_rejected_on_host(lib):
     o.reserved = 7
     assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
     assert out.value is None
+
+
+def test_query_configs_listed(lib):
+    n = lib.spc_query_config_count()
+    assert n >= 2
+    seen = set()
+    for i in range(n):
+        st, tl = C.c_uint32(), C.c_uint32()
+        assert lib.spc_query_config_info(i, C.byref(st), C.byref(tl)) == 0
+        assert st.value >= 64 and st.value % 64 == 0 and tl.value >= 1
+        seen.add((st.value, tl.value))
+    assert len(seen) == n  # no duplicate configurations
+    assert lib.spc_query_config_info(n, None, None) == 1
