@@ -1627,14 +1627,19 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     uint64_t new_entries = B.entries + kept;
     if (B.lab_cap2 < new_entries) {
         // the older buffer (distances <= d-2) is dead once the round kernel
-        // has run: free it first, then take the merged size, plus an eighth
-        // when the labels grew by less than 1/16 this round (the two
-        // buffers alternate, so slowly growing labels reuse them for many
-        // rounds; a fast-growing index gets no slack)
+        // has run: free it first (a large one straight to the runtime: it is
+        // outgrown), then take the merged size, plus an eighth (at most 2^28
+        // entries) when the labels grew by less than 1/16 this round (the
+        // two buffers alternate, so slowly growing labels reuse them for
+        // many rounds; a fast-growing index gets no slack)
         E *p2 = static_cast<E *>(B.lab_hd2);
-        B.arena.release(p2);
+        if (B.arena.size_of(p2) >= (256ull << 20))
+            B.arena.release_to_device(p2);
+        else
+            B.arena.release(p2);
         B.lab_cap2 = 0;
-        uint64_t cap = new_entries + (kept < B.entries / 16 ? new_entries / 8 : 0);
+        const uint64_t slack = std::min<uint64_t>(new_entries / 8, 1ull << 28);
+        uint64_t cap = new_entries + (kept < B.entries / 16 ? slack : 0);
         if (B.arena.alloc(&p2, cap) != SPC_OK) {
             cap = new_entries;
             SPC_TRY(B.arena.alloc(&p2, cap));

@@ -250,6 +250,25 @@ class Arena {
         }
         p = nullptr;
     }
+    // give a block straight back to the runtime (large blocks that later
+    // requests will not fit)
+    template <typename T>
+    void release_to_device(T *&p) {
+        if (!p) return;
+        auto it = sizes_.find((void *)p);
+        if (it != sizes_.end()) {
+            (void)hipStreamSynchronize(st_);
+            used_ -= it->second;
+            (void)hipFree(it->first);
+            sizes_.erase(it);
+        }
+        p = nullptr;
+    }
+    template <typename T>
+    uint64_t size_of(const T *p) const {
+        auto it = sizes_.find((void *)p);
+        return it == sizes_.end() ? 0 : it->second;
+    }
     // hand an allocation to the index: the arena stops tracking it
     template <typename T>
     uint64_t detach(T *p) {
