@@ -288,13 +288,11 @@ __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
 //      u's table.  A hub with d_u(h) + d_w(h) < d prunes; equality keeps;
 //   5. append the survivors, in hub order, to u's slot of the temp buffer.
 // ---------------------------------------------------------------------------
-// LDS budget of the round kernel (about 39 KB with the defaults: four
-// workgroups per CU); measured faster than staging u's L_{<=d-2} part too
+// LDS budget of the round kernel (about 40 KB with the defaults: four
+// workgroups per CU).  u's L_{<=d-2} part is read from HBM by the probes
+// that stream u's side (staging it too measured slower).
 #ifndef SPC_LBITS
 #define SPC_LBITS 12
-#endif
-#ifndef SPC_STAGE_PREV
-#define SPC_STAGE_PREV 0
 #endif
 constexpr int kLBits = SPC_LBITS;
 constexpr int kLCap = 1 << kLBits;   // L(u) hash slots
@@ -402,7 +400,6 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
     using LT = typename Land<DB>::T;
     using LW = typename Land<DB>::W;
     __shared__ E ltab[kLCap];
-    __shared__ E sarr[SPC_STAGE_PREV ? kLStage : 1];  // u's entries of distance <= d-2 past the landmarks, by hub
     __shared__ LW lrow[kLand / 4];
     __shared__ uint32_t ckey[kCCap];
     __shared__ unsigned long long cval[kCCap];
@@ -461,14 +458,11 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
     // the previous round's merged label), for probes that stream u's side
     const E *pu = nullptr;
     uint64_t npu = 0;
-    uint32_t nstu = 0;
     if (d >= 3) {
         const uint64_t q0 = a.prev_off[u];
         const uint64_t qs = a.lc_prev[u];
         pu = static_cast<const E *>(a.prev_hd) + q0 + qs;
         npu = a.prev_off[u + 1] - q0 - qs;
-        nstu = SPC_STAGE_PREV ? (npu < (uint64_t)kLStage ? (uint32_t)npu : (uint32_t)kLStage) : 0;
-        for (uint32_t i = tid; i < nstu; i += RB) sarr[i] = pu[i];
     }
     LabelLookup<DB> look;
     look.tab = ltab;
@@ -765,12 +759,7 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
             const E *pw = static_cast<const E *>(a.prev_hd) + q0;
             const uint64_t nw = np - p0;
             uint64_t cu = 0;
-            if (gvalid) {
-                if (nstu == npu || (nstu > 0 && e_hub<DB>(sarr[nstu - 1]) >= w))
-                    cu = lower_bound_hub<DB>(sarr, nstu, w);
-                else
-                    cu = nstu + lower_bound_hub<DB>(pu + nstu, npu - nstu, w);
-            }
+            if (gvalid) cu = lower_bound_hub<DB>(pu, npu, w);
             uint32_t steps = 1;
             while ((1ull << steps) <= nw) steps++;
             const bool useu = cu * steps < nw;
@@ -787,7 +776,7 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
                 const uint64_t j = (uint64_t)it * 16 + gl;
                 if (act && j < len) {
                     if (useu) {
-                        const E e = (j < nstu) ? sarr[j] : pu[j];
+                        const E e = pu[j];
                         const uint32_t h = e_hub<DB>(e);
                         const uint64_t q = p0 + lower_bound_hub<DB>(pw + p0, nw, h);
                         h2 = q < np && e_hub<DB>(pw[q]) == h && e_dist<DB>(e) + e_dist<DB>(pw[q]) < d;
