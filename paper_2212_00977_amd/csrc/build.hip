@@ -297,7 +297,10 @@ __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
 constexpr int kLBits = SPC_LBITS;
 constexpr int kLCap = 1 << kLBits;   // L(u) hash slots
 constexpr int kLStage = kLCap / 2;   // staged entries (load <= 1/2)
-constexpr int kCBits = 10;
+#ifndef SPC_CBITS
+#define SPC_CBITS 10
+#endif
+constexpr int kCBits = SPC_CBITS;  // >= 9: a candidate slot per thread at least
 constexpr int kCCap = 1 << kCBits;   // candidate hash slots
 constexpr int kULimit = kCCap / 2;   // distinct candidates per chunk
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -305,6 +308,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 #define SPC_ROUND_BLOCK 256
 #endif
 constexpr int kRoundBlock = SPC_ROUND_BLOCK;  // threads per puller workgroup
+static_assert((1 << (SPC_CBITS - 1)) >= SPC_ROUND_BLOCK, "candidate limit below one per thread");
 
 struct RoundArgs {
     uint32_t d, u_lo, u_hi;

@@ -25,19 +25,29 @@ EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_f
            "spc_query_config_info", "spc_tune_queries", "spc_set_query_config"]
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compile every HIP source into libspc.so (always recompiles)."""
+# A test build with tiny on-chip tables (8-bit hash of 128 slots for the
+# puller's label, 256 distinct candidates per chunk): small graphs then take
+# the paths that only large labels take in the default build (unstaged
+# label parts, chunk overflow and narrowing, many chunks per puller).
+SMALL_TABLES = ["-DSPC_LBITS=7", "-DSPC_CBITS=9"]
+SMALL_TABLES_PATH = os.path.join(LIBDIR, "libspc_smalltab.so")
+
+
+def build_library(verbose: bool = False, small_tables: bool = False) -> str:
+    """Compile every HIP source into libspc.so (always recompiles); with
+    small_tables, the test build libspc_smalltab.so."""
     os.makedirs(LIBDIR, exist_ok=True)
-    tmp = LIBPATH + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-I", INCLUDE, "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+    out = SMALL_TABLES_PATH if small_tables else LIBPATH
+    tmp = out + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, *(SMALL_TABLES if small_tables else []), "-I", INCLUDE,
+           "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
     if verbose:
         print(r.stderr)
-    os.replace(tmp, LIBPATH)
-    return LIBPATH
+    os.replace(tmp, out)
+    return out
 
 
 class SpcStats(C.Structure):
