@@ -818,7 +818,7 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
         }
         __syncthreads();
 
-        // 5. survivors: compact, then each goes to its rank by hub
+        // 5. survivors: compact, sort by hub, write out
         uint32_t kk[PER], hh[PER], nk = 0;
         unsigned long long cc[PER];
 #pragma unroll
@@ -839,13 +839,35 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
                 pos++;
             }
         __syncthreads();
+        // sort them by hub: a bitonic network over (hub, list index) keys in
+        // the candidate table's count array (unused until the next chunk),
+        // then write them out in order (coalesced)
+        uint32_t P = 1;
+        while (P < S) P <<= 1;
+        unsigned long long *sk = cval;
+        for (uint32_t i = tid; i < P; i += RB)
+            sk[i] = i < S ? ((unsigned long long)lhub[i] << 32) | i : ~0ull;
+        __syncthreads();
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = tid; i < P; i += RB) {
+                    const uint32_t l = i ^ j;
+                    if (l > i) {
+                        const unsigned long long x = sk[i], y = sk[l];
+                        if ((x > y) == ((i & k) == 0)) {
+                            sk[i] = y;
+                            sk[l] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
         const uint64_t obase = tbase + nout;
         for (uint32_t k = tid; k < S; k += RB) {
-            const uint32_t h = lhub[k];
-            uint32_t r = 0;
-            for (uint32_t j = 0; j < S; j++) r += lhub[j] < h;
-            a.tmp_hub[obase + r] = h;
-            a.tmp_cnt[obase + r] = lcnt[k];
+            const uint32_t idx = (uint32_t)sk[k];
+            a.tmp_hub[obase + k] = lhub[idx];
+            a.tmp_cnt[obase + k] = lcnt[idx];
         }
         nout += S;
         st_raw += chunk_raw;
