@@ -222,18 +222,23 @@ struct Land<16> {
 };
 // true if some of the 4 packed landmark distances satisfies a + b < d; an
 // absent entry is the type max, so its sum is never below d (d <= max-1)
+// Is d_x + d_y < d for some landmark of the word (four distances each)?
+// SWAR: the even and the odd distances are summed in lanes twice as wide
+// (no carry between lanes), and each lane's (d - 1) - sum keeps its guard
+// bit exactly when sum < d.  d >= 1.
 __device__ __forceinline__ bool land_hit(uint32_t x, uint32_t y, uint32_t d) {
-    bool h = false;
-#pragma unroll
-    for (int i = 0; i < 4; i++) h |= ((x >> (8 * i)) & 0xFFu) + ((y >> (8 * i)) & 0xFFu) < d;
-    return h;
+    constexpr uint32_t m = 0x00FF00FFu, g = 0x80008000u;
+    const uint32_t dd = ((d - 1) * 0x00010001u) | g;
+    const uint32_t te = dd - ((x & m) + (y & m));
+    const uint32_t to = dd - (((x >> 8) & m) + ((y >> 8) & m));
+    return ((te | to) & g) != 0;
 }
 __device__ __forceinline__ bool land_hit(uint64_t x, uint64_t y, uint32_t d) {
-    bool h = false;
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-        h |= (uint32_t)((x >> (16 * i)) & 0xFFFFu) + (uint32_t)((y >> (16 * i)) & 0xFFFFu) < d;
-    return h;
+    constexpr uint64_t m = 0x0000FFFF0000FFFFull, g = 0x8000000080000000ull;
+    const uint64_t dd = ((uint64_t)(d - 1) * 0x0000000100000001ull) | g;
+    const uint64_t te = dd - ((x & m) + (y & m));
+    const uint64_t to = dd - (((x >> 16) & m) + ((y >> 16) & m));
+    return ((te | to) & g) != 0;
 }
 
 __device__ __forceinline__ uint32_t land_count_le(uint32_t x, uint32_t lim) {
