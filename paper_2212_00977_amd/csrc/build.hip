@@ -424,7 +424,7 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
     __shared__ uint64_t nb_start[RB];
     __shared__ uint32_t nb_off[RB];
     __shared__ uint32_t red32[RW];
-    __shared__ uint32_t s_nuniq, s_ovf;
+    __shared__ uint32_t s_nuniq, s_ovf, s_next;
     __shared__ unsigned long long s_tail, s_hdr, s_rowb;
 
     const E *hd = static_cast<const E *>(a.lab_hd);
@@ -747,43 +747,61 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
                 f[q] = (i < M && lkeep[i] == 2) ? 1 : 0;
                 nf += f[q];
             }
+            if (tid == 0) s_next = 0;
             uint32_t p = block_excl_scan<uint32_t, RW>(nf, red32, T);
 #pragma unroll
             for (int q = 0; q < PER; q++)
                 if (f[q]) tlist[p++] = (uint16_t)(PER * tid + q);
             __syncthreads();
         }
-        for (uint32_t t0 = wv * 4; t0 < T; t0 += RB / 16) {
-            const uint32_t ti = t0 + grp;
-            const bool gvalid = ti < T;
-            uint32_t i = 0, w = 0;
-            uint64_t q0 = 0, np = 0, p0 = 0;
-            if (gvalid) {
-                i = tlist[ti];
-                w = lhub[i];
-                q0 = a.prev_off[w];
-                np = a.prev_off[w + 1] - q0 - 1;  // the last entry is (w, 0)
-                p0 = a.lc_prev[w];
-            }
-            const E *pw = static_cast<const E *>(a.prev_hd) + q0;
-            const uint64_t nw = np - p0;
-            uint64_t cu = 0;
-            if (gvalid) cu = lower_bound_hub<DB>(pu, npu, w);
-            uint32_t steps = 1;
-            while ((1ull << steps) <= nw) steps++;
-            const bool useu = cu * steps < nw;
-            const uint64_t len = useu ? cu : nw;
-            const uint32_t nit = (uint32_t)((len + 15) / 16);
-            uint32_t maxit = nit;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) maxit = max(maxit, (uint32_t)__shfl_xor(maxit, o, 64));
-            bool done = !gvalid, found = false;
-            uint64_t read = 0;
-            for (uint32_t it = 0; it < maxit; it++) {
+        // The candidates' scans differ widely in length, so the 16-lane
+        // groups take them from a shared counter: a group that finishes one
+        // takes the next, one 16-entry step per trip, and no group waits for
+        // a slow one of another wave.
+        if (T > 0) {
+            bool have = false, retired = false;
+            uint32_t i = 0, it = 0, nit = 0;
+            uint64_t np = 0, p0 = 0, nw = 0, len = 0, read = 0, wt = 1;
+            const E *pw = nullptr;
+            bool useu = false;
+            while (true) {
+                if (!have && !retired) {  // uniform within the group
+                    uint32_t got = 0;
+                    if (gl == 0) got = atomicAdd(&s_next, 1u);
+                    got = (uint32_t)__shfl((int)got, (int)(grp * 16), 64);
+                    if (got < T) {
+                        i = tlist[got];
+                        const uint32_t w = lhub[i];
+                        const uint64_t q0 = a.prev_off[w];
+                        np = a.prev_off[w + 1] - q0 - 1;  // the last entry is (w, 0)
+                        p0 = a.lc_prev[w];
+                        pw = static_cast<const E *>(a.prev_hd) + q0;
+                        nw = np - p0;
+                        const uint64_t cu = lower_bound_hub<DB>(pu, npu, w);
+                        uint32_t steps = 1;
+                        while ((1ull << steps) <= nw) steps++;
+                        useu = cu * steps < nw;
+                        len = useu ? cu : nw;
+                        wt = useu ? steps : 1;
+                        nit = (uint32_t)((len + 15) / 16);
+                        it = 0;
+                        read = 0;
+                        have = true;
+                        if (nit == 0) {  // nothing to scan: kept
+                            if (gl == 0) {
+                                lkeep[i] = 1;
+                                my_hdr++;
+                            }
+                            have = false;
+                        }
+                    } else {
+                        retired = true;
+                    }
+                }
+                if (__ballot(have || !retired) == 0) break;
                 bool h2 = false;
-                const bool act = !done && it < nit;
                 const uint64_t j = (uint64_t)it * 16 + gl;
-                if (act && j < len) {
+                if (have && j < len) {
                     if (useu) {
                         const E e = pu[j];
                         const uint32_t h = e_hub<DB>(e);
@@ -797,23 +815,25 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
                 }
                 const uint64_t m = __ballot(h2);
                 const uint32_t gm = (uint32_t)((m >> (16 * grp)) & 0xFFFFull);
-                if (act) {
+                if (have) {
+                    bool fin = false, found = false;
                     if (gm) {
-                        found = true;
-                        done = true;
-                        read += useu ? (uint64_t)(__ffs(gm)) * steps : (uint64_t)__ffs(gm);
+                        found = fin = true;
+                        read += (uint64_t)__ffs(gm) * wt;
                     } else {
-                        uint64_t k = len - (uint64_t)it * 16;
-                        read += (k < 16 ? k : 16) * (useu ? steps : 1);
-                        if (it + 1 >= nit) done = true;
+                        const uint64_t k = len - (uint64_t)it * 16;
+                        read += (k < 16 ? k : 16) * wt;
+                        fin = ++it >= nit;
+                    }
+                    if (fin) {
+                        if (gl == 0) {
+                            lkeep[i] = found ? 0 : 1;
+                            my_tail += read;
+                            my_hdr++;
+                        }
+                        have = false;
                     }
                 }
-                if (__ballot(!done) == 0) break;
-            }
-            if (gvalid && gl == 0) {
-                lkeep[i] = found ? 0 : 1;
-                my_tail += read;
-                my_hdr++;
             }
         }
         if (gl == 0) {
