@@ -314,6 +314,12 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 #endif
 constexpr int kRoundBlock = SPC_ROUND_BLOCK;  // threads per puller workgroup
 static_assert((1 << (SPC_CBITS - 1)) >= SPC_ROUND_BLOCK, "candidate limit below one per thread");
+#ifndef SPC_TAIL_STEPS
+#define SPC_TAIL_STEPS 4
+#endif
+// merge trips over u's unstaged label per tile of w's entries before the
+// remaining hubs are binary-searched
+constexpr uint32_t kTailSteps = SPC_TAIL_STEPS;
 
 struct RoundArgs {
     uint32_t d, u_lo, u_hi;
@@ -401,8 +407,11 @@ struct LabelLookup {
     }
 };
 
-template <int DB, int RB>
-__global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
+// TM: w's entries past u's staged label are matched by a merge with u's
+// unstaged part (labels of similar length: high-diameter graphs) rather than
+// by binary searches
+template <int DB, int RB, bool TM>
+__global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 VGPRs: 4 waves per SIMD
     constexpr int RW = RB / 64;          // waves per workgroup
     constexpr int PER = kULimit / RB;    // candidate slots per thread
     using E = typename Ent<DB>::T;
@@ -764,6 +773,14 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
             uint64_t np = 0, p0 = 0, nw = 0, len = 0, read = 0, wt = 1;
             const E *pw = nullptr;
             bool useu = false;
+            // w's side: the current tile of w's entries (one per lane), which
+            // of them are decided, and a cursor into the part of u's label
+            // not staged in LDS
+            bool fresh = true, res = true, hit = false;
+            E ew = (E)0;
+            uint64_t ut = 0, upos = 0;
+            uint32_t usteps = 0;
+            bool tmerge = false;  // merge with u's unstaged part (labels of similar size)
             while (true) {
                 if (!have && !retired) {  // uniform within the group
                     uint32_t got = 0;
@@ -786,6 +803,9 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
                         nit = (uint32_t)((len + 15) / 16);
                         it = 0;
                         read = 0;
+                        fresh = true;
+                        ut = 0;
+                        tmerge = look.ntail <= 4 * nw;
                         have = true;
                         if (nit == 0) {  // nothing to scan: kept
                             if (gl == 0) {
@@ -799,23 +819,112 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
                     }
                 }
                 if (__ballot(have || !retired) == 0) break;
-                bool h2 = false;
-                const uint64_t j = (uint64_t)it * 16 + gl;
-                if (have && j < len) {
+                bool h2 = false, step_done = true;
+                if (have) {
                     if (useu) {
-                        const E e = pu[j];
-                        const uint32_t h = e_hub<DB>(e);
-                        const uint64_t q = p0 + lower_bound_hub<DB>(pw + p0, nw, h);
-                        h2 = q < np && e_hub<DB>(pw[q]) == h && e_dist<DB>(e) + e_dist<DB>(pw[q]) < d;
+                        const uint64_t j = (uint64_t)it * 16 + gl;
+                        if (j < len) {
+                            const E e = pu[j];
+                            const uint32_t h = e_hub<DB>(e);
+                            const uint64_t q = p0 + lower_bound_hub<DB>(pw + p0, nw, h);
+                            h2 = q < np && e_hub<DB>(pw[q]) == h && e_dist<DB>(e) + e_dist<DB>(pw[q]) < d;
+                        }
+                    } else if (!TM || look.ntail == 0) {
+                        // u's label all in LDS, or no merge: u's unstaged part
+                        // (if any) is binary-searched by look()
+                        const uint64_t j = (uint64_t)it * 16 + gl;
+                        if (j < len) {
+                            const E e = pw[p0 + j];
+                            const uint32_t du = look(e_hub<DB>(e));
+                            h2 = du != kNone && du + e_dist<DB>(e) < d;
+                        }
                     } else {
-                        const E e = pw[p0 + j];
-                        const uint32_t du = look(e_hub<DB>(e));
-                        h2 = du != kNone && du + e_dist<DB>(e) < d;
+                        if (fresh) {  // next 16 entries of w; hubs staged for u are looked up in LDS
+                            const uint64_t j = (uint64_t)it * 16 + gl;
+                            ew = j < len ? pw[p0 + j] : (E)0;
+                            res = j >= len;
+                            hit = false;
+                            const uint32_t h = e_hub<DB>(ew);
+                            if (!res && h < look.x) {
+                                const uint32_t du = look(h);
+                                hit = du != kNone && du + e_dist<DB>(ew) < d;
+                                res = true;
+                            }
+                            fresh = false;
+                            usteps = 0;
+                            upos = ut;
+                        }
+                        // the others in the part of u's label not staged: a
+                        // 16-wide merge from the cursor for a few trips (the near
+                        // hubs), then parallel binary searches past the cursor;
+                        // the cursor ends at the furthest position found, since
+                        // the next tile's hubs are larger
+                        if (!tmerge && ((__ballot(!res) >> (16 * grp)) & 0xFFFFull)) {
+                            // u's unstaged part is much longer than w's entries:
+                            // binary searches from the cursor
+                            uint64_t q = ut;
+                            if (!res) {
+                                const uint32_t h = e_hub<DB>(ew);
+                                q = ut + lower_bound_hub<DB>(look.tail + ut, look.ntail - ut, h);
+                                hit = q < look.ntail && e_hub<DB>(look.tail[q]) == h &&
+                                      e_dist<DB>(look.tail[q]) + e_dist<DB>(ew) < d;
+                                res = true;
+                            }
+#pragma unroll
+                            for (int o = 8; o > 0; o >>= 1) {
+                                const uint64_t y = __shfl_xor(q, o, 16);
+                                q = y > q ? y : q;
+                            }
+                            ut = q;
+                        } else if ((__ballot(!res) >> (16 * grp)) & 0xFFFFull) {
+                            const bool tv = ut + gl < look.ntail;
+                            const E te = tv ? look.tail[ut + gl] : (E)0;
+                            const uint32_t th = tv ? e_hub<DB>(te) : 0xFFFFFFFFu;
+                            const uint32_t lastu = (uint32_t)__shfl((int)th, 15, 16);
+                            const uint32_t h = e_hub<DB>(ew);
+                            uint32_t pp = 0;
+#pragma unroll
+                            for (uint32_t st = 8; st > 0; st >>= 1) {
+                                const uint32_t y = (uint32_t)__shfl((int)th, (int)(pp + st - 1), 16);
+                                if (y < h) pp += st;
+                            }
+                            const uint32_t hp = (uint32_t)__shfl((int)th, (int)pp, 16);
+                            const E ep = (E)__shfl(te, (int)pp, 16);
+                            if (!res && h <= lastu) {
+                                hit = hp == h && e_dist<DB>(ep) + e_dist<DB>(ew) < d;
+                                upos = ut + pp;
+                                res = true;
+                            }
+                            if (ut < look.ntail) read += (look.ntail - ut < 16) ? look.ntail - ut : 16;
+                            const bool more = ((__ballot(!res) >> (16 * grp)) & 0xFFFFull) != 0;
+                            if (more && ++usteps < kTailSteps) {
+                                ut += 16;  // merge on next trip; this tile waits
+                                step_done = false;
+                            } else {
+                                if (!res) {
+                                    const uint64_t b = ut + 16;
+                                    const uint64_t q =
+                                        b + lower_bound_hub<DB>(look.tail + b, look.ntail - b, h);
+                                    hit = q < look.ntail && e_hub<DB>(look.tail[q]) == h &&
+                                          e_dist<DB>(look.tail[q]) + e_dist<DB>(ew) < d;
+                                    upos = q;
+                                    res = true;
+                                }
+                                uint64_t mx = upos;
+#pragma unroll
+                                for (int o = 8; o > 0; o >>= 1) {
+                                    const uint64_t y = __shfl_xor(mx, o, 16);
+                                    mx = y > mx ? y : mx;
+                                }
+                                ut = mx;
+                            }
+                        }
+                        h2 = hit;
                     }
                 }
-                const uint64_t m = __ballot(h2);
+                const uint64_t m = __ballot(h2 && step_done);
                 const uint32_t gm = (uint32_t)((m >> (16 * grp)) & 0xFFFFull);
-                if (have) {
+                if (have && step_done) {
                     bool fin = false, found = false;
                     if (gm) {
                         found = fin = true;
@@ -824,6 +933,7 @@ __global__ __launch_bounds__(RB) void k_round(RoundArgs a) {
                         const uint64_t k = len - (uint64_t)it * 16;
                         read += (k < 16 ? k : 16) * wt;
                         fin = ++it >= nit;
+                        fresh = true;
                     }
                     if (fin) {
                         if (gl == 0) {
@@ -1507,6 +1617,7 @@ constexpr uint64_t kTempMax = 1ull << 27;
 // pullers per round-kernel launch (one workgroup each: the launch's
 // work-item count stays below 2^32)
 constexpr uint32_t kBatchVerts = 1u << 22;
+constexpr uint32_t kMergeRound = 16;
 
 // One distance round d >= 1.  Returns the number of entries it inserted.
 template <int DB>
@@ -1602,7 +1713,12 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.nxt = B.nxt;
         ra.ctr = B.ctr;
         SPC_HIP(hipEventRecord(B.ev_a, B.st));
-        k_round<DB, kRoundBlock><<<dim3(b1 - b0), dim3(kRoundBlock), 0, B.st>>>(ra);
+        // from round 17 on the graph has a long diameter: there, neighbours'
+        // labels are nearly the same set, which the tail merge exploits
+        if (d > kMergeRound)
+            k_round<DB, kRoundBlock, true><<<dim3(b1 - b0), dim3(kRoundBlock), 0, B.st>>>(ra);
+        else
+            k_round<DB, kRoundBlock, false><<<dim3(b1 - b0), dim3(kRoundBlock), 0, B.st>>>(ra);
         SPC_LAUNCHED();
         B.launches++;
         SPC_HIP(hipEventRecord(B.ev_b, B.st));
