@@ -136,7 +136,7 @@ def bench_served(args, dev, log):
     log(f"query autotuner: configuration {qcfg} {spc.query_configs()[qcfg]}")
 
     mean_batch = 65536 / np.log(65537) - 0.5
-    srv_kw = dict(io_budget_bytes=1 << 30, streams=4, max_batch=1 << 18)
+    srv_kw = dict(io_budget_bytes=1 << 30, streams=args.serve_streams, max_batch=args.serve_max_batch)
     # saturation: a burst (every request at t = 0)
     burst = serve.requests_from(inputs.poisson_requests(g.n, 1e9, args.serve_requests // 2, seed=6))
     for r in burst:
@@ -169,7 +169,8 @@ def bench_served(args, dev, log):
                                   "(ef 16, seed 5); Poisson requests, batch sizes log-uniform "
                                   "in 1..65536; value = served q/s at 1.0x saturation",
                       "n": g.n, "m": g.m, "entries": st["entries"], "rounds": st["rounds"],
-                      "requests_per_level": args.serve_requests, "parallelism": "single-gpu"},
+                      "requests_per_level": args.serve_requests, "max_batch": args.serve_max_batch,
+                      "streams": args.serve_streams, "parallelism": "single-gpu"},
            "p50_ms": one["p50_ms"], "p99_ms": one["p99_ms"],
            "build_ms": build_ms, "build_entries_per_s": st["entries"] / (build_ms * 1e-3),
            "query_config": dict(zip(("stage", "tiles"), spc.query_configs()[qcfg])),
@@ -336,6 +337,9 @@ def main():
     ap.add_argument("--grid-k", type=int, default=2048, help="grid side (grid workload)")
     ap.add_argument("--round-cap", type=int, default=64,
                     help="round cap D for the grid workload (0 = complete index)")
+    ap.add_argument("--serve-max-batch", type=int, default=1 << 18,
+                    help="queries per coalesced launch (rmat_served)")
+    ap.add_argument("--serve-streams", type=int, default=4, help="streams of the server (rmat_served)")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per offered-load level (rmat_served)")
     ap.add_argument("--batch-graphs", type=int, default=512)
