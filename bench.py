@@ -195,6 +195,15 @@ def bench_grid(args, dev, log):
     off_d = torch.from_numpy(g.off.view(np.int64)).to(dev)
     adj_d = torch.from_numpy(g.adj.view(np.int32)).to(dev)
     tie_d = torch.from_numpy(g.tie_key.view(np.int64)).to(dev)
+    order_d, order_ms, core = None, 0.0, None
+    if args.order != "degree":  # host-side hybrid / tree-decomposition order
+        delta = 0xFFFFFFFF if args.order == "td" else args.delta
+        t0 = time.perf_counter()
+        order_np, core = spc.hybrid_order(g.off, g.adj, delta)
+        order_ms = (time.perf_counter() - t0) * 1e3
+        order_d = torch.from_numpy(order_np.view(np.int32)).to(dev)
+        tie_d = None
+        log(f"{args.order} order on the host: {order_ms:.0f} ms, core {core}")
     s_np, t_np = inputs.queries(g.n, args.queries, seed=3)
     s_d = torch.from_numpy(s_np.view(np.int32)).to(dev)
     t_d = torch.from_numpy(t_np.view(np.int32)).to(dev)
@@ -204,7 +213,8 @@ def bench_grid(args, dev, log):
     runs = []
     for i in range(args.warmup + args.steps):
         t0 = time.perf_counter()
-        ix = spc.build_index(off_d, adj_d, tie_key=tie_d, opts=opts, device=dev, stream=stream)
+        ix = spc.build_index(off_d, adj_d, order=order_d, tie_key=tie_d, opts=opts, device=dev,
+                             stream=stream)
         bms = (time.perf_counter() - t0) * 1e3
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
@@ -226,8 +236,10 @@ def bench_grid(args, dev, log):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": bms + qms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
            "data": "synthetic",
-           "config": {"workload": f"grid {k}x{k}, 5% edges deleted, LCC, seed 3, random ties, "
+           "config": {"workload": f"grid {k}x{k}, 5% edges deleted, LCC, seed 3, "
+                                  f"{'degree order, random ties' if args.order == 'degree' else args.order + ' order'}, "
                                   f"round cap {args.round_cap or 'none'}, {args.queries} queries",
+                      "order": args.order, "order_host_ms": order_ms, "core": core,
                       "n": g.n, "m": g.m, "entries": st["entries"], "rounds": st["rounds"],
                       "truncated": bool(st["truncated"]), "dist_bits": st["dist_bits"],
                       "parallelism": "single-gpu"},
@@ -337,6 +349,10 @@ def main():
     ap.add_argument("--grid-k", type=int, default=2048, help="grid side (grid workload)")
     ap.add_argument("--round-cap", type=int, default=64,
                     help="round cap D for the grid workload (0 = complete index)")
+    ap.add_argument("--order", default="degree", choices=["degree", "hybrid", "td"],
+                    help="vertex order of the grid workload: degree (random ties), hybrid "
+                         "(--delta), td (tree decomposition: no degree bound)")
+    ap.add_argument("--delta", type=int, default=5, help="hybrid order degree threshold")
     ap.add_argument("--serve-max-batch", type=int, default=1 << 18,
                     help="queries per coalesced launch (rmat_served)")
     ap.add_argument("--serve-streams", type=int, default=4, help="streams of the server (rmat_served)")

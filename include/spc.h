@@ -207,6 +207,21 @@ spc_status spc_tune_queries(spc_index *ix, uint32_t graph_id, const uint32_t *s,
  * must not run concurrently with queries on the same index. */
 spc_status spc_set_query_config(spc_index *ix, uint32_t cfg);
 
+/* Hybrid vertex order ("Vertex Ordering Strategies": tree-decomposition
+ * order for the fringe, degree order for the core), for spc_graph.order.
+ * Fringe: vertices are removed one at a time, always one of least current
+ * degree (ties: smaller id), while that degree is at most delta; the
+ * remaining neighbours of a removed vertex are connected pairwise, so later
+ * degrees are those of this elimination graph.  Core: the vertices left,
+ * ranked first by input degree (descending, ties by id); then the fringe in
+ * reverse order of removal.  delta = 0xFFFFFFFF gives the pure
+ * tree-decomposition order.  g is a HOST CSR (on_device = 0; self loops and
+ * repeated entries ignored); order_out[n] receives rank -> vertex;
+ * *core_out (may be NULL) the core size.  Runs on the host.
+ * SPC_ERR_INVALID_ARG for NULL pointers, a device graph or ids >= n. */
+spc_status spc_hybrid_order(const spc_graph *g, uint32_t delta, uint32_t *order_out,
+                            uint32_t *core_out);
+
 /* Static string for a status code. */
 const char *spc_status_string(spc_status s);
 

@@ -224,3 +224,48 @@ def build_graph(g, method: str = "pruned", depth_cap: int = 0, **kw) -> Labels:
     """Build for an inputs.Graph (uses its explicit order or tie keys)."""
     return build(g.off, g.adj, order=g.order, tie_key=g.tie_key, method=method,
                  depth_cap=depth_cap, **kw)
+
+
+def hybrid_order(off, adj, delta: int):
+    """Hybrid vertex order (the paper's "Vertex Ordering Strategies": the
+    road-network order from tree decomposition for the fringe, the degree
+    order for the core), written out with Python sets.  Returns
+    (order rank -> vertex, core size).
+
+    Fringe: remove a vertex of least current degree (ties: smaller id) while
+    that degree is <= delta, connecting its remaining neighbours pairwise;
+    degrees are those of this elimination graph (the paper's update
+    deg(u) + deg(u_0) - 1 counts shared neighbours twice; the elimination
+    graph is what the tree decomposition it cites is built from).  Core: the
+    rest, by input degree descending, ties by id, ranked first; then the
+    fringe in reverse order of removal.  Small graphs only."""
+    import heapq
+
+    off, adj = _u64(off), _u32(adj)
+    n = off.shape[0] - 1
+    nbr = [set(int(w) for w in adj[off[v]:off[v + 1]] if int(w) != v) for v in range(n)]
+    deg0 = [len(s) for s in nbr]
+    removed = [False] * n
+    heap = [(len(nbr[v]), v) for v in range(n) if len(nbr[v]) <= delta]
+    heapq.heapify(heap)
+    elim = []
+    while heap:
+        dg, v = heapq.heappop(heap)
+        if removed[v] or dg != len(nbr[v]):
+            continue
+        removed[v] = True
+        elim.append(v)
+        ns = sorted(nbr[v])
+        nbr[v] = set()
+        for a in ns:
+            nbr[a].discard(v)
+        for i, a in enumerate(ns):
+            for b in ns[i + 1:]:
+                nbr[a].add(b)
+                nbr[b].add(a)
+        for a in ns:
+            if len(nbr[a]) <= delta:
+                heapq.heappush(heap, (len(nbr[a]), a))
+    core = sorted((v for v in range(n) if not removed[v]), key=lambda v: (-deg0[v], v))
+    order = np.array(core + elim[::-1], dtype=np.uint32)
+    return order, len(core)

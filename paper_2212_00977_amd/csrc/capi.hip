@@ -106,6 +106,11 @@ spc_status spc_tune_queries(spc_index *ix, uint32_t graph_id, const uint32_t *s,
     return spc::tune_queries_impl(ix, graph_id, s, t, nq, static_cast<hipStream_t>(stream), cfg_out);
 }
 
+spc_status spc_hybrid_order(const spc_graph *g, uint32_t delta, uint32_t *order_out,
+                            uint32_t *core_out) {
+    return spc::hybrid_order_impl(g, delta, order_out, core_out);
+}
+
 spc_status spc_set_query_config(spc_index *ix, uint32_t cfg) {
     if (!ix || cfg >= spc::query_cfg_count()) return SPC_ERR_INVALID_ARG;
     ix->query_cfg = cfg;

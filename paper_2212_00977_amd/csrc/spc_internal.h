@@ -353,6 +353,8 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *opt
 spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                       uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
                       hipStream_t st);
+// order.hip
+spc_status hybrid_order_impl(const spc_graph *g, uint32_t delta, uint32_t *order, uint32_t *core_out);
 spc_status tune_queries_impl(spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                              uint64_t nq, hipStream_t st, uint32_t *cfg_out);
 uint32_t query_cfg_count();

@@ -15,14 +15,14 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "lib")
 LIBPATH = os.path.join(LIBDIR, "libspc.so")
-SOURCES = ["memory.hip", "primitives.hip", "build.hip", "query.hip", "capi.hip"]
+SOURCES = ["memory.hip", "primitives.hip", "build.hip", "query.hip", "order.hip", "capi.hip"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_free",
            "spc_index_stats", "spc_round_stats", "spc_round_profile", "spc_graph_entries", "spc_export_labels",
            "spc_status_string", "spc_release_cached_memory", "spc_query_config_count",
-           "spc_query_config_info", "spc_tune_queries", "spc_set_query_config"]
+           "spc_query_config_info", "spc_tune_queries", "spc_set_query_config", "spc_hybrid_order"]
 
 
 # A test build with tiny on-chip tables (8-bit hash of 128 slots for the
@@ -114,6 +114,8 @@ def load(path: str | None = None):
     L.spc_query_config_info.restype = C.c_int
     L.spc_tune_queries.argtypes = [vp, u32, vp, vp, u64, vp, C.POINTER(u32)]
     L.spc_tune_queries.restype = C.c_int
+    L.spc_hybrid_order.argtypes = [C.POINTER(SpcGraph), u32, vp, C.POINTER(u32)]
+    L.spc_hybrid_order.restype = C.c_int
     L.spc_set_query_config.argtypes = [vp, u32]
     L.spc_set_query_config.restype = C.c_int
     L.spc_status_string.argtypes = [C.c_int]

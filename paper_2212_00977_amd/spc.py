@@ -285,6 +285,25 @@ def build_index_batch(graphs, opts: BuildOptions | None = None, device=None, str
     return Index(h, device)
 
 
+def hybrid_order(off, adj, delta: int = 5):
+    """Hybrid vertex order of a host CSR (numpy): (order rank -> vertex, core
+    size); computed on the host by the library (spc_hybrid_order)."""
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.uint64))
+    adj = np.ascontiguousarray(np.asarray(adj, dtype=np.uint32))
+    n = off.shape[0] - 1
+    g = native.SpcGraph()
+    g.n = n
+    g.nnz = int(adj.shape[0])
+    g.row_off = off.ctypes.data
+    g.col = adj.ctypes.data if adj.shape[0] else None
+    g.on_device = 0
+    order = np.zeros(max(n, 1), dtype=np.uint32)
+    core = C.c_uint32()
+    _check(native.load().spc_hybrid_order(C.byref(g), int(delta) & 0xFFFFFFFF, order.ctypes.data,
+                                          C.byref(core)), "spc_hybrid_order")
+    return order[:n], core.value
+
+
 def query_configs() -> list:
     """(stage, tiles) of every query launch configuration, by number."""
     lib = native.load()
