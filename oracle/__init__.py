@@ -269,3 +269,145 @@ def hybrid_order(off, adj, delta: int):
     core = sorted((v for v in range(n) if not removed[v]), key=lambda v: (-deg0[v], v))
     order = np.array(core + elim[::-1], dtype=np.uint32)
     return order, len(core)
+
+
+@dataclass
+class Shell:
+    """1-shell of a graph (per vertex, original ids)."""
+    core: np.ndarray    # bool: vertex keeps a label
+    root: np.ndarray    # shr(v): the core vertex v's tree hangs from (v itself in the core)
+    depth: np.ndarray   # distance from v to root[v]
+    parent: np.ndarray  # neighbour of v on the path to root[v] (v itself in the core)
+
+
+def one_shell(off, adj) -> Shell:
+    """The 1-shell of the paper's Section "Reduction by 1-Shell", written
+    from its definitions with Python sets (small graphs only).
+
+    The core is the 2-core: the largest subgraph in which every vertex has
+    at least two neighbours, obtained by deleting vertices of degree below
+    two until none is left.  Every other vertex is in the fringe, which is a
+    forest; each of its trees is joined to the core by one edge, whose core
+    end is the root shr(v) of the tree's vertices.  A component with an empty
+    2-core is a tree: its centre (least eccentricity, the smaller id of two
+    centres) stays in the core as the root of the rest.  depth and parent
+    follow a breadth-first search from the roots through fringe vertices."""
+    from collections import deque
+
+    off, adj = _u64(off), _u32(adj)
+    n = off.shape[0] - 1
+    nbr = [sorted(set(int(w) for w in adj[off[v]:off[v + 1]] if int(w) != v)) for v in range(n)]
+    deg = [len(x) for x in nbr]
+    core = [True] * n
+    stack = [v for v in range(n) if deg[v] < 2]
+    while stack:
+        v = stack.pop()
+        if not core[v]:
+            continue
+        core[v] = False
+        for w in nbr[v]:
+            if core[w]:
+                deg[w] -= 1
+                if deg[w] < 2:
+                    stack.append(w)
+
+    def bfs(src):
+        dist = {src: 0}
+        q = deque([src])
+        while q:
+            v = q.popleft()
+            for w in nbr[v]:
+                if w not in dist:
+                    dist[w] = dist[v] + 1
+                    q.append(w)
+        return dist
+
+    seen = [False] * n
+    for v in range(n):
+        if seen[v]:
+            continue
+        comp = list(bfs(v))
+        for x in comp:
+            seen[x] = True
+        if not any(core[x] for x in comp):
+            ecc = {x: max(bfs(x).values()) for x in comp}
+            centre = min(comp, key=lambda x: (ecc[x], x))
+            core[centre] = True
+    root = np.arange(n, dtype=np.uint32)
+    depth = np.zeros(n, dtype=np.uint32)
+    parent = np.arange(n, dtype=np.uint32)
+    q = deque(v for v in range(n) if core[v])
+    done = list(core)
+    while q:
+        v = q.popleft()
+        for w in nbr[v]:
+            if not done[w]:
+                done[w] = True
+                root[w], depth[w], parent[w] = root[v], depth[v] + 1, v
+                q.append(w)
+    return Shell(np.array(core, dtype=bool), root, depth, parent)
+
+
+@dataclass
+class ReducedIndex:
+    """Labels of the core only, plus the 1-shell that answers the rest."""
+    shell: Shell
+    core_ids: np.ndarray  # core id -> original vertex (ascending)
+    cid: np.ndarray       # original vertex -> core id (core vertices only)
+    labels: Labels        # index of the core subgraph, ORIGINAL core ids in .order
+
+    def query(self, s, t):
+        """Query rule of the 1-shell reduction: when root(s) = root(t) the
+        tree path is the only shortest path; otherwise the core query
+        between the roots, with both depths added to the distance."""
+        sh = self.shell
+        s, t = _u32(s), _u32(t)
+        rs, rt = sh.root[s], sh.root[t]
+        d, c = self.labels.query(self.cid[rs], self.cid[rt])
+        d = d.astype(np.uint64)
+        far = d != INF
+        d[far] += sh.depth[s][far].astype(np.uint64) + sh.depth[t][far]
+        d = np.where(far, d, INF).astype(np.uint32)
+        for i in np.nonzero(rs == rt)[0]:
+            x, y = int(s[i]), int(t[i])
+            dx, dy = int(sh.depth[x]), int(sh.depth[y])
+            tot = dx + dy
+            while dx > dy:
+                x, dx = int(sh.parent[x]), dx - 1
+            while dy > dx:
+                y, dy = int(sh.parent[y]), dy - 1
+            while x != y:
+                x, y, dx = int(sh.parent[x]), int(sh.parent[y]), dx - 1
+            d[i], c[i] = tot - 2 * dx, 1
+        return d, c
+
+
+def core_subgraph(off, adj, core, order=None, tie_key=None):
+    """CSR of the subgraph induced by the core (core ids ascending with the
+    original ids), the order restricted to it, and its tie keys."""
+    off, adj = _u64(off), _u32(adj)
+    core = np.asarray(core, dtype=bool)
+    n = off.shape[0] - 1
+    ids = np.nonzero(core)[0].astype(np.uint32)
+    cid = np.full(n, INF, dtype=np.uint32)
+    cid[ids] = np.arange(ids.shape[0], dtype=np.uint32)
+    rows = []
+    for v in ids:
+        nb = adj[off[v]:off[v + 1]]
+        rows.append(cid[nb[core[nb]]])
+    coff = np.zeros(ids.shape[0] + 1, dtype=np.uint64)
+    coff[1:] = np.cumsum([r.shape[0] for r in rows]) if rows else []
+    cadj = np.concatenate(rows).astype(np.uint32) if rows else np.zeros(0, dtype=np.uint32)
+    cord = None if order is None else cid[_u32(order)[core[_u32(order)]]]
+    ctie = None if tie_key is None else _u64(tie_key)[ids]
+    return coff, cadj, ids, cid, cord, ctie
+
+
+def build_reduced(off, adj, order=None, tie_key=None) -> ReducedIndex:
+    """1-shell reduction, then the label index of the core subgraph (its own
+    degree order unless an order is given, which is then restricted to the
+    core)."""
+    sh = one_shell(off, adj)
+    coff, cadj, ids, cid, cord, ctie = core_subgraph(off, adj, sh.core, order, tie_key)
+    lab = build(coff, cadj, order=cord, tie_key=ctie)
+    return ReducedIndex(sh, ids, cid, lab)
