@@ -326,6 +326,49 @@ def bench_batch(args, dev, log):
     print(json.dumps(out), flush=True)
 
 
+def one_shell_side(off_d, adj_d, s_d, t_d, dev, stream, cfg, ref_d, ref_c, log, reps=2):
+    """The same workload built with the 1-shell cut off (Section "Reduction
+    by 1-Shell"): build time, fringe, index size and query rate of the
+    reduced index, and how many answers differ from the full index's (the
+    last timed step's outputs).  Not part of the headline value."""
+    import torch
+
+    from paper_2212_00977_amd import spc
+
+    nq = int(s_d.shape[0])
+    opts = spc.BuildOptions(one_shell=True)
+    builds, queries = [], []
+    for i in range(reps):  # the first build warms the block cache
+        t0 = time.perf_counter()
+        ix = spc.build_index(off_d, adj_d, device=dev, stream=stream, opts=opts)
+        builds.append((time.perf_counter() - t0) * 1e3)
+        ix.set_query_config(cfg)
+        bits = ix.dist_bits
+        d = torch.empty(nq, dtype=torch.uint8 if bits == 8 else torch.int16, device=dev)
+        c = torch.empty(nq, dtype=torch.int64, device=dev)
+        f = torch.empty(nq, dtype=torch.uint8, device=dev)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        ix.query(s_d, t_d, stream=stream, out=(d, c, f))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        queries.append(ev0.elapsed_time(ev1))
+        st = ix.stats()
+        if i < reps - 1:
+            ix.free()
+    same_bits = bits == 8
+    diff = int(((d.to(torch.int32) != ref_d.to(torch.int32)) | (c != ref_c)).sum()) if same_bits else -1
+    ix.free()
+    out = {"build_ms": builds[-1], "query_ms": queries[-1], "queries_per_s": nq / (queries[-1] * 1e-3),
+           "fringe_vertices": st["fringe_vertices"], "fringe_depth": st["fringe_depth"],
+           "core_vertices": st["n"], "entries": st["entries"], "index_bytes": st["index_bytes"],
+           "peak_build_bytes": st["peak_build_bytes"], "dist_bits": bits,
+           "answers_differing_from_full_index": diff}
+    log(f"one-shell: build {builds[-1]:.1f} ms, fringe {st['fringe_vertices']}, "
+        f"entries {st['entries']}, queries {queries[-1]:.1f} ms, differing answers {diff}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,6 +402,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per offered-load level (rmat_served)")
     ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--no-one-shell", action="store_true",
+                    help="skip the side measurement of the 1-shell reduced build")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -498,6 +543,9 @@ def main():
         "peak_build_bytes": st["peak_build_bytes"],
     }
     last_ix = runs[-1]["index"]
+    if not args.no_one_shell:
+        out["one_shell"] = one_shell_side(off_d, adj_d, s_d, t_d, dev, stream, qcfg[0], dist_o, cnt_o,
+                                          log)
     if args.serve_seconds > 0 or args.serve_sweep:
         out["serve"] = serve_runs(last_ix, g.n, args, out["queries_per_s"], log)
     last_ix.free()

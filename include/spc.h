@@ -58,6 +58,9 @@ typedef enum {
 #define SPC_FLAG_HORIZON 0x4u    /* truncated index: answer not proven exact (dist > round cap or none found) */
 #define SPC_FLAG_INVALID 0x8u    /* s or t >= n: dist = INF, count 0 */
 
+/* Index reductions (spc_build_opts.reduce). */
+#define SPC_REDUCE_ONE_SHELL 0x1u /* Section "Reduction by 1-Shell": label only the core */
+
 /* An undirected, unweighted graph (Preliminaries: G = (V, E)) as a symmetric
  * CSR: the neighbours of v are col[row_off[v] .. row_off[v+1]).  Every edge
  * appears in both directions; no self loops, no duplicate entries.
@@ -85,7 +88,17 @@ typedef struct {
                             round D+1 would have had candidates */
     uint64_t mem_budget; /* device bytes the build may hold at once; 0 = unlimited */
     uint32_t validate;   /* nonzero: check that the CSR is simple and symmetric */
-    uint32_t reserved;   /* must be 0 */
+    /* 0, or SPC_REDUCE_ONE_SHELL (Section "Reduction by 1-Shell"): the
+     * fringe -- every vertex outside the 2-core, i.e. the trees hanging off
+     * the rest of the graph by one edge, and whole tree components but one
+     * vertex each -- is cut off and only the remaining core is labelled
+     * (ordered by its own degrees when no order is given, else by the given
+     * order restricted to it).  Each fringe vertex v keeps root(v) (the core
+     * vertex its tree hangs from; the centre of a tree component, the smaller
+     * id of two centres), its depth (distance to root(v)) and its parent (next
+     * vertex towards root(v)); queries answer from these and the core labels
+     * (spc_query_batch).  Other bits: SPC_ERR_INVALID_ARG. */
+    uint32_t reduce;
 } spc_build_opts;
 
 typedef struct {
@@ -95,7 +108,9 @@ typedef struct {
     uint64_t entries;         /* label entries, self entries included */
     uint32_t rounds;          /* last round run: first empty round, or the cap */
     uint32_t max_dist;        /* largest label distance */
-    uint32_t dist_bits;       /* 8 or 16: width of query dist outputs */
+    uint32_t dist_bits;       /* 8 or 16: width of query dist outputs (8 when every query
+                                 distance fits in 0..254: twice the largest label distance,
+                                 plus twice the largest fringe depth, at most 254) */
     uint32_t truncated;       /* 1 if round_cap stopped the build early */
     uint64_t saturated_entries; /* entries whose count is 2^64-1 */
     uint64_t index_bytes;     /* device bytes held by the finished index */
@@ -108,6 +123,9 @@ typedef struct {
     uint64_t alg_bytes_round_kernel; /* algorithmic bytes of the fused round kernel */
     uint64_t round_kernel_launches;  /* dispatches of the fused round kernel */
     uint32_t query_config;           /* query launch configuration in use */
+    uint32_t label_bits;             /* 8 or 16: width of stored label distances */
+    uint64_t fringe_vertices;        /* vertices cut off by SPC_REDUCE_ONE_SHELL (0 otherwise) */
+    uint32_t fringe_depth;           /* largest fringe depth */
     uint32_t reserved;
 } spc_stats;
 
@@ -116,7 +134,9 @@ typedef struct {
  * malformed graph (ids >= n, self loops, asymmetric or duplicate entries when
  * validate is set, order not a permutation), SPC_ERR_UNSUPPORTED when
  * n >= 2^24 - 1 with dist_bits = 8, n > 2^26 - 1024 (all graphs of a batch
- * together) or nnz > 2^32 - 2^20, SPC_ERR_DIST_RANGE as documented above. */
+ * together) or nnz > 2^32 - 2^20, SPC_ERR_DIST_RANGE as documented above or
+ * when a query distance could exceed 65534 (twice the largest label distance
+ * plus twice the largest fringe depth). */
 spc_status spc_build_index(const spc_graph *g, const spc_build_opts *opts, void *stream,
                            spc_index **out);
 
@@ -129,9 +149,15 @@ spc_status spc_build_index_batch(const spc_graph *gs, uint32_t k, const spc_buil
 /* SPC queries (Eq. con:spc1 and con:spc2) on graph `graph_id` of the index
  * (0 for single-graph indexes).  s, t: device uint32[nq] with vertex ids of
  * that graph.  Outputs (device, caller-owned, nq each): dist_out is uint8 when
- * the index has 8-bit labels and uint16 otherwise, INF = the type's maximum;
+ * spc_stats.dist_bits is 8 and uint16 otherwise, INF = the type's maximum;
  * count_out uint64; flags_out uint8 (SPC_FLAG_*, may be NULL).  s = t gives
- * (0, 1).  Asynchronous on `stream`; nq == 0 is a no-op. */
+ * (0, 1).  Asynchronous on `stream`; nq == 0 is a no-op.
+ * With SPC_REDUCE_ONE_SHELL ("Query Evaluation in Parallel" of that section):
+ * when root(s) = root(t) the only shortest path is the tree path, count 1,
+ * distance depth(s) + depth(t) - 2 depth(lowest common ancestor); otherwise
+ * the core labels of root(s) and root(t) are joined and depth(s) + depth(t)
+ * is added to the distance (the count is unchanged: every s-t path runs
+ * through root(s) and root(t), each reached by one path). */
 spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
                            const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
                            uint8_t *flags_out, void *stream);
@@ -169,18 +195,32 @@ spc_status spc_round_profile(const spc_index *ix, uint32_t max_rounds, double *k
                              uint64_t *staged, uint64_t *row_bytes, uint64_t *headers,
                              uint64_t *mem_peak);
 
-/* Number of label entries of graph `graph_id` (host out). */
+/* Number of labelled vertices (the core under SPC_REDUCE_ONE_SHELL, else
+ * every vertex) and label entries of graph `graph_id` (host out). */
 spc_status spc_graph_entries(const spc_index *ix, uint32_t graph_id, uint32_t *n_out,
                              uint64_t *entries_out);
 
 /* Export the labels of graph `graph_id` in RANK space (vertex id = rank in
  * that graph, hubs likewise), each label sorted by hub: off[n+1], hub, dist,
- * count[entries], order[n] (rank -> vertex id).  Pointers are device pointers
- * when on_device is nonzero, host pointers otherwise; any may be NULL to skip
- * it.  Synchronises `stream`. */
+ * count[entries], order[n] (rank -> vertex id), n = the labelled vertices of
+ * spc_graph_entries (for a reduced index, the core; order then gives the
+ * input graph's vertex ids).  Pointers are device pointers when on_device is
+ * nonzero, host pointers otherwise; any may be NULL to skip it.
+ * Synchronises `stream`. */
 spc_status spc_export_labels(const spc_index *ix, uint32_t graph_id, uint64_t *off,
                              uint32_t *hub, uint16_t *dist, uint64_t *count, uint32_t *order,
                              int32_t on_device, void *stream);
+
+/* The 1-shell of graph `graph_id` (Section "Reduction by 1-Shell"), per
+ * vertex of the input graph: root[v] (shr(v): the core vertex v's tree hangs
+ * from, v itself in the core), depth[v] (distance to root[v]), parent[v]
+ * (the neighbour of v on the path to root[v], v itself in the core).  An
+ * index built without SPC_REDUCE_ONE_SHELL reports every vertex in the core.
+ * Arrays of the graph's input size n; device pointers when on_device is
+ * nonzero, host pointers otherwise; any may be NULL.  Synchronises `stream`. */
+spc_status spc_export_reduction(const spc_index *ix, uint32_t graph_id, uint32_t *root,
+                                uint32_t *depth, uint32_t *parent, int32_t on_device,
+                                void *stream);
 
 /* Query launch configurations.  The query kernel stages slices of L(s) in
  * LDS and streams L(t) past them; a configuration fixes the slice length

@@ -403,11 +403,11 @@ def core_subgraph(off, adj, core, order=None, tie_key=None):
     return coff, cadj, ids, cid, cord, ctie
 
 
-def build_reduced(off, adj, order=None, tie_key=None) -> ReducedIndex:
+def build_reduced(off, adj, order=None, tie_key=None, depth_cap: int = 0) -> ReducedIndex:
     """1-shell reduction, then the label index of the core subgraph (its own
     degree order unless an order is given, which is then restricted to the
-    core)."""
+    core; depth_cap > 0 keeps the distance-partial core labels)."""
     sh = one_shell(off, adj)
     coff, cadj, ids, cid, cord, ctie = core_subgraph(off, adj, sh.core, order, tie_key)
-    lab = build(coff, cadj, order=cord, tie_key=ctie)
+    lab = build(coff, cadj, order=cord, tie_key=ctie, depth_cap=depth_cap)
     return ReducedIndex(sh, ids, cid, lab)

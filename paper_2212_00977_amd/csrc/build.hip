@@ -1237,6 +1237,9 @@ struct Build {
     uint64_t NNZ = 0;
     uint32_t k = 1;
     std::vector<uint32_t> vbase, gn;
+    ShellResult shell;  // SPC_REDUCE_ONE_SHELL: the fringe and the core ids
+    bool reduced = false;
+    std::vector<uint32_t> obase, on;  // input vertex ranges when reduced
     // graph
     uint64_t *goff = nullptr;
     uint32_t *gadj = nullptr;
@@ -1438,10 +1441,40 @@ struct Build {
     }
 };
 
-// union CSR + ordering + relabel (+ validation)
-spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_tie, bool validate) {
-    const uint32_t N = B.N;
-    const uint64_t NNZ = B.NNZ;
+// simple + symmetric check of a CSR; sorts each row of adj in place
+spc_status validate_csr(Build &B, const uint64_t *off, uint32_t *adj, uint32_t N, uint64_t NNZ,
+                        uint32_t *err) {
+    if (!NNZ) return SPC_OK;
+    int xb = std::max(1, bit_width(N));
+    uint64_t *keys = nullptr, *keys2 = nullptr;
+    SPC_TRY(B.arena.alloc(&keys, NNZ));
+    SPC_TRY(B.arena.alloc(&keys2, NNZ));
+    uint64_t *rws = nullptr;
+    SPC_TRY(B.arena.alloc(&rws, radix_ws_elems(NNZ)));
+    hipLaunchKernelGGL(k_row_keys, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, off, adj, N, xb,
+                       keys);
+    SPC_LAUNCHED();
+    SPC_TRY(radix_sort_pairs(keys, nullptr, keys2, nullptr, NNZ, 2 * xb, rws, B.st));
+    hipLaunchKernelGGL(k_keys_to_adj, dim3(grid_for(NNZ, kBlock)), dim3(kBlock), 0, B.st, keys, NNZ, xb,
+                       adj);
+    SPC_LAUNCHED();
+    SPC_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), B.st));
+    hipLaunchKernelGGL(k_check_adj, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, off, adj, N, err);
+    SPC_LAUNCHED();
+    uint64_t ev[1];
+    SPC_TRY(B.read_u64((const uint64_t *)err, ev));
+    B.arena.release(keys);
+    B.arena.release(keys2);
+    B.arena.release(rws);
+    if ((uint32_t)ev[0] != 0) return SPC_ERR_INVALID_ARG;
+    return SPC_OK;
+}
+
+// union CSR (+ 1-shell reduction) + ordering + relabel (+ validation)
+spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_tie, bool validate,
+                      bool reduce) {
+    uint32_t N = B.N;
+    uint64_t NNZ = B.NNZ;
     uint64_t *off = nullptr;
     uint32_t *col = nullptr, *deg = nullptr, *err = nullptr, *vb_dev = nullptr;
     SPC_TRY(B.arena.alloc(&off, (uint64_t)N + 1));
@@ -1528,6 +1561,37 @@ spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_ti
     B.arena.release(st_col);
     B.arena.release(st_ord);
 
+    if (reduce) {
+        // Section "Reduction by 1-Shell": the rest of the build sees the core
+        // only.  The input is checked first: the stripping assumes a simple
+        // symmetric graph.
+        if (validate) SPC_TRY(validate_csr(B, off, col, N, NNZ, err));
+        validate = false;  // the core of a valid graph is valid
+        ShellResult &R = B.shell;
+        SPC_TRY(one_shell(B.arena, B.st, B.ws, N, NNZ, off, col, ord_union, tie_union, B.vbase, &R));
+        B.arena.release(off);
+        B.arena.release(col);
+        B.arena.release(ord_union);
+        B.arena.release(tie_union);
+        off = R.off;
+        col = R.col;
+        ord_union = R.ord;
+        tie_union = R.tie;
+        R.off = nullptr;
+        R.col = nullptr;
+        R.ord = nullptr;
+        R.tie = nullptr;
+        B.reduced = true;
+        B.obase = B.vbase;
+        B.on = B.gn;
+        B.vbase = R.cbase;
+        for (uint32_t g = 0; g < B.k; g++) B.gn[g] = B.vbase[g + 1] - B.vbase[g];
+        B.N = N = R.N;
+        B.NNZ = NNZ = R.NNZ;
+        SPC_HIP(hipMemcpyAsync(vb_dev, B.vbase.data(), B.k * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               B.st));
+    }
+
     // degrees and order
     uint32_t *maxdeg = err + 1;
     hipLaunchKernelGGL(k_degrees, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st, off, N, deg,
@@ -1582,31 +1646,7 @@ spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_ti
     B.arena.release(col);
     B.arena.release(deg);
 
-    if (validate && NNZ) {
-        int xb = std::max(1, bit_width(N));
-        uint64_t *keys = nullptr, *keys2 = nullptr;
-        SPC_TRY(B.arena.alloc(&keys, NNZ));
-        SPC_TRY(B.arena.alloc(&keys2, NNZ));
-        uint64_t *rws = nullptr;
-        SPC_TRY(B.arena.alloc(&rws, radix_ws_elems(NNZ)));
-        hipLaunchKernelGGL(k_row_keys, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, B.goff,
-                           B.gadj, N, xb, keys);
-        SPC_LAUNCHED();
-        SPC_TRY(radix_sort_pairs(keys, nullptr, keys2, nullptr, NNZ, 2 * xb, rws, B.st));
-        hipLaunchKernelGGL(k_keys_to_adj, dim3(grid_for(NNZ, kBlock)), dim3(kBlock), 0, B.st, keys,
-                           NNZ, xb, B.gadj);
-        SPC_LAUNCHED();
-        SPC_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), B.st));
-        hipLaunchKernelGGL(k_check_adj, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, B.goff,
-                           B.gadj, N, err);
-        SPC_LAUNCHED();
-        uint64_t ev[1];
-        SPC_TRY(B.read_u64((const uint64_t *)err, ev));
-        B.arena.release(keys);
-        B.arena.release(keys2);
-        B.arena.release(rws);
-        if ((uint32_t)ev[0] != 0) return SPC_ERR_INVALID_ARG;
-    }
+    if (validate) SPC_TRY(validate_csr(B, B.goff, B.gadj, N, NNZ, err));
     B.arena.release(err);
     B.arena.release(vb_dev);
     return SPC_OK;
@@ -1950,7 +1990,7 @@ inline float elapsed(hipEvent_t a, hipEvent_t b) {
 spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, hipStream_t st,
                       spc_index **out) {
     if (!gs || !o || !out || k == 0) return SPC_ERR_INVALID_ARG;
-    if (o->reserved != 0) return SPC_ERR_INVALID_ARG;
+    if ((o->reduce & ~SPC_REDUCE_ONE_SHELL) != 0) return SPC_ERR_INVALID_ARG;
     if (o->dist_bits != 0 && o->dist_bits != 8 && o->dist_bits != 16) return SPC_ERR_INVALID_ARG;
     uint64_t N64 = 0, NNZ = 0;
     uint32_t n_order = 0, n_tie = 0, n_dev = 0;
@@ -2012,8 +2052,7 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         }
     } evg{ev};
     for (int i = 0; i < 4; i++) SPC_HIP(hipEventCreate(&ev[i]));
-    const uint32_t N = B.N;
-    if (N == 0) {  // nothing to order or label: an empty index
+    if (B.N == 0) {  // nothing to order or label: an empty index
         if (NNZ) return SPC_ERR_INVALID_ARG;
         spc_index *ix = new (std::nothrow) spc_index();
         if (!ix) return SPC_ERR_OUT_OF_MEMORY;
@@ -2028,6 +2067,7 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         SPC_HIP(hipStreamSynchronize(st));
         ix->device = dev;
         ix->dist_bits = (uint32_t)db;
+        ix->out_bits = (uint32_t)db;
         ix->vbase.assign(B.vbase.begin(), B.vbase.end());
         ix->gn = B.gn;
         ix->round_stats.push_back(RoundCounters());
@@ -2040,12 +2080,17 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         *out = ix;
         return SPC_OK;
     }
-    SPC_TRY(B.arena.alloc(&B.ws, std::max(radix_ws_elems((uint64_t)N + 1), scan_ws_elems((uint64_t)N + 1))));
+    SPC_TRY(B.arena.alloc(&B.ws, std::max(radix_ws_elems((uint64_t)B.N + 1), scan_ws_elems((uint64_t)B.N + 1))));
     SPC_TRY(B.arena.alloc(&B.ctr, 8));
 
     SPC_HIP(hipEventRecord(ev[0], st));
-    SPC_TRY(preprocess(B, gs, n_order == k, n_tie == k, o->validate != 0));
+    SPC_TRY(preprocess(B, gs, n_order == k, n_tie == k, o->validate != 0,
+                       (o->reduce & SPC_REDUCE_ONE_SHELL) != 0));
     SPC_HIP(hipEventRecord(ev[1], st));
+    // from here on the graph is the core when the 1-shell was cut off
+    const uint32_t N = B.N;
+    const uint64_t NNZ_in = NNZ;
+    NNZ = B.NNZ;
 
     // round 0
     SPC_TRY(B.arena.alloc(&B.raw, (uint64_t)N + 1));
@@ -2153,20 +2198,27 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     SPC_HIP(hipEventRecord(ev[3], st));
     SPC_HIP(hipStreamSynchronize(st));
 
+    uint32_t maxd = 0;
+    for (size_t r = 0; r < B.stats.size(); r++)
+        if (B.stats[r].kept) maxd = (uint32_t)r;
+    // a query distance is at most two label distances plus two fringe
+    // depths: the outputs take the narrowest width that holds every one
+    const uint64_t qmax = 2ull * maxd + (B.reduced ? 2ull * B.shell.max_depth : 0ull);
+    if (qmax > Ent<16>::kMaxDist) return SPC_ERR_DIST_RANGE;
+    const uint32_t out_bits = (B.db == 16 || qmax > Ent<8>::kMaxDist) ? 16u : 8u;
+
     spc_index *ix = new (std::nothrow) spc_index();
     if (!ix) return SPC_ERR_OUT_OF_MEMORY;
     ix->device = dev;
     ix->n = N;
-    ix->m = NNZ / 2;
+    ix->m = NNZ_in / 2;
     ix->dist_bits = (uint32_t)B.db;
+    ix->out_bits = out_bits;
     ix->rounds = last_round;
     ix->round_cap = o->round_cap;
     ix->truncated = truncated;
     ix->entries = B.entries;
     ix->saturated = nsat;
-    uint32_t maxd = 0;
-    for (size_t r = 0; r < B.stats.size(); r++)
-        if (B.stats[r].kept) maxd = (uint32_t)r;
     ix->max_dist = maxd;
     ix->vbase.assign(B.vbase.begin(), B.vbase.end());
     ix->gn = B.gn;
@@ -2188,6 +2240,23 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         uint64_t b = B.arena.detach(blk);
         ix->blocks.emplace_back(blk, (size_t)b);
         ix->index_bytes += b;
+    }
+    if (B.reduced) {
+        ShellResult &R = B.shell;
+        ix->reduced = true;
+        ix->obase = B.obase;
+        ix->on = B.on;
+        ix->red_root = R.root;
+        ix->red_depth = R.depth;
+        ix->red_parent = R.parent;
+        ix->core_vid = R.core_vid;
+        ix->fringe = R.fringe;
+        ix->fringe_depth = R.max_depth;
+        for (void *blk : {(void *)R.root, (void *)R.depth, (void *)R.parent, (void *)R.core_vid}) {
+            uint64_t b = B.arena.detach(blk);
+            ix->blocks.emplace_back(blk, (size_t)b);
+            ix->index_bytes += b;
+        }
     }
     *out = ix;
     return SPC_OK;

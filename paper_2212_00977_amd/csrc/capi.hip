@@ -79,7 +79,10 @@ spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
     out->entries = ix->entries;
     out->rounds = ix->rounds;
     out->max_dist = ix->max_dist;
-    out->dist_bits = ix->dist_bits;
+    out->dist_bits = ix->out_bits;
+    out->label_bits = ix->dist_bits;
+    out->fringe_vertices = ix->fringe;
+    out->fringe_depth = ix->fringe_depth;
     out->truncated = ix->truncated ? 1u : 0u;
     out->saturated_entries = ix->saturated;
     out->index_bytes = ix->index_bytes;
@@ -165,6 +168,12 @@ spc_status spc_export_labels(const spc_index *ix, uint32_t graph_id, uint64_t *o
                              void *stream) {
     return spc::export_impl(ix, graph_id, off, hub, dist, count, order, on_device,
                             static_cast<hipStream_t>(stream));
+}
+
+spc_status spc_export_reduction(const spc_index *ix, uint32_t graph_id, uint32_t *root,
+                                uint32_t *depth, uint32_t *parent, int32_t on_device, void *stream) {
+    return spc::export_reduction_impl(ix, graph_id, root, depth, parent, on_device,
+                                      static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

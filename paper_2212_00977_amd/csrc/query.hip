@@ -8,6 +8,10 @@
 // past it, several tiles per round of loads, each entry binary-searched in
 // LDS.  The loads of a round are independent, so a query waits for a few
 // memory round trips per slice rather than one per tile.
+//
+// On an index with the 1-shell cut off, s and t are first mapped to their
+// roots: equal roots leave the tree path as the only shortest path; other
+// roots are joined as above and the two depths added.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +33,10 @@ struct QueryArgs {
     uint64_t nq;
     uint32_t vbase, gn;     // graph view
     uint32_t cap;           // round cap of a truncated index, 0 otherwise
+    // 1-shell (null when not reduced): per input vertex, core id of the
+    // root, depth, parent; the graph's input vertex range
+    const uint32_t *red_root, *red_depth, *red_parent;
+    uint32_t obase, on;
     void *dist_out;
     uint64_t *count_out;
     uint8_t *flags_out;
@@ -36,10 +44,11 @@ struct QueryArgs {
 
 // kQStage: L(s) entries staged per wave; kQTiles: L(t) tiles of 64
 // requested together.  The pair is a launch configuration (see kQueryCfg).
-template <int DB, uint32_t kQStage, int kQTiles>
+// DB: label distance bits; OB: output distance bits.
+template <int DB, int OB, uint32_t kQStage, int kQTiles>
 __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     using E = typename Ent<DB>::T;
-    using DT = typename std::conditional<DB == 8, uint8_t, uint16_t>::type;
+    using DT = typename std::conditional<OB == 8, uint8_t, uint16_t>::type;
     __shared__ E stage[kWaves][kQStage];
     const uint64_t q = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (q >= a.nq) return;
@@ -48,7 +57,8 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     const E *hd = static_cast<const E *>(a.lab_hd);
     const uint32_t s = a.s[q], t = a.t[q];
     const DT kInf = (DT)~(DT)0;
-    if (s >= a.gn || t >= a.gn) {
+    const uint32_t lim = a.red_root ? a.on : a.gn;
+    if (s >= lim || t >= lim) {
         if (lane == 0) {
             static_cast<DT *>(a.dist_out)[q] = kInf;
             a.count_out[q] = 0;
@@ -56,7 +66,35 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
         }
         return;
     }
-    const uint32_t rs = a.rank_of[a.vbase + s], rt = a.rank_of[a.vbase + t];
+    uint32_t rs, rt, extra = 0;
+    if (a.red_root) {
+        const uint32_t gs = a.obase + s, gt = a.obase + t;
+        const uint32_t cs = a.red_root[gs], ct = a.red_root[gt];
+        if (cs == ct) {
+            // one tree: climb to the lowest common ancestor (every step
+            // lowers the depth by one, so the walk ends by depth 0)
+            if (lane == 0) {
+                uint32_t x = gs, y = gt, dx = a.red_depth[gs], dy = a.red_depth[gt];
+                const uint32_t tot = dx + dy;
+                for (; dx > dy; dx--) x = a.red_parent[x];
+                for (; dy > dx; dy--) y = a.red_parent[y];
+                for (; x != y && dx > 0; dx--) {
+                    x = a.red_parent[x];
+                    y = a.red_parent[y];
+                }
+                static_cast<DT *>(a.dist_out)[q] = (DT)(tot - 2 * dx);
+                a.count_out[q] = 1;
+                if (a.flags_out) a.flags_out[q] = 0;
+            }
+            return;
+        }
+        extra = a.red_depth[gs] + a.red_depth[gt];
+        rs = a.rank_of[cs];
+        rt = a.rank_of[ct];
+    } else {
+        rs = a.rank_of[a.vbase + s];
+        rt = a.rank_of[a.vbase + t];
+    }
     const uint64_t as = a.lab_off[rs], na = a.lab_off[rs + 1] - as;
     const uint64_t bs = a.lab_off[rt], nb = a.lab_off[rt + 1] - bs;
     uint32_t best = 0xFFFFFFFFu;
@@ -161,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
             fl |= SPC_FLAG_UNREACHABLE;
             if (a.cap) fl |= SPC_FLAG_HORIZON;
         } else {
-            dout = (DT)mn;
+            dout = (DT)(mn + extra);
             cout = part;
             if (part == kSat) fl |= SPC_FLAG_SATURATED;
             if (a.cap && mn > a.cap) fl |= SPC_FLAG_HORIZON;
@@ -188,9 +226,22 @@ __global__ void k_export_ent(const typename Ent<DB>::T *hd, const uint64_t *cnt,
     if (dist) dist[i] = (uint16_t)e_dist<DB>(e);
     if (count) count[i] = cnt[e0 + i];
 }
-__global__ void k_export_order(const uint32_t *order, uint32_t vbase, uint32_t n, uint32_t *out) {
+// rank -> vertex id of the graph; through core -> input ids when reduced
+__global__ void k_export_order(const uint32_t *order, uint32_t vbase, uint32_t n,
+                               const uint32_t *core_vid, uint32_t obase, uint32_t *out) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = order[vbase + i] - vbase;
+    if (i < n) out[i] = core_vid ? core_vid[order[vbase + i]] - obase : order[vbase + i] - vbase;
+}
+// the 1-shell of one graph in its input ids (identity when not reduced)
+__global__ void k_export_shell(const uint32_t *root, const uint32_t *depth, const uint32_t *parent,
+                               const uint32_t *core_vid, uint32_t obase, uint32_t n, uint32_t *root_out,
+                               uint32_t *depth_out, uint32_t *parent_out) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = obase + i;
+    if (root_out) root_out[i] = root ? core_vid[root[v]] - obase : i;
+    if (depth_out) depth_out[i] = depth ? depth[v] : 0;
+    if (parent_out) parent_out[i] = parent ? parent[v] - obase : i;
 }
 
 inline uint32_t grid1(uint64_t items) { return (uint32_t)((items + kBlock - 1) / kBlock); }
@@ -204,26 +255,30 @@ constexpr QueryCfg kQueryCfg[] = {{512, 2}, {512, 1}, {512, 4}, {256, 1}, {256, 
                                   {1024, 1}, {1024, 2}, {2048, 1}};
 constexpr uint32_t kQueryCfgs = sizeof(kQueryCfg) / sizeof(kQueryCfg[0]);
 
-template <int DB>
+template <int DB, int OB>
 void launch_cfg(uint32_t cfg, dim3 g, hipStream_t st, const QueryArgs &c) {
     switch (cfg) {
-        case 1: hipLaunchKernelGGL((k_query<DB, 512, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 2: hipLaunchKernelGGL((k_query<DB, 512, 4>), g, dim3(kBlock), 0, st, c); break;
-        case 3: hipLaunchKernelGGL((k_query<DB, 256, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 4: hipLaunchKernelGGL((k_query<DB, 256, 2>), g, dim3(kBlock), 0, st, c); break;
-        case 5: hipLaunchKernelGGL((k_query<DB, 1024, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 6: hipLaunchKernelGGL((k_query<DB, 1024, 2>), g, dim3(kBlock), 0, st, c); break;
-        case 7: hipLaunchKernelGGL((k_query<DB, 2048, 1>), g, dim3(kBlock), 0, st, c); break;
-        default: hipLaunchKernelGGL((k_query<DB, 512, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 1: hipLaunchKernelGGL((k_query<DB, OB, 512, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 2: hipLaunchKernelGGL((k_query<DB, OB, 512, 4>), g, dim3(kBlock), 0, st, c); break;
+        case 3: hipLaunchKernelGGL((k_query<DB, OB, 256, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 4: hipLaunchKernelGGL((k_query<DB, OB, 256, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 5: hipLaunchKernelGGL((k_query<DB, OB, 1024, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 6: hipLaunchKernelGGL((k_query<DB, OB, 1024, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 7: hipLaunchKernelGGL((k_query<DB, OB, 2048, 1>), g, dim3(kBlock), 0, st, c); break;
+        default: hipLaunchKernelGGL((k_query<DB, OB, 512, 2>), g, dim3(kBlock), 0, st, c); break;
     }
 }
 
-spc_status launch_query(uint32_t dist_bits, uint32_t cfg, const QueryArgs &c, hipStream_t st) {
+// 16-bit labels always come with 16-bit outputs
+spc_status launch_query(uint32_t dist_bits, uint32_t out_bits, uint32_t cfg, const QueryArgs &c,
+                        hipStream_t st) {
     const dim3 g((uint32_t)((c.nq + kWaves - 1) / kWaves));
-    if (dist_bits == 8)
-        launch_cfg<8>(cfg, g, st, c);
+    if (dist_bits == 16)
+        launch_cfg<16, 16>(cfg, g, st, c);
+    else if (out_bits == 16)
+        launch_cfg<8, 16>(cfg, g, st, c);
     else
-        launch_cfg<16>(cfg, g, st, c);
+        launch_cfg<8, 8>(cfg, g, st, c);
     SPC_LAUNCHED();
     return SPC_OK;
 }
@@ -263,7 +318,7 @@ spc_status query_cfg_info(uint32_t cfg, uint32_t *stage, uint32_t *tiles) {
 spc_status tune_queries_impl(spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                              uint64_t nq, hipStream_t st, uint32_t *cfg_out) {
     if (!ix || graph_id >= ix->gn.size() || !s || !t || nq == 0) return SPC_ERR_INVALID_ARG;
-    const size_t dsz = ix->dist_bits == 8 ? 1 : 2;
+    const size_t dsz = ix->out_bits == 8 ? 1 : 2;
     // one output set per side of the comparison, in one block:
     // dist | count | flags, reference then candidate
     const uint64_t per = (nq * (dsz + 8 + 1) + 255) & ~uint64_t(255);
@@ -343,13 +398,18 @@ spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, 
     a.vbase = ix->vbase[graph_id];
     a.gn = ix->gn[graph_id];
     a.cap = ix->truncated ? ix->round_cap : 0;
+    a.red_root = ix->reduced ? ix->red_root : nullptr;
+    a.red_depth = ix->red_depth;
+    a.red_parent = ix->red_parent;
+    a.obase = ix->reduced ? ix->obase[graph_id] : 0;
+    a.on = ix->reduced ? ix->on[graph_id] : 0;
     a.dist_out = dist_out;
     a.count_out = count_out;
     a.flags_out = flags_out;
     // one wave per query: launches of at most 2^24 queries keep the
     // work-item count of each below 2^32
     constexpr uint64_t kChunk = 1ull << 24;
-    const size_t dsz = ix->dist_bits == 8 ? 1 : 2;
+    const size_t dsz = ix->out_bits == 8 ? 1 : 2;
     for (uint64_t q0 = 0; q0 < nq; q0 += kChunk) {
         const uint64_t nc = std::min(kChunk, nq - q0);
         QueryArgs c = a;
@@ -359,7 +419,7 @@ spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, 
         c.dist_out = static_cast<char *>(dist_out) + q0 * dsz;
         c.count_out = count_out + q0;
         c.flags_out = flags_out ? flags_out + q0 : nullptr;
-        SPC_TRY(launch_query(ix->dist_bits, cfg, c, st));
+        SPC_TRY(launch_query(ix->dist_bits, ix->out_bits, cfg, c, st));
     }
     return SPC_OK;
 }
@@ -411,7 +471,9 @@ spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, ui
         SPC_LAUNCHED();
     }
     if (order && n) {
-        hipLaunchKernelGGL(k_export_order, dim3(grid1(n)), dim3(kBlock), 0, st, ix->order, vb, n, d_ord);
+        hipLaunchKernelGGL(k_export_order, dim3(grid1(n)), dim3(kBlock), 0, st, ix->order, vb, n,
+                           ix->reduced ? ix->core_vid : nullptr, ix->reduced ? ix->obase[graph_id] : 0,
+                           d_ord);
         SPC_LAUNCHED();
     }
     if (!on_device) {
@@ -420,6 +482,30 @@ spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, ui
         if (dist && ne) SPC_HIP(hipMemcpyAsync(dist, d_dist, ne * 2, hipMemcpyDeviceToHost, st));
         if (count && ne) SPC_HIP(hipMemcpyAsync(count, d_cnt, ne * 8, hipMemcpyDeviceToHost, st));
         if (order && n) SPC_HIP(hipMemcpyAsync(order, d_ord, (uint64_t)n * 4, hipMemcpyDeviceToHost, st));
+    }
+    SPC_HIP(hipStreamSynchronize(st));
+    return SPC_OK;
+}
+
+spc_status export_reduction_impl(const spc_index *ix, uint32_t graph_id, uint32_t *root,
+                                 uint32_t *depth, uint32_t *parent, int32_t on_device, hipStream_t st) {
+    if (!ix || graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
+    const uint32_t n = ix->reduced ? ix->on[graph_id] : ix->gn[graph_id];
+    const uint32_t ob = ix->reduced ? ix->obase[graph_id] : ix->vbase[graph_id];
+    if (n == 0) return SPC_OK;
+    uint32_t *d[3] = {root, depth, parent};
+    Arena tmp(0, st);
+    if (!on_device)
+        for (auto &p : d)
+            if (p) SPC_TRY(tmp.alloc(&p, n));
+    hipLaunchKernelGGL(k_export_shell, dim3(grid1(n)), dim3(kBlock), 0, st,
+                       ix->reduced ? ix->red_root : nullptr, ix->reduced ? ix->red_depth : nullptr,
+                       ix->reduced ? ix->red_parent : nullptr, ix->core_vid, ob, n, d[0], d[1], d[2]);
+    SPC_LAUNCHED();
+    if (!on_device) {
+        uint32_t *h[3] = {root, depth, parent};
+        for (int i = 0; i < 3; i++)
+            if (h[i]) SPC_HIP(hipMemcpyAsync(h[i], d[i], (uint64_t)n * 4, hipMemcpyDeviceToHost, st));
     }
     SPC_HIP(hipStreamSynchronize(st));
     return SPC_OK;

@@ -310,6 +310,22 @@ spc_status radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 // ---------------------------------------------------------------------------
 // The index
 // ---------------------------------------------------------------------------
+// 1-shell reduction of a union CSR (reduce.hip).  Device arrays come from
+// the caller's arena.
+struct ShellResult {
+    uint64_t *off = nullptr;  // core CSR [N+1], core ids
+    uint32_t *col = nullptr;  // [NNZ]
+    uint32_t *ord = nullptr;  // the given order restricted to the core, or null
+    uint64_t *tie = nullptr;  // the given tie keys restricted to the core, or null
+    // per input vertex: core id of root(v), depth, parent (input id)
+    uint32_t *root = nullptr, *depth = nullptr, *parent = nullptr;
+    uint32_t *core_vid = nullptr;  // core id -> input id
+    std::vector<uint32_t> cbase;   // core id range of each graph, k+1 entries
+    uint32_t N = 0;
+    uint64_t NNZ = 0, fringe = 0;
+    uint32_t max_depth = 0;
+};
+
 struct RoundCounters {
     uint64_t raw = 0, merged = 0, kept = 0, scanned = 0;
     uint64_t staged = 0, row_bytes = 0, headers = 0;
@@ -343,12 +359,26 @@ struct spc_index {
     uint64_t alg_bytes_round_kernel = 0;
     uint64_t round_kernel_launches = 0;
     uint32_t query_cfg = 0;  // query launch configuration (query.hip)
+    uint32_t out_bits = 8;   // width of query dist outputs
+    // SPC_REDUCE_ONE_SHELL: input vertex ranges [obase[i], obase[i] + on[i])
+    // of the graphs, and per input vertex (union ids) the core id of its
+    // root, its depth and its parent; core id -> input id
+    bool reduced = false;
+    std::vector<uint32_t> obase, on;
+    uint32_t *red_root = nullptr, *red_depth = nullptr, *red_parent = nullptr;
+    uint32_t *core_vid = nullptr;
+    uint64_t fringe = 0;
+    uint32_t fringe_depth = 0;
 };
 
 namespace spc {
 // build.hip
 spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *opts, hipStream_t st,
                       spc_index **out);
+// reduce.hip
+spc_status one_shell(Arena &ar, hipStream_t st, uint64_t *ws, uint32_t N, uint64_t NNZ,
+                     const uint64_t *off, const uint32_t *col, const uint32_t *ord, const uint64_t *tie,
+                     const std::vector<uint32_t> &vbase, ShellResult *R);
 // query.hip
 spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                       uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
@@ -362,4 +392,6 @@ spc_status query_cfg_info(uint32_t cfg, uint32_t *stage, uint32_t *tiles);
 spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, uint32_t *hub,
                        uint16_t *dist, uint64_t *count, uint32_t *order, int32_t on_device,
                        hipStream_t st);
+spc_status export_reduction_impl(const spc_index *ix, uint32_t graph_id, uint32_t *root,
+                                 uint32_t *depth, uint32_t *parent, int32_t on_device, hipStream_t st);
 }  // namespace spc

@@ -15,14 +15,16 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "lib")
 LIBPATH = os.path.join(LIBDIR, "libspc.so")
-SOURCES = ["memory.hip", "primitives.hip", "build.hip", "query.hip", "order.hip", "capi.hip"]
+SOURCES = ["memory.hip", "primitives.hip", "build.hip", "reduce.hip", "query.hip", "order.hip",
+           "capi.hip"]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_free",
            "spc_index_stats", "spc_round_stats", "spc_round_profile", "spc_graph_entries", "spc_export_labels",
            "spc_status_string", "spc_release_cached_memory", "spc_query_config_count",
-           "spc_query_config_info", "spc_tune_queries", "spc_set_query_config", "spc_hybrid_order"]
+           "spc_query_config_info", "spc_tune_queries", "spc_set_query_config", "spc_hybrid_order",
+           "spc_export_reduction"]
 
 
 # A test build with tiny on-chip tables (8-bit hash of 128 slots for the
@@ -59,7 +61,8 @@ class SpcStats(C.Structure):
                 ("ms_rounds", C.c_double), ("ms_finalize", C.c_double), ("ms_total", C.c_double),
                 ("ms_round_kernel", C.c_double), ("alg_bytes_round_kernel", C.c_uint64),
                 ("round_kernel_launches", C.c_uint64), ("query_config", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("label_bits", C.c_uint32), ("fringe_vertices", C.c_uint64),
+                ("fringe_depth", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class SpcGraph(C.Structure):
@@ -70,7 +73,7 @@ class SpcGraph(C.Structure):
 
 class SpcBuildOpts(C.Structure):
     _fields_ = [("dist_bits", C.c_uint32), ("round_cap", C.c_uint32),
-                ("mem_budget", C.c_uint64), ("validate", C.c_uint32), ("reserved", C.c_uint32)]
+                ("mem_budget", C.c_uint64), ("validate", C.c_uint32), ("reduce", C.c_uint32)]
 
 
 _lib = None
@@ -116,6 +119,8 @@ def load(path: str | None = None):
     L.spc_tune_queries.restype = C.c_int
     L.spc_hybrid_order.argtypes = [C.POINTER(SpcGraph), u32, vp, C.POINTER(u32)]
     L.spc_hybrid_order.restype = C.c_int
+    L.spc_export_reduction.argtypes = [vp, u32, vp, vp, vp, i32, vp]
+    L.spc_export_reduction.restype = C.c_int
     L.spc_set_query_config.argtypes = [vp, u32]
     L.spc_set_query_config.restype = C.c_int
     L.spc_status_string.argtypes = [C.c_int]

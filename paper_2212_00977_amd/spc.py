@@ -92,6 +92,7 @@ class BuildOptions:
     round_cap: int = 0
     mem_budget: int = 0
     validate: bool = True
+    one_shell: bool = False  # SPC_REDUCE_ONE_SHELL: label the 2-core only
 
     def struct(self):
         o = native.SpcBuildOpts()
@@ -99,17 +100,18 @@ class BuildOptions:
         o.round_cap = self.round_cap
         o.mem_budget = self.mem_budget
         o.validate = 1 if self.validate else 0
-        o.reserved = 0
+        o.reduce = 1 if self.one_shell else 0
         return o
 
 
 class Index:
     """A built SPC label index resident in device memory."""
 
-    def __init__(self, handle: C.c_void_p, device):
+    def __init__(self, handle: C.c_void_p, device, sizes=None):
         self._h = handle
         self.device = device
         self._stats = None
+        self._sizes = sizes  # input vertex count of each graph
 
     def __del__(self):
         self.free()
@@ -231,6 +233,22 @@ class Index:
         _check(rc, "spc_export_labels")
         return dict(off=off, hub=hub[:e], dist=dist[:e], count=cnt[:e], order=order[:n])
 
+    def export_reduction(self, graph_id: int = 0):
+        """The 1-shell of one graph (host numpy, input vertex ids): root
+        (shr), depth, parent per vertex; identity for an unreduced index."""
+        n = self.input_vertices(graph_id)
+        out = [np.zeros(max(n, 1), dtype=np.uint32) for _ in range(3)]
+        rc = native.load().spc_export_reduction(self.handle, graph_id, *(a.ctypes.data for a in out),
+                                                0, _stream_handle(None))
+        _check(rc, "spc_export_reduction")
+        return dict(root=out[0][:n], depth=out[1][:n], parent=out[2][:n])
+
+    def input_vertices(self, graph_id: int = 0) -> int:
+        """Vertices of graph `graph_id` as given to the build."""
+        if self._sizes is None:
+            raise RuntimeError("input sizes unknown for this handle")
+        return self._sizes[graph_id]
+
     def export_device(self, graph_id: int = 0):
         """Same as export() into device tensors (int32/int16/int64 bit views)."""
         torch = _torch()
@@ -260,7 +278,7 @@ def build_index(off, adj, order=None, tie_key=None, opts: BuildOptions | None = 
     h = C.c_void_p()
     rc = native.load().spc_build_index(C.byref(g), C.byref(o), _stream_handle(stream), C.byref(h))
     _check(rc, "spc_build_index")
-    return Index(h, device)
+    return Index(h, device, [int(g.n)])
 
 
 def build_graph(graph, opts: BuildOptions | None = None, device=None, stream=None) -> Index:
@@ -282,7 +300,7 @@ def build_index_batch(graphs, opts: BuildOptions | None = None, device=None, str
     rc = native.load().spc_build_index_batch(arr, len(graphs), C.byref(o), _stream_handle(stream),
                                              C.byref(h))
     _check(rc, "spc_build_index_batch")
-    return Index(h, device)
+    return Index(h, device, [int(g.n) for g in graphs])
 
 
 def hybrid_order(off, adj, delta: int = 5):

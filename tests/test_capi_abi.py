@@ -73,7 +73,7 @@ def test_bad_options_rejected_on_host(lib):
     o.dist_bits = 12
     assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
     o.dist_bits = 0
-    o.reserved = 7
+    o.reduce = 6  # only SPC_REDUCE_ONE_SHELL is defined
     assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
     assert out.value is None
 
