@@ -124,10 +124,12 @@ def bench_served(args, dev, log):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
+    ix = spc.build_index(off_d, adj_d, device=dev, stream=stream,
+                         opts=spc.BuildOptions(one_shell=args.one_shell))
     build_ms = (time.perf_counter() - t0) * 1e3
     st = ix.stats()
-    log(f"build {build_ms:.0f} ms, {st['entries']} entries, peak {st['peak_build_bytes'] / 2**30:.1f} GiB")
+    log(f"build {build_ms:.0f} ms, {st['entries']} entries, fringe {st['fringe_vertices']}, "
+        f"peak {st['peak_build_bytes'] / 2**30:.1f} GiB")
     del off_d, adj_d
     spc.release_cached_memory()
     torch.cuda.empty_cache()
@@ -170,7 +172,8 @@ def bench_served(args, dev, log):
                                   "in 1..65536; value = served q/s at 1.0x saturation",
                       "n": g.n, "m": g.m, "entries": st["entries"], "rounds": st["rounds"],
                       "requests_per_level": args.serve_requests, "max_batch": args.serve_max_batch,
-                      "streams": args.serve_streams, "parallelism": "single-gpu"},
+                      "streams": args.serve_streams, "one_shell": args.one_shell,
+                      "fringe_vertices": st["fringe_vertices"], "parallelism": "single-gpu"},
            "p50_ms": one["p50_ms"], "p99_ms": one["p99_ms"],
            "build_ms": build_ms, "build_entries_per_s": st["entries"] / (build_ms * 1e-3),
            "query_config": dict(zip(("stage", "tiles"), spc.query_configs()[qcfg])),
@@ -274,9 +277,11 @@ def bench_batch(args, dev, log):
     t_d = [torch.from_numpy(t.view(np.int32)).to(dev) for _, t in qs]
     torch.cuda.synchronize()
 
+    opts = spc.BuildOptions(one_shell=args.one_shell)
+
     def batched():
         t0 = time.perf_counter()
-        ix = spc.build_index_batch(dev_graphs, device=dev, stream=stream)
+        ix = spc.build_index_batch(dev_graphs, device=dev, stream=stream, opts=opts)
         t1 = time.perf_counter()
         return ix, (t1 - t0) * 1e3
 
@@ -284,7 +289,7 @@ def bench_batch(args, dev, log):
         t0 = time.perf_counter()
         entries = 0
         for g in dev_graphs:
-            ix = spc.build_index(g.off, g.adj, device=dev, stream=stream)
+            ix = spc.build_index(g.off, g.adj, device=dev, stream=stream, opts=opts)
             entries += ix.stats()["entries"]
             ix.free()
         return entries, (time.perf_counter() - t0) * 1e3
@@ -319,7 +324,8 @@ def bench_batch(args, dev, log):
            "config": {"workload": f"{len(graphs)} R-MAT graphs, scales 10..16, ef 8, seed 4, "
                                   "one batched build + 10,000 queries per graph",
                       "graphs": len(graphs), "n": N, "m": M, "entries": entries,
-                      "rounds": st["rounds"], "parallelism": "single-gpu"},
+                      "rounds": st["rounds"], "one_shell": args.one_shell,
+                      "fringe_vertices": st["fringe_vertices"], "parallelism": "single-gpu"},
            "batched_build_ms": bms, "plain_build_ms": pms,
            "plain_entries_per_s": pe / (pms * 1e-3), "batched_speedup": pms / bms,
            "query_ms": qms, "queries_per_s": 10000 * len(graphs) / (qms * 1e-3)}
@@ -404,6 +410,8 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--no-one-shell", action="store_true",
                     help="skip the side measurement of the 1-shell reduced build")
+    ap.add_argument("--one-shell", action="store_true",
+                    help="build with the 1-shell reduction (rmat_served, rmat_batch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")

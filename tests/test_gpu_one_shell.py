@@ -14,6 +14,16 @@ from tests.gpu_util import all_pairs, assert_labels_equal, gpu_query
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(scope="module")
+def spc():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2212_00977_amd import spc as mod
+
+    return mod
+
+
 def _say(msg):
     print(f"[case] {msg}", flush=True)
 
