@@ -4,6 +4,8 @@ the oracle's 1-shell; the core labels equal the oracle's labels of the core
 subgraph; every answer equals the oracle's unreduced index (itself pinned to
 path enumeration), including tree paths inside the fringe and tree
 components; batches, explicit orders, tie keys and truncated builds."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -78,8 +80,7 @@ def check_reduced(spc, g, opts=None, queries=20000, order=None, tie_key=None, ca
     assert st["fringe_vertices"] == int((~sh.core).sum())
     assert st["fringe_depth"] == (int(sh.depth.max()) if g.n else 0)
     lab = ix.export()
-    ref = red.labels
-    ref.order = red.core_ids[ref.order]  # core ids -> input ids
+    ref = dataclasses.replace(red.labels, order=red.core_ids[red.labels.order])  # core -> input ids
     assert_labels_equal(lab, ref, g.name)
     assert st["n"] == int(sh.core.sum()) and st["entries"] == ref.entries
     if g.n:
@@ -138,8 +139,7 @@ def test_reduced_batch(spc):
         assert np.array_equal(ex["root"], red.shell.root), g.name
         assert np.array_equal(ex["depth"], red.shell.depth), g.name
         assert np.array_equal(ex["parent"], red.shell.parent), g.name
-        ref = red.labels
-        ref.order = red.core_ids[ref.order]
+        ref = dataclasses.replace(red.labels, order=red.core_ids[red.labels.order])
         assert_labels_equal(ix.export(i), ref, g.name)
         s, t = inputs.queries(g.n, 5000, seed=i)
         d, c, f = gpu_query(ix, s, t, graph_id=i)
