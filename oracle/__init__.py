@@ -411,3 +411,167 @@ def build_reduced(off, adj, order=None, tie_key=None, depth_cap: int = 0) -> Red
     coff, cadj, ids, cid, cord, ctie = core_subgraph(off, adj, sh.core, order, tie_key)
     lab = build(coff, cadj, order=cord, tie_key=ctie, depth_cap=depth_cap)
     return ReducedIndex(sh, ids, cid, lab)
+
+
+def twin_classes(off, adj) -> np.ndarray:
+    """Classes of the neighbourhood-equivalence relation of the paper's
+    Section "Reduction by Equivalence Relation": u ~ v when
+    nbr(u) minus {v} equals nbr(v) minus {u}.  For two vertices that are not
+    adjacent this says nbr(u) = nbr(v); for adjacent ones, nbr(u) + {u} =
+    nbr(v) + {v}; vertices are grouped by those two sets.  Returns rep[v]:
+    the smallest vertex of v's class."""
+    off, adj = _u64(off), _u32(adj)
+    n = off.shape[0] - 1
+    nbr = [frozenset(int(w) for w in adj[off[v]:off[v + 1]] if int(w) != v) for v in range(n)]
+    rep = np.arange(n, dtype=np.uint32)
+    first_open, first_closed = {}, {}
+    for v in range(n):
+        o = nbr[v]
+        c = o | {v}
+        if o in first_open:
+            rep[v] = first_open[o]
+        elif c in first_closed:
+            rep[v] = first_closed[c]
+        else:
+            first_open[o] = v
+            first_closed[c] = v
+    return rep
+
+
+def weighted_labels(off, adj, weight, order=None, tie_key=None, depth_cap: int = 0) -> Labels:
+    """Label index of a graph whose vertices carry weights, from the
+    definition (Python big integers, small graphs only).  An entry (h, d, c)
+    of L(v) exists when some shortest v-h path has every vertex other than
+    h ranked below h (a trough path); c sums, over those paths, the product
+    of the weights of the path's inner vertices (both ends excluded),
+    saturated at 2^64-1.  With every weight 1 this is the plain index."""
+    from collections import deque
+
+    off, adj = _u64(off), _u32(adj)
+    n = off.shape[0] - 1
+    if order is None:
+        order = degree_order(off, tie_key)
+    order = _u32(order)
+    rank = np.zeros(n, dtype=np.int64)
+    rank[order] = np.arange(n)
+    nbr = [[int(w) for w in adj[off[v]:off[v + 1]]] for v in range(n)]
+    w = [int(x) for x in weight]
+    lab = [[] for _ in range(n)]  # per rank: (hub rank, dist, count)
+    for hr in range(n):
+        h = int(order[hr])
+        full = {h: 0}
+        q = deque([h])
+        while q:
+            u = q.popleft()
+            for x in nbr[u]:
+                if x not in full:
+                    full[x] = full[u] + 1
+                    q.append(x)
+        dist, sig = {h: 0}, {h: 1}
+        q = deque([h])
+        while q:
+            u = q.popleft()
+            if depth_cap and dist[u] >= depth_cap:
+                continue
+            f = 1 if u == h else w[u]
+            for x in nbr[u]:
+                if rank[x] <= hr:
+                    continue
+                if x not in dist:
+                    dist[x] = dist[u] + 1
+                    sig[x] = 0
+                    q.append(x)
+                if dist[x] == dist[u] + 1:
+                    sig[x] += sig[u] * f
+        for v, dv in dist.items():
+            if dv == full[v]:
+                lab[int(rank[v])].append((hr, dv, min(sig[v], SAT)))
+    offs = np.zeros(n + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(x) for x in lab])
+    ent = [e for x in lab for e in sorted(x)]
+    hub = np.array([e[0] for e in ent], dtype=np.uint32)
+    dst = np.array([e[1] for e in ent], dtype=np.uint32)
+    cnt = np.array([e[2] for e in ent], dtype=np.uint64)
+    return Labels(n, offs, hub, dst, cnt, order, int(dst.max()) + 1 if ent else 0, n)
+
+
+def weighted_query(lab: Labels, weight_by_rank, rs, rt):
+    """Query over weighted labels (rank-space ids): least d_s + d_t over
+    common hubs; the count sums c_s c_t, times the hub's weight when the hub
+    is inside the path (not s or t itself)."""
+    out_d, out_c = [], []
+    for a, b in zip((int(x) for x in rs), (int(x) for x in rt)):
+        la = {int(h): (int(d), int(c)) for h, d, c in zip(lab.hub[lab.off[a]:lab.off[a + 1]],
+                                                         lab.dist[lab.off[a]:lab.off[a + 1]],
+                                                         lab.count[lab.off[a]:lab.off[a + 1]])}
+        best, tot = INF, 0
+        for h, d, c in zip(lab.hub[lab.off[b]:lab.off[b + 1]], lab.dist[lab.off[b]:lab.off[b + 1]],
+                           lab.count[lab.off[b]:lab.off[b + 1]]):
+            h = int(h)
+            if h not in la:
+                continue
+            dd = la[h][0] + int(d)
+            f = 1 if h in (a, b) else int(weight_by_rank[h])
+            x = la[h][1] * int(c) * f
+            if dd < best:
+                best, tot = dd, x
+            elif dd == best:
+                tot += x
+        out_d.append(best)
+        out_c.append(min(tot, SAT))
+    return np.array(out_d, dtype=np.uint32), np.array(out_c, dtype=np.uint64)
+
+
+@dataclass
+class TwinIndex:
+    """Equivalence-reduced index: one representative per class, weighted by
+    the class size, and the weighted labels of the quotient graph."""
+    rep: np.ndarray       # input vertex -> its class's representative (smallest id)
+    cid: np.ndarray       # input vertex -> quotient id (representatives only)
+    ids: np.ndarray       # quotient id -> input vertex
+    weight: np.ndarray    # quotient id -> class size
+    clique: np.ndarray    # input vertex: its class is a clique (adjacent twins)
+    degree: np.ndarray    # input degree
+    labels: Labels        # weighted labels of the quotient graph (quotient ids)
+
+    def query(self, s, t):
+        """Query rule: s = t gives (0, 1); two members of one class are
+        adjacent (1, 1) or share every neighbour (2, degree); otherwise the
+        weighted query between the representatives, which equals the
+        input graph's answer because a shortest path meets each class at
+        most once and any member of a class can stand for the one used."""
+        s, t = _u32(s), _u32(t)
+        rank = self.labels.rank_of()
+        wr = np.zeros(self.weight.shape[0], dtype=np.uint64)
+        wr[rank] = self.weight
+        d, c = weighted_query(self.labels, wr, rank[self.cid[self.rep[s]]], rank[self.cid[self.rep[t]]])
+        for i in range(s.shape[0]):
+            a, b = int(s[i]), int(t[i])
+            if a == b:
+                d[i], c[i] = 0, 1
+            elif self.rep[a] == self.rep[b]:
+                if self.clique[a]:
+                    d[i], c[i] = 1, 1
+                elif self.degree[a] == 0:
+                    d[i], c[i] = INF, 0
+                else:
+                    d[i], c[i] = 2, int(self.degree[a])
+        return d, c
+
+
+def build_twin_reduced(off, adj, order=None, tie_key=None, depth_cap: int = 0) -> TwinIndex:
+    """Neighbourhood-equivalence reduction, then the weighted labels of the
+    quotient graph (the subgraph induced by the representatives; its own
+    degree order unless an order is given, which is then restricted)."""
+    off, adj = _u64(off), _u32(adj)
+    n = off.shape[0] - 1
+    rep = twin_classes(off, adj)
+    keep = rep == np.arange(n)
+    coff, cadj, ids, cid, cord, ctie = core_subgraph(off, adj, keep, order, tie_key)
+    size = np.bincount(rep, minlength=n)[ids].astype(np.uint64)
+    adjset = [set(int(w) for w in adj[off[v]:off[v + 1]]) for v in range(n)]
+    # members of a class of adjacent twins are pairwise adjacent
+    clique = np.array([any(rep[u] == rep[v] for u in adjset[v]) for v in range(n)], dtype=bool)
+    deg = np.diff(off).astype(np.uint64)
+    lab = weighted_labels(coff, cadj, size, order=cord, tie_key=ctie, depth_cap=depth_cap)
+    return TwinIndex(rep, cid, ids, size, clique, deg, lab)
