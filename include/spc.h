@@ -59,7 +59,8 @@ typedef enum {
 #define SPC_FLAG_INVALID 0x8u    /* s or t >= n: dist = INF, count 0 */
 
 /* Index reductions (spc_build_opts.reduce). */
-#define SPC_REDUCE_ONE_SHELL 0x1u /* Section "Reduction by 1-Shell": label only the core */
+#define SPC_REDUCE_ONE_SHELL 0x1u   /* Section "Reduction by 1-Shell": label only the core */
+#define SPC_REDUCE_EQUIVALENCE 0x2u /* Section "Reduction by Equivalence Relation" */
 
 /* An undirected, unweighted graph (Preliminaries: G = (V, E)) as a symmetric
  * CSR: the neighbours of v are col[row_off[v] .. row_off[v+1]).  Every edge
@@ -97,7 +98,16 @@ typedef struct {
      * vertex its tree hangs from; the centre of a tree component, the smaller
      * id of two centres), its depth (distance to root(v)) and its parent (next
      * vertex towards root(v)); queries answer from these and the core labels
-     * (spc_query_batch).  Other bits: SPC_ERR_INVALID_ARG. */
+     * (spc_query_batch).
+     * SPC_REDUCE_EQUIVALENCE (Section "Reduction by Equivalence Relation"):
+     * u and v are twins when nbr(u) minus {v} equals nbr(v) minus {u}; each
+     * class of twins keeps its smallest id as representative, weighted by the
+     * class size, and only the subgraph induced by the representatives is
+     * labelled (its own degree order, or the given order restricted).  Label
+     * counts then weight every path by the product of the class sizes of its
+     * inner vertices, and spc_export_reduction reports root(v) = v's
+     * representative, depth 0.  One reduction per build: any other value of
+     * reduce is SPC_ERR_INVALID_ARG. */
     uint32_t reduce;
 } spc_build_opts;
 
@@ -126,7 +136,8 @@ typedef struct {
     uint32_t label_bits;             /* 8 or 16: width of stored label distances */
     uint64_t fringe_vertices;        /* vertices cut off by SPC_REDUCE_ONE_SHELL (0 otherwise) */
     uint32_t fringe_depth;           /* largest fringe depth */
-    uint32_t reserved;
+    uint32_t twin_vertices;          /* vertices merged into a representative by
+                                        SPC_REDUCE_EQUIVALENCE (0 otherwise) */
 } spc_stats;
 
 /* Build the index of one graph (Alg. 2 rounds until a round adds no entry).
@@ -157,7 +168,13 @@ spc_status spc_build_index_batch(const spc_graph *gs, uint32_t k, const spc_buil
  * distance depth(s) + depth(t) - 2 depth(lowest common ancestor); otherwise
  * the core labels of root(s) and root(t) are joined and depth(s) + depth(t)
  * is added to the distance (the count is unchanged: every s-t path runs
- * through root(s) and root(t), each reached by one path). */
+ * through root(s) and root(t), each reached by one path).
+ * With SPC_REDUCE_EQUIVALENCE: s = t gives (0, 1); two members of one class
+ * are adjacent, (1, 1), or share all their k neighbours, (2, k) (k = 0:
+ * unreachable); otherwise the labels of the two representatives are joined,
+ * each common hub other than the representatives counting once per member
+ * of its class (a shortest path meets a class at most once, and any member
+ * can take the place of the one it meets). */
 spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
                            const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
                            uint8_t *flags_out, void *stream);
@@ -214,8 +231,9 @@ spc_status spc_export_labels(const spc_index *ix, uint32_t graph_id, uint64_t *o
 /* The 1-shell of graph `graph_id` (Section "Reduction by 1-Shell"), per
  * vertex of the input graph: root[v] (shr(v): the core vertex v's tree hangs
  * from, v itself in the core), depth[v] (distance to root[v]), parent[v]
- * (the neighbour of v on the path to root[v], v itself in the core).  An
- * index built without SPC_REDUCE_ONE_SHELL reports every vertex in the core.
+ * (the neighbour of v on the path to root[v], v itself in the core).  Under
+ * SPC_REDUCE_EQUIVALENCE root[v] is v's representative, depth 0, parent v;
+ * an index built without a reduction reports every vertex as its own root.
  * Arrays of the graph's input size n; device pointers when on_device is
  * nonzero, host pointers otherwise; any may be NULL.  Synchronises `stream`. */
 spc_status spc_export_reduction(const spc_index *ix, uint32_t graph_id, uint32_t *root,

@@ -63,6 +63,8 @@ def lib():
         f = getattr(L, nm)
         f.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32]
         f.restype = vp
+    L.oracle_build_definition_weighted.argtypes = [C.c_uint32, _u64p, _u32p, _u64p, C.c_uint32]
+    L.oracle_build_definition_weighted.restype = vp
     L.oracle_build_pruned.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, C.c_uint32,
                                       C.c_double]
     L.oracle_build_pruned.restype = vp
@@ -495,6 +497,16 @@ def weighted_labels(off, adj, weight, order=None, tie_key=None, depth_cap: int =
     return Labels(n, offs, hub, dst, cnt, order, int(dst.max()) + 1 if ent else 0, n)
 
 
+def build_weighted(off, adj, weight, order=None, tie_key=None, depth_cap: int = 0) -> Labels:
+    """weighted_labels in C (the definition, one BFS pair per hub), for
+    graphs of a few thousand vertices; weight is per vertex (input ids)."""
+    n, roff, radj, order = _prep(off, adj, order, tie_key)
+    wr = np.zeros(max(n, 1), dtype=np.uint64)
+    wr[:n] = _u64(weight)[order]
+    h = lib().oracle_build_definition_weighted(n, roff, radj, wr, depth_cap)
+    return _collect(h, n, order, with_stats=False)
+
+
 def weighted_query(lab: Labels, weight_by_rank, rs, rt):
     """Query over weighted labels (rank-space ids): least d_s + d_t over
     common hubs; the count sums c_s c_t, times the hub's weight when the hub
@@ -573,5 +585,6 @@ def build_twin_reduced(off, adj, order=None, tie_key=None, depth_cap: int = 0) -
     # members of a class of adjacent twins are pairwise adjacent
     clique = np.array([any(rep[u] == rep[v] for u in adjset[v]) for v in range(n)], dtype=bool)
     deg = np.diff(off).astype(np.uint64)
-    lab = weighted_labels(coff, cadj, size, order=cord, tie_key=ctie, depth_cap=depth_cap)
+    build_fn = weighted_labels if ids.shape[0] <= 400 else build_weighted
+    lab = build_fn(coff, cadj, size, order=cord, tie_key=ctie, depth_cap=depth_cap)
     return TwinIndex(rep, cid, ids, size, clique, deg, lab)

@@ -325,6 +325,57 @@ oracle_index *oracle_build_definition(uint32_t n, const uint64_t *off, const uin
 }
 
 /* ------------------------------------------------------------------------ */
+/* The definition with vertex weights (Section "Reduction by Equivalence    */
+/* Relation": one vertex stands for a class of twins and carries its size): */
+/* a trough path counts the product of the weights of its inner vertices.   */
+/* ------------------------------------------------------------------------ */
+oracle_index *oracle_build_definition_weighted(uint32_t n, const uint64_t *off, const uint32_t *adj,
+                                               const uint64_t *weight, uint32_t depth_cap)
+{
+    oracle_index *ix = index_new(n);
+    uint32_t *dfull = xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    uint64_t *sfull = xmalloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    uint32_t *dist = xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    uint64_t *sig = xmalloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    uint32_t *queue = xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    for (uint32_t w = 0; w < n; w++) {
+        oracle_bfs_count(n, off, adj, w, 0, depth_cap, dfull, sfull);
+        for (uint32_t i = 0; i < n; i++) {
+            dist[i] = ORACLE_INF;
+            sig[i] = 0;
+        }
+        uint64_t head = 0, tail = 0;
+        dist[w] = 0;
+        sig[w] = 1;
+        queue[tail++] = w;
+        while (head < tail) {
+            uint32_t v = queue[head++];
+            if (depth_cap && dist[v] >= depth_cap) continue;
+            uint64_t f = v == w ? 1 : weight[v]; /* v is inside every path it extends */
+            for (uint64_t k = off[v]; k < off[v + 1]; k++) {
+                uint32_t x = adj[k];
+                if (x <= w) continue; /* only vertices ranked below w */
+                if (dist[x] == ORACLE_INF) {
+                    dist[x] = dist[v] + 1;
+                    queue[tail++] = x;
+                }
+                if (dist[x] == dist[v] + 1) sig[x] = sat_add(sig[x], sat_mul(sig[v], f));
+            }
+        }
+        for (uint32_t v = w; v < n; v++)
+            if (dist[v] != ORACLE_INF && dist[v] == dfull[v]) label_push(&ix->lab[v], w, dist[v], sig[v]);
+    }
+    free(dfull);
+    free(sfull);
+    free(dist);
+    free(sig);
+    free(queue);
+    ix->hubs_done = n;
+    ix->rounds = last_round(ix, depth_cap);
+    return ix;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sequential pruned BFS, hubs in rank order.  While hub r is processed,     */
 /* the labels hold only hubs ranked above r, so a vertex v met at depth D is */
 /* skipped when a common hub of L(v) and L(r) already gives a distance < D.  */

@@ -55,6 +55,11 @@ oracle_index *oracle_build_pruned(uint32_t n, const uint64_t *off,
                                   uint32_t max_hubs, double time_limit_s);
 oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t *adj,
                                 uint32_t depth_cap);
+/* The definition builder with vertex weights weight[rank]: an entry's count
+ * sums, over its trough shortest paths, the product of the weights of the
+ * path's inner vertices (all weights 1: the plain index). */
+oracle_index *oracle_build_definition_weighted(uint32_t n, const uint64_t *off, const uint32_t *adj,
+                                               const uint64_t *weight, uint32_t depth_cap);
 
 uint64_t oracle_index_entries(const oracle_index *ix);
 /* Last round run by a round-by-distance build: the first empty round

@@ -1237,8 +1237,11 @@ struct Build {
     uint64_t NNZ = 0;
     uint32_t k = 1;
     std::vector<uint32_t> vbase, gn;
-    ShellResult shell;  // SPC_REDUCE_ONE_SHELL: the fringe and the core ids
+    ShellResult shell;  // SPC_REDUCE_*: what was cut off, and the core ids
     bool reduced = false;
+    uint32_t *hub_w = nullptr;  // neighbourhood equivalence: class size per rank
+    uint64_t *wcnt = nullptr;   // weighted copy of the pulled round's counts
+    uint64_t wcap = 0;
     std::vector<uint32_t> obase, on;  // input vertex ranges when reduced
     // graph
     uint64_t *goff = nullptr;
@@ -1441,6 +1444,25 @@ struct Build {
     }
 };
 
+// out[rank_of[v]] = in[v]
+__global__ void k_to_rank(uint32_t N, const uint32_t *rank_of, const uint32_t *in, uint32_t *out) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < N) out[rank_of[v]] = in[v];
+}
+// counts of the pulled round, each times the weight of the vertex holding
+// it (that vertex is inside every path the pull extends), one wave per vertex
+__global__ __launch_bounds__(kBlock) void k_weigh_pool(uint32_t N, const uint64_t *pstart, const uint32_t *plen,
+                                                        const uint64_t *cnt, const uint32_t *w, uint64_t *out) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t nw = gridDim.x * kWaves;
+    for (uint32_t v = blockIdx.x * kWaves + (threadIdx.x >> 6); v < N; v += nw) {
+        const uint32_t len = plen[v];
+        if (!len) continue;
+        const uint64_t s = pstart[v], f = w[v];
+        for (uint32_t i = lane; i < len; i += 64) out[s + i] = sat_mul(cnt[s + i], f);
+    }
+}
+
 // simple + symmetric check of a CSR; sorts each row of adj in place
 spc_status validate_csr(Build &B, const uint64_t *off, uint32_t *adj, uint32_t N, uint64_t NNZ,
                         uint32_t *err) {
@@ -1472,7 +1494,7 @@ spc_status validate_csr(Build &B, const uint64_t *off, uint32_t *adj, uint32_t N
 
 // union CSR (+ 1-shell reduction) + ordering + relabel (+ validation)
 spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_tie, bool validate,
-                      bool reduce) {
+                      uint32_t reduce) {
     uint32_t N = B.N;
     uint64_t NNZ = B.NNZ;
     uint64_t *off = nullptr;
@@ -1562,13 +1584,18 @@ spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_ti
     B.arena.release(st_ord);
 
     if (reduce) {
-        // Section "Reduction by 1-Shell": the rest of the build sees the core
-        // only.  The input is checked first: the stripping assumes a simple
-        // symmetric graph.
+        // Sections "Reduction by 1-Shell" and "Reduction by Equivalence
+        // Relation": the rest of the build sees the core only.  The input is
+        // checked first: both reductions assume a simple symmetric graph.
+        const bool sorted = validate && NNZ;  // validation sorts every row
         if (validate) SPC_TRY(validate_csr(B, off, col, N, NNZ, err));
         validate = false;  // the core of a valid graph is valid
         ShellResult &R = B.shell;
-        SPC_TRY(one_shell(B.arena, B.st, B.ws, N, NNZ, off, col, ord_union, tie_union, B.vbase, &R));
+        if (reduce & SPC_REDUCE_ONE_SHELL)
+            SPC_TRY(one_shell(B.arena, B.st, B.ws, N, NNZ, off, col, ord_union, tie_union, B.vbase, &R));
+        else
+            SPC_TRY(twin_reduce(B.arena, B.st, B.ws, N, NNZ, off, col, sorted, ord_union, tie_union,
+                                B.vbase, &R));
         B.arena.release(off);
         B.arena.release(col);
         B.arena.release(ord_union);
@@ -1635,6 +1662,13 @@ spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_ti
     hipLaunchKernelGGL(k_rank_of, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st, B.order, N, deg,
                        B.rank_of, rdeg);
     SPC_LAUNCHED();
+    if (B.shell.weight) {  // class sizes into rank space
+        SPC_TRY(B.arena.alloc(&B.hub_w, (uint64_t)N + 1));
+        hipLaunchKernelGGL(k_to_rank, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, B.st, N, B.rank_of,
+                           B.shell.weight, B.hub_w);
+        SPC_LAUNCHED();
+        B.arena.release(B.shell.weight);
+    }
     SPC_TRY(B.arena.alloc(&B.goff, (uint64_t)N + 1));
     SPC_TRY(B.arena.alloc(&B.gadj, std::max<uint64_t>(NNZ, 1)));
     SPC_TRY(scan_u32(rdeg, B.goff, N, B.ws, B.st));
@@ -1698,6 +1732,23 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         }
     }
 
+    // vertex weights (neighbourhood equivalence): from round 2 on, a pulled
+    // entry (w, d-1) of v extends paths that pass through v
+    const uint64_t *pool_cnt = B.rcnt[d - 1];
+    if (B.hub_w && d >= 2) {
+        const uint64_t used = std::max<uint64_t>(B.rused[d - 1], 1);
+        if (used > B.wcap) {
+            B.arena.release(B.wcnt);
+            B.wcap = 0;
+            SPC_TRY(B.arena.alloc(&B.wcnt, used));
+            B.wcap = used;
+        }
+        hipLaunchKernelGGL(k_weigh_pool, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, pstart, plen,
+                           B.rcnt[d - 1], B.hub_w, B.wcnt);
+        SPC_LAUNCHED();
+        pool_cnt = B.wcnt;
+    }
+
     uint64_t *rs = nullptr;
     uint32_t *rl = nullptr;
     SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
@@ -1744,7 +1795,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.pstart = pstart;
         ra.plen = plen;
         ra.pool_hub = B.rhub[d - 1];
-        ra.pool_cnt = B.rcnt[d - 1];
+        ra.pool_cnt = pool_cnt;
         ra.raw_off = B.raw_off;
         ra.tmp_hub = B.tmp_hub;
         ra.tmp_cnt = B.tmp_cnt;
@@ -1990,7 +2041,9 @@ inline float elapsed(hipEvent_t a, hipEvent_t b) {
 spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, hipStream_t st,
                       spc_index **out) {
     if (!gs || !o || !out || k == 0) return SPC_ERR_INVALID_ARG;
-    if ((o->reduce & ~SPC_REDUCE_ONE_SHELL) != 0) return SPC_ERR_INVALID_ARG;
+    // one reduction at a time
+    if (o->reduce != 0 && o->reduce != SPC_REDUCE_ONE_SHELL && o->reduce != SPC_REDUCE_EQUIVALENCE)
+        return SPC_ERR_INVALID_ARG;
     if (o->dist_bits != 0 && o->dist_bits != 8 && o->dist_bits != 16) return SPC_ERR_INVALID_ARG;
     uint64_t N64 = 0, NNZ = 0;
     uint32_t n_order = 0, n_tie = 0, n_dev = 0;
@@ -2084,8 +2137,7 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     SPC_TRY(B.arena.alloc(&B.ctr, 8));
 
     SPC_HIP(hipEventRecord(ev[0], st));
-    SPC_TRY(preprocess(B, gs, n_order == k, n_tie == k, o->validate != 0,
-                       (o->reduce & SPC_REDUCE_ONE_SHELL) != 0));
+    SPC_TRY(preprocess(B, gs, n_order == k, n_tie == k, o->validate != 0, o->reduce));
     SPC_HIP(hipEventRecord(ev[1], st));
     // from here on the graph is the core when the 1-shell was cut off
     const uint32_t N = B.N;
@@ -2203,7 +2255,8 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         if (B.stats[r].kept) maxd = (uint32_t)r;
     // a query distance is at most two label distances plus two fringe
     // depths: the outputs take the narrowest width that holds every one
-    const uint64_t qmax = 2ull * maxd + (B.reduced ? 2ull * B.shell.max_depth : 0ull);
+    uint64_t qmax = 2ull * maxd + (B.reduced ? 2ull * B.shell.max_depth : 0ull);
+    if (B.hub_w && qmax < 2) qmax = 2;  // two twins with common neighbours
     if (qmax > Ent<16>::kMaxDist) return SPC_ERR_DIST_RANGE;
     const uint32_t out_bits = (B.db == 16 || qmax > Ent<8>::kMaxDist) ? 16u : 8u;
 
@@ -2252,7 +2305,12 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         ix->core_vid = R.core_vid;
         ix->fringe = R.fringe;
         ix->fringe_depth = R.max_depth;
-        for (void *blk : {(void *)R.root, (void *)R.depth, (void *)R.parent, (void *)R.core_vid}) {
+        ix->twins = R.twins;
+        ix->red_same = R.same;
+        ix->hub_w = B.hub_w;
+        for (void *blk : {(void *)R.root, (void *)R.depth, (void *)R.parent, (void *)R.core_vid,
+                          (void *)R.same, (void *)B.hub_w}) {
+            if (!blk) continue;
             uint64_t b = B.arena.detach(blk);
             ix->blocks.emplace_back(blk, (size_t)b);
             ix->index_bytes += b;

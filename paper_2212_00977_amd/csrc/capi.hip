@@ -83,6 +83,7 @@ spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
     out->label_bits = ix->dist_bits;
     out->fringe_vertices = ix->fringe;
     out->fringe_depth = ix->fringe_depth;
+    out->twin_vertices = (uint32_t)ix->twins;
     out->truncated = ix->truncated ? 1u : 0u;
     out->saturated_entries = ix->saturated;
     out->index_bytes = ix->index_bytes;

@@ -11,7 +11,11 @@
 //
 // On an index with the 1-shell cut off, s and t are first mapped to their
 // roots: equal roots leave the tree path as the only shortest path; other
-// roots are joined as above and the two depths added.
+// roots are joined as above and the two depths added.  On an index reduced
+// by neighbourhood equivalence they are mapped to their classes'
+// representatives: two members of one class are answered from the class
+// alone, others by the join of the representatives, where a common hub
+// inside the path counts once per member of its class.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +41,9 @@ struct QueryArgs {
     // root, depth, parent; the graph's input vertex range
     const uint32_t *red_root, *red_depth, *red_parent;
     uint32_t obase, on;
+    // neighbourhood equivalence (null otherwise): class size per hub (rank
+    // space); per input vertex the answer for two members of its class
+    const uint32_t *hub_w, *red_same;
     void *dist_out;
     uint64_t *count_out;
     uint8_t *flags_out;
@@ -70,6 +77,32 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     if (a.red_root) {
         const uint32_t gs = a.obase + s, gt = a.obase + t;
         const uint32_t cs = a.red_root[gs], ct = a.red_root[gt];
+        if (cs == ct && a.red_same) {
+            // one class: the same vertex (0, 1); adjacent twins (1, 1);
+            // others share all k neighbours: (2, k), unreachable when k = 0
+            if (lane == 0) {
+                const uint32_t k = a.red_same[gs];
+                DT dd = 0;
+                uint64_t cc = 1;
+                uint8_t fl = 0;
+                if (s != t) {
+                    if (k == 0xFFFFFFFFu) {
+                        dd = 1;
+                    } else if (k == 0) {
+                        dd = kInf;
+                        cc = 0;
+                        fl = SPC_FLAG_UNREACHABLE;
+                    } else {
+                        dd = 2;
+                        cc = k;
+                    }
+                }
+                static_cast<DT *>(a.dist_out)[q] = dd;
+                a.count_out[q] = cc;
+                if (a.flags_out) a.flags_out[q] = fl;
+            }
+            return;
+        }
         if (cs == ct) {
             // one tree: climb to the lowest common ancestor (every step
             // lowers the depth by one, so the walk ends by depth 0)
@@ -165,6 +198,11 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
                     if (dd[j] == gmin) {
                         cs[j] = a.lab_cnt[as + ia + pos[j]];
                         ct[j] = a.lab_cnt[bs + ib + (uint64_t)j * 64 + lane];
+                        // a hub other than s and t lies inside the path
+                        if (a.hub_w) {
+                            const uint32_t h = e_hub<DB>(eb[j]);
+                            if (h != rs && h != rt) ct[j] = sat_mul(ct[j], a.hub_w[h]);
+                        }
                     }
                 }
                 if (gmin < best) {
@@ -403,6 +441,8 @@ spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, 
     a.red_parent = ix->red_parent;
     a.obase = ix->reduced ? ix->obase[graph_id] : 0;
     a.on = ix->reduced ? ix->on[graph_id] : 0;
+    a.hub_w = ix->hub_w;
+    a.red_same = ix->red_same;
     a.dist_out = dist_out;
     a.count_out = count_out;
     a.flags_out = flags_out;

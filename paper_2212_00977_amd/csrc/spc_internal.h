@@ -320,9 +320,13 @@ struct ShellResult {
     // per input vertex: core id of root(v), depth, parent (input id)
     uint32_t *root = nullptr, *depth = nullptr, *parent = nullptr;
     uint32_t *core_vid = nullptr;  // core id -> input id
+    // neighbourhood equivalence: class size per core id; per input vertex
+    // the answer for two members of its class (~0: adjacent twins (1, 1),
+    // else the degree: (2, degree), or unreachable at 0)
+    uint32_t *weight = nullptr, *same = nullptr;
     std::vector<uint32_t> cbase;   // core id range of each graph, k+1 entries
     uint32_t N = 0;
-    uint64_t NNZ = 0, fringe = 0;
+    uint64_t NNZ = 0, fringe = 0, twins = 0;
     uint32_t max_depth = 0;
 };
 
@@ -369,6 +373,10 @@ struct spc_index {
     uint32_t *core_vid = nullptr;
     uint64_t fringe = 0;
     uint32_t fringe_depth = 0;
+    // neighbourhood equivalence: class size of every hub (rank space) and
+    // the same-class answer per input vertex; null otherwise
+    uint32_t *hub_w = nullptr, *red_same = nullptr;
+    uint64_t twins = 0;
 };
 
 namespace spc {
@@ -379,6 +387,9 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *opt
 spc_status one_shell(Arena &ar, hipStream_t st, uint64_t *ws, uint32_t N, uint64_t NNZ,
                      const uint64_t *off, const uint32_t *col, const uint32_t *ord, const uint64_t *tie,
                      const std::vector<uint32_t> &vbase, ShellResult *R);
+spc_status twin_reduce(Arena &ar, hipStream_t st, uint64_t *ws, uint32_t N, uint64_t NNZ,
+                       const uint64_t *off, uint32_t *col, bool rows_sorted, const uint32_t *ord,
+                       const uint64_t *tie, const std::vector<uint32_t> &vbase, ShellResult *R);
 // query.hip
 spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                       uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,

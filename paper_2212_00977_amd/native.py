@@ -62,7 +62,7 @@ class SpcStats(C.Structure):
                 ("ms_round_kernel", C.c_double), ("alg_bytes_round_kernel", C.c_uint64),
                 ("round_kernel_launches", C.c_uint64), ("query_config", C.c_uint32),
                 ("label_bits", C.c_uint32), ("fringe_vertices", C.c_uint64),
-                ("fringe_depth", C.c_uint32), ("reserved", C.c_uint32)]
+                ("fringe_depth", C.c_uint32), ("twin_vertices", C.c_uint32)]
 
 
 class SpcGraph(C.Structure):

@@ -93,6 +93,7 @@ class BuildOptions:
     mem_budget: int = 0
     validate: bool = True
     one_shell: bool = False  # SPC_REDUCE_ONE_SHELL: label the 2-core only
+    equivalence: bool = False  # SPC_REDUCE_EQUIVALENCE: one weighted vertex per class of twins
 
     def struct(self):
         o = native.SpcBuildOpts()
@@ -100,7 +101,7 @@ class BuildOptions:
         o.round_cap = self.round_cap
         o.mem_budget = self.mem_budget
         o.validate = 1 if self.validate else 0
-        o.reduce = 1 if self.one_shell else 0
+        o.reduce = (1 if self.one_shell else 0) | (2 if self.equivalence else 0)
         return o
 
 

@@ -120,3 +120,27 @@ def test_twin_query_on_larger_graphs_equals_bfs_counting():
                     assert d[v] == oracle.INF and c[v] == 0
                 else:
                     assert int(d[v]) == bd[v] and int(c[v]) == min(bc[v], brute.SAT), (src, v)
+
+
+@pytest.mark.parametrize("gi", range(6))
+def test_c_weighted_builder_equals_python_definition(gi):
+    g = twin_graphs()[gi]
+    rng = np.random.default_rng(gi)
+    w = rng.integers(1, 9, g.n).astype(np.uint64)
+    for cap in (0, 2):
+        a = oracle.weighted_labels(g.off, g.adj, w, depth_cap=cap)
+        b = oracle.build_weighted(g.off, g.adj, w, depth_cap=cap)
+        for k in ("off", "hub", "dist", "count", "order"):
+            assert np.array_equal(getattr(a, k), getattr(b, k)), (k, cap)
+
+
+def test_c_weighted_builder_saturates_like_the_definition():
+    # a 12x12 grid with every weight 7: corner-to-corner counts pass 2^64
+    k = 12
+    e = [(i * k + j, i * k + j + 1) for i in range(k) for j in range(k - 1)]
+    e += [(i * k + j, (i + 1) * k + j) for i in range(k - 1) for j in range(k)]
+    g = csr(k * k, e)
+    w = np.full(g.n, 7, dtype=np.uint64)
+    a = oracle.weighted_labels(g.off, g.adj, w)
+    b = oracle.build_weighted(g.off, g.adj, w)
+    assert np.array_equal(a.count, b.count) and int((b.count == np.uint64(oracle.SAT)).sum()) > 0
