@@ -125,11 +125,11 @@ def bench_served(args, dev, log):
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     ix = spc.build_index(off_d, adj_d, device=dev, stream=stream,
-                         opts=spc.BuildOptions(one_shell=args.one_shell))
+                         opts=spc.BuildOptions(one_shell=args.one_shell, equivalence=args.equivalence))
     build_ms = (time.perf_counter() - t0) * 1e3
     st = ix.stats()
     log(f"build {build_ms:.0f} ms, {st['entries']} entries, fringe {st['fringe_vertices']}, "
-        f"peak {st['peak_build_bytes'] / 2**30:.1f} GiB")
+        f"twins {st['twin_vertices']}, peak {st['peak_build_bytes'] / 2**30:.1f} GiB")
     del off_d, adj_d
     spc.release_cached_memory()
     torch.cuda.empty_cache()
@@ -173,7 +173,8 @@ def bench_served(args, dev, log):
                       "n": g.n, "m": g.m, "entries": st["entries"], "rounds": st["rounds"],
                       "requests_per_level": args.serve_requests, "max_batch": args.serve_max_batch,
                       "streams": args.serve_streams, "one_shell": args.one_shell,
-                      "fringe_vertices": st["fringe_vertices"], "parallelism": "single-gpu"},
+                      "equivalence": args.equivalence, "fringe_vertices": st["fringe_vertices"],
+                      "twin_vertices": st["twin_vertices"], "parallelism": "single-gpu"},
            "p50_ms": one["p50_ms"], "p99_ms": one["p99_ms"],
            "build_ms": build_ms, "build_entries_per_s": st["entries"] / (build_ms * 1e-3),
            "query_config": dict(zip(("stage", "tiles"), spc.query_configs()[qcfg])),
@@ -277,7 +278,7 @@ def bench_batch(args, dev, log):
     t_d = [torch.from_numpy(t.view(np.int32)).to(dev) for _, t in qs]
     torch.cuda.synchronize()
 
-    opts = spc.BuildOptions(one_shell=args.one_shell)
+    opts = spc.BuildOptions(one_shell=args.one_shell, equivalence=args.equivalence)
 
     def batched():
         t0 = time.perf_counter()
@@ -325,24 +326,27 @@ def bench_batch(args, dev, log):
                                   "one batched build + 10,000 queries per graph",
                       "graphs": len(graphs), "n": N, "m": M, "entries": entries,
                       "rounds": st["rounds"], "one_shell": args.one_shell,
-                      "fringe_vertices": st["fringe_vertices"], "parallelism": "single-gpu"},
+                      "equivalence": args.equivalence, "fringe_vertices": st["fringe_vertices"],
+                      "twin_vertices": st["twin_vertices"], "parallelism": "single-gpu"},
            "batched_build_ms": bms, "plain_build_ms": pms,
            "plain_entries_per_s": pe / (pms * 1e-3), "batched_speedup": pms / bms,
            "query_ms": qms, "queries_per_s": 10000 * len(graphs) / (qms * 1e-3)}
     print(json.dumps(out), flush=True)
 
 
-def one_shell_side(off_d, adj_d, s_d, t_d, dev, stream, cfg, ref_d, ref_c, log, reps=2):
-    """The same workload built with the 1-shell cut off (Section "Reduction
-    by 1-Shell"): build time, fringe, index size and query rate of the
-    reduced index, and how many answers differ from the full index's (the
-    last timed step's outputs).  Not part of the headline value."""
+def reduced_side(kind, off_d, adj_d, s_d, t_d, dev, stream, cfg, ref_d, ref_c, log, reps=2):
+    """The same workload built with an index reduction -- kind "one_shell"
+    (Section "Reduction by 1-Shell") or "equivalence" (Section "Reduction
+    by Equivalence Relation"): build time, vertices cut off or merged, index
+    size and query rate of the reduced index, and how many answers differ
+    from the full index's (the last timed step's outputs).  Not part of the
+    headline value."""
     import torch
 
     from paper_2212_00977_amd import spc
 
     nq = int(s_d.shape[0])
-    opts = spc.BuildOptions(one_shell=True)
+    opts = spc.BuildOptions(**{kind: True})
     builds, queries = [], []
     for i in range(reps):  # the first build warms the block cache
         t0 = time.perf_counter()
@@ -367,10 +371,10 @@ def one_shell_side(off_d, adj_d, s_d, t_d, dev, stream, cfg, ref_d, ref_c, log, 
     ix.free()
     out = {"build_ms": builds[-1], "query_ms": queries[-1], "queries_per_s": nq / (queries[-1] * 1e-3),
            "fringe_vertices": st["fringe_vertices"], "fringe_depth": st["fringe_depth"],
-           "core_vertices": st["n"], "entries": st["entries"], "index_bytes": st["index_bytes"],
+           "twin_vertices": st["twin_vertices"], "core_vertices": st["n"], "entries": st["entries"], "index_bytes": st["index_bytes"],
            "peak_build_bytes": st["peak_build_bytes"], "dist_bits": bits,
            "answers_differing_from_full_index": diff}
-    log(f"one-shell: build {builds[-1]:.1f} ms, fringe {st['fringe_vertices']}, "
+    log(f"{kind}: build {builds[-1]:.1f} ms, fringe {st['fringe_vertices']}, twins {st['twin_vertices']}, "
         f"entries {st['entries']}, queries {queries[-1]:.1f} ms, differing answers {diff}")
     return out
 
@@ -408,10 +412,12 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per offered-load level (rmat_served)")
     ap.add_argument("--batch-graphs", type=int, default=512)
-    ap.add_argument("--no-one-shell", action="store_true",
-                    help="skip the side measurement of the 1-shell reduced build")
+    ap.add_argument("--no-reductions", action="store_true",
+                    help="skip the side measurements of the reduced builds")
     ap.add_argument("--one-shell", action="store_true",
                     help="build with the 1-shell reduction (rmat_served, rmat_batch)")
+    ap.add_argument("--equivalence", action="store_true",
+                    help="build with the neighbourhood-equivalence reduction (rmat_served, rmat_batch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -551,9 +557,9 @@ def main():
         "peak_build_bytes": st["peak_build_bytes"],
     }
     last_ix = runs[-1]["index"]
-    if not args.no_one_shell:
-        out["one_shell"] = one_shell_side(off_d, adj_d, s_d, t_d, dev, stream, qcfg[0], dist_o, cnt_o,
-                                          log)
+    if not args.no_reductions:
+        for kind in ("one_shell", "equivalence"):
+            out[kind] = reduced_side(kind, off_d, adj_d, s_d, t_d, dev, stream, qcfg[0], dist_o, cnt_o, log)
     if args.serve_seconds > 0 or args.serve_sweep:
         out["serve"] = serve_runs(last_ix, g.n, args, out["queries_per_s"], log)
     last_ix.free()
