@@ -337,6 +337,7 @@ struct RoundArgs {
     const uint32_t *plen;
     const uint32_t *pool_hub;        // round d-1 entries
     const uint64_t *pool_cnt;
+    const uint32_t *adj_w;           // per adjacency slot: the neighbour's weight (W only)
     uint32_t *cur, *nxt;             // per adjacency slot: segment positions at lo / hi
     const uint64_t *raw_off;  // exclusive prefix of raw over all vertices
     uint32_t *tmp_hub;
@@ -410,7 +411,9 @@ struct LabelLookup {
 // TM: w's entries past u's staged label are matched by a merge with u's
 // unstaged part (labels of similar length: high-diameter graphs) rather than
 // by binary searches
-template <int DB, int RB, bool TM>
+// W: vertex weights (neighbourhood equivalence, rounds >= 2): a pulled
+// count is multiplied by the weight of the neighbour it is pulled from.
+template <int DB, int RB, bool TM, bool W>
 __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 VGPRs: 4 waves per SIMD
     constexpr int RW = RB / 64;          // waves per workgroup
     constexpr int PER = kULimit / RB;    // candidate slots per thread
@@ -641,6 +644,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                 uint64_t idx = nb_start[jl] + (k - nb_off[jl]);
                 uint32_t w = a.pool_hub[idx];
                 uint64_t c = a.pool_cnt[idx];
+                if constexpr (W) c = sat_mul(c, (uint64_t)a.adj_w[g0 + nb0 + jl]);
                 if (held(w)) continue;  // Label Elimination
                 uint32_t s = hash_slot(w, kCBits);
                 bool ok = true;
@@ -1240,8 +1244,7 @@ struct Build {
     ShellResult shell;  // SPC_REDUCE_*: what was cut off, and the core ids
     bool reduced = false;
     uint32_t *hub_w = nullptr;  // neighbourhood equivalence: class size per rank
-    uint64_t *wcnt = nullptr;   // weighted copy of the pulled round's counts
-    uint64_t wcap = 0;
+    uint32_t *adj_w = nullptr;  // and of the neighbour in every adjacency slot
     std::vector<uint32_t> obase, on;  // input vertex ranges when reduced
     // graph
     uint64_t *goff = nullptr;
@@ -1449,18 +1452,10 @@ __global__ void k_to_rank(uint32_t N, const uint32_t *rank_of, const uint32_t *i
     uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < N) out[rank_of[v]] = in[v];
 }
-// counts of the pulled round, each times the weight of the vertex holding
-// it (that vertex is inside every path the pull extends), one wave per vertex
-__global__ __launch_bounds__(kBlock) void k_weigh_pool(uint32_t N, const uint64_t *pstart, const uint32_t *plen,
-                                                        const uint64_t *cnt, const uint32_t *w, uint64_t *out) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t nw = gridDim.x * kWaves;
-    for (uint32_t v = blockIdx.x * kWaves + (threadIdx.x >> 6); v < N; v += nw) {
-        const uint32_t len = plen[v];
-        if (!len) continue;
-        const uint64_t s = pstart[v], f = w[v];
-        for (uint32_t i = lane; i < len; i += 64) out[s + i] = sat_mul(cnt[s + i], f);
-    }
+// weight of the neighbour in every adjacency slot (rank space)
+__global__ void k_adj_weights(const uint32_t *adj, uint64_t nnz, const uint32_t *w, uint32_t *out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride) out[i] = w[adj[i]];
 }
 
 // simple + symmetric check of a CSR; sorts each row of adj in place
@@ -1681,6 +1676,14 @@ spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_ti
     B.arena.release(deg);
 
     if (validate) SPC_TRY(validate_csr(B, B.goff, B.gadj, N, NNZ, err));
+    if (B.hub_w) {  // after validation, which reorders rows
+        SPC_TRY(B.arena.alloc(&B.adj_w, std::max<uint64_t>(NNZ, 1)));
+        if (NNZ) {
+            hipLaunchKernelGGL(k_adj_weights, dim3(grid_stride(NNZ)), dim3(kBlock), 0, B.st, B.gadj, NNZ,
+                               B.hub_w, B.adj_w);
+            SPC_LAUNCHED();
+        }
+    }
     B.arena.release(err);
     B.arena.release(vb_dev);
     return SPC_OK;
@@ -1732,23 +1735,6 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         }
     }
 
-    // vertex weights (neighbourhood equivalence): from round 2 on, a pulled
-    // entry (w, d-1) of v extends paths that pass through v
-    const uint64_t *pool_cnt = B.rcnt[d - 1];
-    if (B.hub_w && d >= 2) {
-        const uint64_t used = std::max<uint64_t>(B.rused[d - 1], 1);
-        if (used > B.wcap) {
-            B.arena.release(B.wcnt);
-            B.wcap = 0;
-            SPC_TRY(B.arena.alloc(&B.wcnt, used));
-            B.wcap = used;
-        }
-        hipLaunchKernelGGL(k_weigh_pool, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, pstart, plen,
-                           B.rcnt[d - 1], B.hub_w, B.wcnt);
-        SPC_LAUNCHED();
-        pool_cnt = B.wcnt;
-    }
-
     uint64_t *rs = nullptr;
     uint32_t *rl = nullptr;
     SPC_TRY(B.arena.alloc(&rs, (uint64_t)N + 1));
@@ -1795,7 +1781,10 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.pstart = pstart;
         ra.plen = plen;
         ra.pool_hub = B.rhub[d - 1];
-        ra.pool_cnt = pool_cnt;
+        ra.pool_cnt = B.rcnt[d - 1];
+        // vertex weights (neighbourhood equivalence): from round 2 on, a
+        // pulled entry (w, d-1) of v extends paths that pass through v
+        ra.adj_w = B.adj_w;
         ra.raw_off = B.raw_off;
         ra.tmp_hub = B.tmp_hub;
         ra.tmp_cnt = B.tmp_cnt;
@@ -1806,10 +1795,19 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         SPC_HIP(hipEventRecord(B.ev_a, B.st));
         // from round 17 on the graph has a long diameter: there, neighbours'
         // labels are nearly the same set, which the tail merge exploits
-        if (d > kMergeRound)
-            k_round<DB, kRoundBlock, true><<<dim3(b1 - b0), dim3(kRoundBlock), 0, B.st>>>(ra);
-        else
-            k_round<DB, kRoundBlock, false><<<dim3(b1 - b0), dim3(kRoundBlock), 0, B.st>>>(ra);
+        const bool weighted = B.adj_w && d >= 2;
+        const dim3 grid(b1 - b0), blk(kRoundBlock);
+        if (d > kMergeRound) {
+            if (weighted)
+                k_round<DB, kRoundBlock, true, true><<<grid, blk, 0, B.st>>>(ra);
+            else
+                k_round<DB, kRoundBlock, true, false><<<grid, blk, 0, B.st>>>(ra);
+        } else {
+            if (weighted)
+                k_round<DB, kRoundBlock, false, true><<<grid, blk, 0, B.st>>>(ra);
+            else
+                k_round<DB, kRoundBlock, false, false><<<grid, blk, 0, B.st>>>(ra);
+        }
         SPC_LAUNCHED();
         B.launches++;
         SPC_HIP(hipEventRecord(B.ev_b, B.st));

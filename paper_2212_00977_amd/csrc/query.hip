@@ -51,8 +51,9 @@ struct QueryArgs {
 
 // kQStage: L(s) entries staged per wave; kQTiles: L(t) tiles of 64
 // requested together.  The pair is a launch configuration (see kQueryCfg).
-// DB: label distance bits; OB: output distance bits.
-template <int DB, int OB, uint32_t kQStage, int kQTiles>
+// DB: label distance bits; OB: output distance bits; RED: the index was
+// built with a reduction (the plain instances carry none of its code).
+template <int DB, int OB, bool RED, uint32_t kQStage, int kQTiles>
 __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     using E = typename Ent<DB>::T;
     using DT = typename std::conditional<OB == 8, uint8_t, uint16_t>::type;
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     const E *hd = static_cast<const E *>(a.lab_hd);
     const uint32_t s = a.s[q], t = a.t[q];
     const DT kInf = (DT)~(DT)0;
-    const uint32_t lim = a.red_root ? a.on : a.gn;
+    const uint32_t lim = RED ? a.on : a.gn;
     if (s >= lim || t >= lim) {
         if (lane == 0) {
             static_cast<DT *>(a.dist_out)[q] = kInf;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
         return;
     }
     uint32_t rs, rt, extra = 0;
-    if (a.red_root) {
+    if constexpr (RED) {
         const uint32_t gs = a.obase + s, gt = a.obase + t;
         const uint32_t cs = a.red_root[gs], ct = a.red_root[gt];
         if (cs == ct && a.red_same) {
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
                         cs[j] = a.lab_cnt[as + ia + pos[j]];
                         ct[j] = a.lab_cnt[bs + ib + (uint64_t)j * 64 + lane];
                         // a hub other than s and t lies inside the path
-                        if (a.hub_w) {
+                        if (RED && a.hub_w) {
                             const uint32_t h = e_hub<DB>(eb[j]);
                             if (h != rs && h != rt) ct[j] = sat_mul(ct[j], a.hub_w[h]);
                         }
@@ -293,18 +294,25 @@ constexpr QueryCfg kQueryCfg[] = {{512, 2}, {512, 1}, {512, 4}, {256, 1}, {256, 
                                   {1024, 1}, {1024, 2}, {2048, 1}};
 constexpr uint32_t kQueryCfgs = sizeof(kQueryCfg) / sizeof(kQueryCfg[0]);
 
-template <int DB, int OB>
+template <int DB, int OB, bool RED>
 void launch_cfg(uint32_t cfg, dim3 g, hipStream_t st, const QueryArgs &c) {
     switch (cfg) {
-        case 1: hipLaunchKernelGGL((k_query<DB, OB, 512, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 2: hipLaunchKernelGGL((k_query<DB, OB, 512, 4>), g, dim3(kBlock), 0, st, c); break;
-        case 3: hipLaunchKernelGGL((k_query<DB, OB, 256, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 4: hipLaunchKernelGGL((k_query<DB, OB, 256, 2>), g, dim3(kBlock), 0, st, c); break;
-        case 5: hipLaunchKernelGGL((k_query<DB, OB, 1024, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 6: hipLaunchKernelGGL((k_query<DB, OB, 1024, 2>), g, dim3(kBlock), 0, st, c); break;
-        case 7: hipLaunchKernelGGL((k_query<DB, OB, 2048, 1>), g, dim3(kBlock), 0, st, c); break;
-        default: hipLaunchKernelGGL((k_query<DB, OB, 512, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 1: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 2: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 4>), g, dim3(kBlock), 0, st, c); break;
+        case 3: hipLaunchKernelGGL((k_query<DB, OB, RED, 256, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 4: hipLaunchKernelGGL((k_query<DB, OB, RED, 256, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 5: hipLaunchKernelGGL((k_query<DB, OB, RED, 1024, 1>), g, dim3(kBlock), 0, st, c); break;
+        case 6: hipLaunchKernelGGL((k_query<DB, OB, RED, 1024, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 7: hipLaunchKernelGGL((k_query<DB, OB, RED, 2048, 1>), g, dim3(kBlock), 0, st, c); break;
+        default: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 2>), g, dim3(kBlock), 0, st, c); break;
     }
+}
+template <int DB, int OB>
+void launch_red(uint32_t cfg, dim3 g, hipStream_t st, const QueryArgs &c) {
+    if (c.red_root)
+        launch_cfg<DB, OB, true>(cfg, g, st, c);
+    else
+        launch_cfg<DB, OB, false>(cfg, g, st, c);
 }
 
 // 16-bit labels always come with 16-bit outputs
@@ -312,11 +320,11 @@ spc_status launch_query(uint32_t dist_bits, uint32_t out_bits, uint32_t cfg, con
                         hipStream_t st) {
     const dim3 g((uint32_t)((c.nq + kWaves - 1) / kWaves));
     if (dist_bits == 16)
-        launch_cfg<16, 16>(cfg, g, st, c);
+        launch_red<16, 16>(cfg, g, st, c);
     else if (out_bits == 16)
-        launch_cfg<8, 16>(cfg, g, st, c);
+        launch_red<8, 16>(cfg, g, st, c);
     else
-        launch_cfg<8, 8>(cfg, g, st, c);
+        launch_red<8, 8>(cfg, g, st, c);
     SPC_LAUNCHED();
     return SPC_OK;
 }
