@@ -63,7 +63,9 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     const uint32_t lane = threadIdx.x & 63;
     E *st = stage[threadIdx.x >> 6];
     const E *hd = static_cast<const E *>(a.lab_hd);
-    const uint32_t s = a.s[q], t = a.t[q];
+    // one query per wave: its ids, ranks and label ranges are wave-uniform
+    // and kept in scalar registers
+    const uint32_t s = __builtin_amdgcn_readfirstlane(a.s[q]), t = __builtin_amdgcn_readfirstlane(a.t[q]);
     const DT kInf = (DT)~(DT)0;
     const uint32_t lim = RED ? a.on : a.gn;
     if (s >= lim || t >= lim) {
@@ -122,12 +124,12 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
             }
             return;
         }
-        extra = a.red_depth[gs] + a.red_depth[gt];
-        rs = a.rank_of[cs];
-        rt = a.rank_of[ct];
+        extra = __builtin_amdgcn_readfirstlane(a.red_depth[gs] + a.red_depth[gt]);
+        rs = __builtin_amdgcn_readfirstlane(a.rank_of[cs]);
+        rt = __builtin_amdgcn_readfirstlane(a.rank_of[ct]);
     } else {
-        rs = a.rank_of[a.vbase + s];
-        rt = a.rank_of[a.vbase + t];
+        rs = __builtin_amdgcn_readfirstlane(a.rank_of[a.vbase + s]);
+        rt = __builtin_amdgcn_readfirstlane(a.rank_of[a.vbase + t]);
     }
     const uint64_t as = a.lab_off[rs], na = a.lab_off[rs + 1] - as;
     const uint64_t bs = a.lab_off[rt], nb = a.lab_off[rt + 1] - bs;

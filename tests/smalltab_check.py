@@ -42,6 +42,26 @@ def main():
     ix = spc.build_index_batch(batch)
     for gi, g in enumerate(batch):
         assert_labels_equal(ix.export(gi), oracle.build_graph(g), g.name)
+    # the reductions: the weighted pull (equivalence) and the core builds
+    # (1-shell) through the same overflow paths
+    import dataclasses
+    for g in (inputs.rmat(12, 16, seed=5), inputs.rmat(11, 8, seed=4), inputs.chung_lu(1 << 12, seed=2)):
+        for kind in ("equivalence", "one_shell"):
+            print(f"[case] small tables {kind}: {g.name} n={g.n}", flush=True)
+            ix = spc.build_graph(g, opts=spc.BuildOptions(**{kind: True}))
+            if kind == "equivalence":
+                red = oracle.build_twin_reduced(g.off, g.adj, order=g.order, tie_key=g.tie_key)
+                ids = red.ids
+            else:
+                red = oracle.build_reduced(g.off, g.adj, order=g.order, tie_key=g.tie_key)
+                ids = red.core_ids
+            ref = dataclasses.replace(red.labels, order=ids[red.labels.order])
+            assert_labels_equal(ix.export(), ref, f"{g.name} {kind}")
+            s, t = inputs.queries(g.n, 20000, seed=9)
+            d, c, f = gpu_query(ix, s, t)
+            rd, rc = red.query(s, t)
+            assert np.array_equal(d, rd) and np.array_equal(c, rc), (g.name, kind)
+            ix.free()
     print("small tables ok", flush=True)
     return 0
 
