@@ -244,11 +244,22 @@ class Index:
         _check(rc, "spc_export_reduction")
         return dict(root=out[0][:n], depth=out[1][:n], parent=out[2][:n])
 
+    def export_reduction_device(self, graph_id: int = 0):
+        """export_reduction into device tensors (int32 bit views)."""
+        torch = _torch()
+        n = self.input_vertices(graph_id)
+        out = [torch.empty(max(n, 1), dtype=torch.int32, device=self.device) for _ in range(3)]
+        rc = native.load().spc_export_reduction(self.handle, graph_id, *(a.data_ptr() for a in out), 1,
+                                                _stream_handle(None))
+        _check(rc, "spc_export_reduction")
+        return dict(root=out[0][:n], depth=out[1][:n], parent=out[2][:n])
+
     def input_vertices(self, graph_id: int = 0) -> int:
         """Vertices of graph `graph_id` as given to the build."""
         if self._sizes is None:
             raise RuntimeError("input sizes unknown for this handle")
-        return self._sizes[graph_id]
+        # an id out of range is left to the library, which refuses it
+        return self._sizes[graph_id] if 0 <= graph_id < len(self._sizes) else 0
 
     def export_device(self, graph_id: int = 0):
         """Same as export() into device tensors (int32/int16/int64 bit views)."""

@@ -198,3 +198,15 @@ def test_unreduced_index_reports_identity_shell(spc):
     ex = ix.export_reduction()
     assert np.array_equal(ex["root"], np.arange(g.n)) and not ex["depth"].any()
     assert ix.stats()["fringe_vertices"] == 0
+
+
+def test_export_reduction_to_device_memory(spc):
+    g = forest(500, 21, extra=10)
+    for opts in (spc.BuildOptions(one_shell=True), spc.BuildOptions(equivalence=True), spc.BuildOptions()):
+        ix = spc.build_graph(g, opts=opts)
+        host = ix.export_reduction()
+        dev = ix.export_reduction_device()
+        for k in ("root", "depth", "parent"):
+            assert np.array_equal(dev[k].cpu().numpy().view(np.uint32), host[k]), k
+        with pytest.raises(spc.SpcError):
+            ix.export_reduction(1)
