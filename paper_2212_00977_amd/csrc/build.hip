@@ -1241,6 +1241,7 @@ struct Build {
     uint64_t NNZ = 0;
     uint32_t k = 1;
     std::vector<uint32_t> vbase, gn;
+    bool simple = false;  // the input was validated simple and symmetric
     ShellResult shell;  // SPC_REDUCE_*: what was cut off, and the core ids
     bool reduced = false;
     uint32_t *hub_w = nullptr;  // neighbourhood equivalence: class size per rank
@@ -1490,6 +1491,7 @@ spc_status validate_csr(Build &B, const uint64_t *off, uint32_t *adj, uint32_t N
 // union CSR (+ 1-shell reduction) + ordering + relabel (+ validation)
 spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_tie, bool validate,
                       uint32_t reduce) {
+    B.simple = validate;  // checked below, or the build fails
     uint32_t N = B.N;
     uint64_t NNZ = B.NNZ;
     uint64_t *off = nullptr;
@@ -1696,6 +1698,40 @@ constexpr uint64_t kTempMax = 1ull << 27;
 constexpr uint32_t kBatchVerts = 1u << 22;
 constexpr uint32_t kMergeRound = 16;
 
+// Round 1 of a simple graph: round 0 holds only self entries, so L_1(u) is
+// every neighbour ranked above u with count 1 -- nothing is held, merged or
+// pruned.  Each puller's neighbours above it are written as (puller, hub)
+// keys into its segment of the round kernel's output layout; a radix sort
+// then orders every segment by hub.
+__global__ __launch_bounds__(kBlock) void k_round1_keys(uint32_t u_lo, uint32_t u_hi, const uint64_t *goff,
+                                                         const uint32_t *gadj, const uint64_t *raw_off,
+                                                         uint64_t *keys, uint32_t *surv) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t nw = gridDim.x * kWaves;
+    for (uint32_t u = u_lo + blockIdx.x * kWaves + (threadIdx.x >> 6); u < u_hi; u += nw) {
+        uint64_t out = raw_off[u] - raw_off[u_lo];
+        const uint64_t e = goff[u + 1];
+        for (uint64_t k0 = goff[u]; k0 < e; k0 += 64) {
+            const uint64_t k = k0 + lane;
+            const uint32_t v = k < e ? gadj[k] : 0xFFFFFFFFu;
+            const bool keep = v < u;
+            const uint64_t m = __ballot(keep);
+            if (keep) keys[out + (uint64_t)__popcll(m & lanemask_lt())] = ((uint64_t)(u - u_lo) << 32) | v;
+            out += (uint64_t)__popcll(m);
+        }
+        if (lane == 0) surv[u] = (uint32_t)(raw_off[u + 1] - raw_off[u]);
+    }
+}
+// sorted keys -> hubs and unit counts (the keys live in the count array)
+__global__ void k_round1_out(uint64_t n, uint32_t *hub, uint64_t *cnt) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t key = cnt[i];
+        hub[i] = (uint32_t)key;
+        cnt[i] = 1;
+    }
+}
+
 // One distance round d >= 1.  Returns the number of entries it inserted.
 template <int DB>
 spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
@@ -1743,8 +1779,9 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     SPC_TRY(B.reserve_round(d, total_raw));  // survivors are a subset of the pulls
     SPC_HIP(hipMemsetAsync(B.ctr, 0, 8 * sizeof(unsigned long long), B.st));
 
-    uint64_t kept = 0;
+    uint64_t kept = 0, fast_raw = 0;
     double round_ms = 0;
+    const bool fast1 = d == 1 && B.simple;
     for (size_t bi = 0; bi + 1 < bounds.size(); bi++) {
         uint32_t b0 = bounds[bi], b1 = bounds[bi + 1];
         uint64_t r2[2];
@@ -1797,7 +1834,26 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         // labels are nearly the same set, which the tail merge exploits
         const bool weighted = B.adj_w && d >= 2;
         const dim3 grid(b1 - b0), blk(kRoundBlock);
-        if (d > kMergeRound) {
+        if (fast1) {
+            // the keys are built in the count array, sorted there, then
+            // split into hubs and unit counts
+            uint64_t *keys2 = nullptr, *rws = nullptr;
+            SPC_TRY(B.arena.alloc(&keys2, std::max<uint64_t>(need, 1)));
+            SPC_TRY(B.arena.alloc(&rws, radix_ws_elems(std::max<uint64_t>(need, 1))));
+            hipLaunchKernelGGL(k_round1_keys, dim3(grid_for(b1 - b0, kWaves)), dim3(kBlock), 0, B.st, b0, b1,
+                               B.goff, B.gadj, B.raw_off, B.tmp_cnt, B.surv);
+            SPC_LAUNCHED();
+            if (need) {
+                SPC_TRY(radix_sort_pairs(B.tmp_cnt, nullptr, keys2, nullptr, need,
+                                         32 + std::max(1, bit_width(b1 - b0)), rws, B.st));
+                hipLaunchKernelGGL(k_round1_out, dim3(grid_stride(need)), dim3(kBlock), 0, B.st, need,
+                                   B.tmp_hub, B.tmp_cnt);
+                SPC_LAUNCHED();
+            }
+            B.arena.release(keys2);
+            B.arena.release(rws);
+            fast_raw += need;
+        } else if (d > kMergeRound) {
             if (weighted)
                 k_round<DB, kRoundBlock, true, true><<<grid, blk, 0, B.st>>>(ra);
             else
@@ -1809,14 +1865,14 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
                 k_round<DB, kRoundBlock, false, false><<<grid, blk, 0, B.st>>>(ra);
         }
         SPC_LAUNCHED();
-        B.launches++;
+        if (!fast1) B.launches++;
         SPC_HIP(hipEventRecord(B.ev_b, B.st));
         SPC_TRY(scan_u32(B.surv + b0, B.soff, b1 - b0, B.ws, B.st));
         uint64_t sb;
         SPC_TRY(B.read_u64(B.soff + (b1 - b0), &sb));
         float ms = 0;
         SPC_HIP(hipEventElapsedTime(&ms, B.ev_a, B.ev_b));
-        B.ms_round_kernel += ms;
+        if (!fast1) B.ms_round_kernel += ms;  // the fused round kernel only
         round_ms += ms;
         if (B.rcap[d] < B.rused[d] + sb) {
             // copied growth: the first batch sizes the round from its
@@ -1844,9 +1900,9 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     uint64_t c[8];
     SPC_TRY(B.read_u64((const uint64_t *)B.ctr, c, 8));
     RoundCounters rc;
-    rc.raw = c[0];
-    rc.merged = c[1];
-    rc.kept = c[2];
+    rc.raw = c[0] + fast_raw;
+    rc.merged = c[1] + fast_raw;
+    rc.kept = c[2] + fast_raw;
     rc.scanned = c[3];
     rc.staged = c[4];
     rc.row_bytes = c[5];

@@ -108,3 +108,18 @@ def test_reduced_with_16_bit_labels(spc, kind):
     d, c, f = gpu_query(ix, s, t)
     rd, rc = red.query(s, t)
     assert np.array_equal(d, rd) and np.array_equal(c, rc)
+
+
+def test_round_one_paths_agree(spc):
+    # validated input takes the dedicated round-1 kernel, unvalidated input
+    # the round kernel: same labels, same per-round counters
+    for g in (inputs.rmat(12, 8, seed=2), inputs.chung_lu(1 << 12, seed=5), inputs.grid_lcc(24, 0.05, seed=3)):
+        a = spc.build_graph(g, opts=spc.BuildOptions(validate=True))
+        b = spc.build_graph(g, opts=spc.BuildOptions(validate=False))
+        ea, eb = a.export(), b.export()
+        for k in ("off", "hub", "dist", "count", "order"):
+            assert np.array_equal(ea[k], eb[k]), (g.name, k)
+        ra, rb = a.round_stats(), b.round_stats()
+        for k in ("raw", "merged", "kept"):
+            assert np.array_equal(ra[k], rb[k]), (g.name, k)
+        assert assert_labels_equal(ea, oracle.build_graph(g), g.name) is None
