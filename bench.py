@@ -416,6 +416,8 @@ def main():
                     help="skip the side measurements of the reduced builds")
     ap.add_argument("--one-shell", action="store_true",
                     help="build with the 1-shell reduction (rmat_served, rmat_batch)")
+    ap.add_argument("--propagation", default="pull", choices=["pull", "push", "auto"],
+                    help="propagation paradigm of the chunglu workload's timed builds")
     ap.add_argument("--equivalence", action="store_true",
                     help="build with the neighbourhood-equivalence reduction (rmat_served, rmat_batch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -470,9 +472,11 @@ def main():
     torch.cuda.synchronize()
     qcfg = [None]
 
+    bopts = spc.BuildOptions(propagation=args.propagation)
+
     def step(keep=False):
         t0 = time.perf_counter()
-        ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
+        ix = spc.build_index(off_d, adj_d, device=dev, stream=stream, opts=bopts)
         t1 = time.perf_counter()
         ix.set_query_config(qcfg[0])
         ev0.record(stream)
@@ -537,7 +541,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": f"chung-lu n=2^{20 - args.scale_down} exp 2.1 clip [2,20000] "
-                               f"mean deg 10 seed 2, degree order, {args.queries} uniform queries",
+                               f"mean deg 10 seed 2, degree order, {args.propagation} propagation, "
+                               f"{args.queries} uniform queries",
                    "n": g.n, "m": g.m, "entries": entries, "rounds": st["rounds"],
                    "max_dist": st["max_dist"], "queries": args.queries,
                    "parallelism": "single-gpu"},

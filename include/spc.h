@@ -58,6 +58,11 @@ typedef enum {
 #define SPC_FLAG_HORIZON 0x4u    /* truncated index: answer not proven exact (dist > round cap or none found) */
 #define SPC_FLAG_INVALID 0x8u    /* s or t >= n: dist = INF, count 0 */
 
+/* Propagation paradigm (spc_build_opts.propagation). */
+#define SPC_PROPAGATE_PULL 0u
+#define SPC_PROPAGATE_PUSH 1u
+#define SPC_PROPAGATE_AUTO 2u
+
 /* Index reductions (spc_build_opts.reduce). */
 #define SPC_REDUCE_ONE_SHELL 0x1u   /* Section "Reduction by 1-Shell": label only the core */
 #define SPC_REDUCE_EQUIVALENCE 0x2u /* Section "Reduction by Equivalence Relation" */
@@ -109,6 +114,16 @@ typedef struct {
      * representative, depth 0.  One reduction per build: any other value of
      * reduce is SPC_ERR_INVALID_ARG. */
     uint32_t reduce;
+    /* SPC_PROPAGATE_PULL (0, Alg. 2), SPC_PROPAGATE_PUSH (Alg. 1: from round 2
+     * on, every vertex scatters its newest entries to its neighbours, the
+     * pushes are sorted and equal hubs merged before elimination and
+     * pruning), or SPC_PROPAGATE_AUTO (push in a round whose pushes are
+     * fewer than the adjacency slots, else pull).  The index is the same
+     * either way.  Pushing needs a validated graph (validate nonzero);
+     * without validation every round pulls.  Other values:
+     * SPC_ERR_INVALID_ARG. */
+    uint32_t propagation;
+    uint32_t reserved;   /* must be 0 */
 } spc_build_opts;
 
 typedef struct {

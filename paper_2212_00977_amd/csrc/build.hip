@@ -1242,6 +1242,11 @@ struct Build {
     uint32_t k = 1;
     std::vector<uint32_t> vbase, gn;
     bool simple = false;  // the input was validated simple and symmetric
+    uint32_t prop = 0;    // SPC_PROPAGATE_*
+    // PUSH rounds: every puller's merged candidates as the segment of one
+    // virtual neighbour (itself)
+    uint64_t *vgoff = nullptr, *vpstart = nullptr;
+    uint32_t *vgadj = nullptr, *vplen = nullptr;
     ShellResult shell;  // SPC_REDUCE_*: what was cut off, and the core ids
     bool reduced = false;
     uint32_t *hub_w = nullptr;  // neighbourhood equivalence: class size per rank
@@ -1722,6 +1727,88 @@ __global__ __launch_bounds__(kBlock) void k_round1_keys(uint32_t u_lo, uint32_t 
         if (lane == 0) surv[u] = (uint32_t)(raw_off[u + 1] - raw_off[u]);
     }
 }
+// PUSH propagation (Alg. 1): every pusher v scatters the entries of its
+// round d-1 segment whose hub lies below a neighbour u to u, for the pullers
+// u of the batch [u_lo, u_hi); one wave per pusher, one lane per neighbour.
+// A puller's slots start at its raw offset: it receives exactly the entries
+// the pull would read.  Counts are multiplied by the pusher's weight (vw,
+// neighbourhood equivalence), which lies inside every path it extends.
+__global__ __launch_bounds__(kBlock) void k_push_scatter(uint32_t N, uint32_t u_lo, uint32_t u_hi,
+                                                          const uint64_t *goff, const uint32_t *gadj,
+                                                          const uint64_t *pstart, const uint32_t *plen,
+                                                          const uint32_t *pool_hub, const uint64_t *pool_cnt,
+                                                          const uint32_t *vw, const uint64_t *raw_off,
+                                                          uint32_t *cursor, uint64_t *keys, uint64_t *cnt) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t nw = gridDim.x * kWaves;
+    for (uint32_t v = blockIdx.x * kWaves + (threadIdx.x >> 6); v < N; v += nw) {
+        const uint32_t ln = plen[v];
+        if (!ln) continue;
+        const uint64_t ps = pstart[v];
+        const uint64_t f = vw ? vw[v] : 1;
+        for (uint64_t k = goff[v] + lane; k < goff[v + 1]; k += 64) {
+            const uint32_t u = gadj[k];
+            if (u < u_lo || u >= u_hi) continue;
+            const uint32_t p = (v < u) ? ln : lower_bound_u32(pool_hub + ps, ln, u);
+            if (!p) continue;
+            const uint32_t pos = atomicAdd(&cursor[u - u_lo], p);
+            // u's slots end at its next raw offset (a symmetric graph fills
+            // them exactly; the bound only guards the writes)
+            const uint64_t lim = raw_off[u + 1] - raw_off[u_lo];
+            const uint32_t q = pos >= lim ? 0u : (uint32_t)std::min<uint64_t>(p, lim - pos);
+            for (uint32_t j = 0; j < q; j++) {
+                keys[pos + j] = ((uint64_t)(u - u_lo) << 32) | pool_hub[ps + j];
+                cnt[pos + j] = sat_mul(pool_cnt[ps + j], f);
+            }
+        }
+    }
+}
+__global__ void k_push_cursor(uint32_t u_lo, uint32_t n, const uint64_t *raw_off, uint32_t *cursor,
+                              uint32_t *idx, uint64_t need) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < need || i < n; i += stride) {
+        if (i < n) cursor[i] = (uint32_t)(raw_off[u_lo + i] - raw_off[u_lo]);
+        if (i < need) idx[i] = (uint32_t)i;
+    }
+}
+__global__ void k_push_heads(const uint64_t *keys, uint64_t n, uint32_t *head) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+// Label Merging of the sorted pushes: one entry per (puller, hub), its
+// counts summed
+__global__ void k_push_unique(const uint64_t *keys, const uint32_t *idx, const uint64_t *cnt,
+                              const uint32_t *head, const uint64_t *hpos, uint64_t n, uint32_t *uhub,
+                              uint64_t *ucnt) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (!head[i]) continue;
+        uint64_t sum = cnt[idx[i]];
+        for (uint64_t j = i + 1; j < n && !head[j]; j++) sum = sat_add(sum, cnt[idx[j]]);
+        uhub[hpos[i]] = (uint32_t)keys[i];
+        ucnt[hpos[i]] = sum;
+    }
+}
+// each puller's merged candidates as the segment of one virtual neighbour
+// (itself)
+__global__ void k_push_segs(uint32_t u_lo, uint32_t u_hi, const uint64_t *raw_off, const uint64_t *hpos,
+                            uint64_t *vpstart, uint32_t *vplen) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t u = u_lo + blockIdx.x * blockDim.x + threadIdx.x; u < u_hi; u += stride) {
+        const uint64_t t0 = raw_off[u] - raw_off[u_lo], t1 = raw_off[u + 1] - raw_off[u_lo];
+        vpstart[u] = hpos[t0];
+        vplen[u] = (uint32_t)(hpos[t1] - hpos[t0]);
+    }
+}
+__global__ void k_iota_adj(uint32_t N, uint64_t *off, uint32_t *adj) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v <= N; v += stride) {
+        off[v] = v;
+        if (v < N) adj[v] = v;
+    }
+}
+
 // sorted keys -> hubs and unit counts (the keys live in the count array)
 __global__ void k_round1_out(uint64_t n, uint32_t *hub, uint64_t *cnt) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1782,6 +1869,21 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     uint64_t kept = 0, fast_raw = 0;
     double round_ms = 0;
     const bool fast1 = d == 1 && B.simple;
+    // PUSH (Alg. 1) every round from 2 on, or where the pushes are fewer than
+    // the adjacency slots the pull would walk (SPC_PROPAGATE_AUTO)
+    // (validated input only: the pushes fill exactly the pull's slots when
+    // the graph is symmetric)
+    const bool push = d >= 2 && B.simple &&
+                      (B.prop == SPC_PROPAGATE_PUSH || (B.prop == SPC_PROPAGATE_AUTO && total_raw < B.NNZ));
+    if (push && !B.vgoff) {
+        SPC_TRY(B.arena.alloc(&B.vgoff, (uint64_t)N + 1));
+        SPC_TRY(B.arena.alloc(&B.vgadj, (uint64_t)N + 1));
+        SPC_TRY(B.arena.alloc(&B.vpstart, (uint64_t)N + 1));
+        SPC_TRY(B.arena.alloc(&B.vplen, (uint64_t)N + 1));
+        hipLaunchKernelGGL(k_iota_adj, dim3(grid_stride((uint64_t)N + 1)), dim3(kBlock), 0, B.st, N, B.vgoff,
+                           B.vgadj);
+        SPC_LAUNCHED();
+    }
     for (size_t bi = 0; bi + 1 < bounds.size(); bi++) {
         uint32_t b0 = bounds[bi], b1 = bounds[bi + 1];
         uint64_t r2[2];
@@ -1800,6 +1902,47 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
             SPC_TRY(B.arena.alloc(&B.tmp_hub, cap));
             SPC_TRY(B.arena.alloc(&B.tmp_cnt, cap));
             B.tmp_cap = cap;
+        }
+        // PUSH: scatter, sort by (puller, hub), merge equal hubs
+        uint64_t *pkeys = nullptr, *pkeys2 = nullptr, *pcnt = nullptr, *phpos = nullptr, *pws = nullptr,
+                 *pucnt = nullptr;
+        uint32_t *pidx = nullptr, *pidx2 = nullptr, *phead = nullptr, *pcur = nullptr, *puhub = nullptr;
+        if (push) {
+            const uint64_t n1 = std::max<uint64_t>(need, 1);
+            SPC_TRY(B.arena.alloc(&pkeys, n1));
+            SPC_TRY(B.arena.alloc(&pkeys2, n1));
+            SPC_TRY(B.arena.alloc(&pcnt, n1));
+            SPC_TRY(B.arena.alloc(&pidx, n1));
+            SPC_TRY(B.arena.alloc(&pidx2, n1));
+            SPC_TRY(B.arena.alloc(&phead, n1));
+            SPC_TRY(B.arena.alloc(&phpos, n1 + 1));
+            SPC_TRY(B.arena.alloc(&puhub, n1));
+            SPC_TRY(B.arena.alloc(&pucnt, n1));
+            SPC_TRY(B.arena.alloc(&pcur, (uint64_t)(b1 - b0) + 1));
+            SPC_TRY(B.arena.alloc(&pws, std::max(radix_ws_elems(n1), scan_ws_elems(n1 + 1))));
+            hipLaunchKernelGGL(k_push_cursor, dim3(grid_stride(std::max<uint64_t>(need, b1 - b0))), dim3(kBlock),
+                               0, B.st, b0, b1 - b0, B.raw_off, pcur, pidx, need);
+            SPC_LAUNCHED();
+            hipLaunchKernelGGL(k_push_scatter, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, b0, b1,
+                               B.goff, B.gadj, pstart, plen, B.rhub[d - 1], B.rcnt[d - 1], B.hub_w, B.raw_off,
+                               pcur, pkeys, pcnt);
+            SPC_LAUNCHED();
+            if (need) {
+                SPC_TRY(radix_sort_pairs(pkeys, pidx, pkeys2, pidx2, need, 32 + std::max(1, bit_width(b1 - b0)),
+                                         pws, B.st));
+                hipLaunchKernelGGL(k_push_heads, dim3(grid_stride(need)), dim3(kBlock), 0, B.st, pkeys, need,
+                                   phead);
+                SPC_LAUNCHED();
+                SPC_TRY(scan_u32(phead, phpos, need, pws, B.st));
+                hipLaunchKernelGGL(k_push_unique, dim3(grid_stride(need)), dim3(kBlock), 0, B.st, pkeys, pidx,
+                                   pcnt, phead, phpos, need, puhub, pucnt);
+                SPC_LAUNCHED();
+            } else {
+                SPC_HIP(hipMemsetAsync(phpos, 0, sizeof(uint64_t), B.st));
+            }
+            hipLaunchKernelGGL(k_push_segs, dim3(grid_stride(b1 - b0)), dim3(kBlock), 0, B.st, b0, b1, B.raw_off,
+                               phpos, B.vpstart, B.vplen);
+            SPC_LAUNCHED();
         }
         RoundArgs ra;
         ra.d = d;
@@ -1822,6 +1965,14 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         // vertex weights (neighbourhood equivalence): from round 2 on, a
         // pulled entry (w, d-1) of v extends paths that pass through v
         ra.adj_w = B.adj_w;
+        if (push) {  // the pushes, merged, arrive through one virtual neighbour
+            ra.goff = B.vgoff;
+            ra.gadj = B.vgadj;
+            ra.pstart = B.vpstart;
+            ra.plen = B.vplen;
+            ra.pool_hub = puhub;
+            ra.pool_cnt = pucnt;
+        }
         ra.raw_off = B.raw_off;
         ra.tmp_hub = B.tmp_hub;
         ra.tmp_cnt = B.tmp_cnt;
@@ -1832,7 +1983,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         SPC_HIP(hipEventRecord(B.ev_a, B.st));
         // from round 17 on the graph has a long diameter: there, neighbours'
         // labels are nearly the same set, which the tail merge exploits
-        const bool weighted = B.adj_w && d >= 2;
+        const bool weighted = B.adj_w && d >= 2 && !push;  // pushes carry their weights
         const dim3 grid(b1 - b0), blk(kRoundBlock);
         if (fast1) {
             // the keys are built in the count array, sorted there, then
@@ -1867,6 +2018,10 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         SPC_LAUNCHED();
         if (!fast1) B.launches++;
         SPC_HIP(hipEventRecord(B.ev_b, B.st));
+        if (push) {
+            for (uint64_t *q : {pkeys, pkeys2, pcnt, phpos, pws, pucnt}) B.arena.release(q);
+            for (uint32_t *q : {pidx, pidx2, phead, pcur, puhub}) B.arena.release(q);
+        }
         SPC_TRY(scan_u32(B.surv + b0, B.soff, b1 - b0, B.ws, B.st));
         uint64_t sb;
         SPC_TRY(B.read_u64(B.soff + (b1 - b0), &sb));
@@ -1900,7 +2055,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     uint64_t c[8];
     SPC_TRY(B.read_u64((const uint64_t *)B.ctr, c, 8));
     RoundCounters rc;
-    rc.raw = c[0] + fast_raw;
+    rc.raw = push ? total_raw : c[0] + fast_raw;  // a push round's kernel reads merged candidates
     rc.merged = c[1] + fast_raw;
     rc.kept = c[2] + fast_raw;
     rc.scanned = c[3];
@@ -2098,6 +2253,7 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     // one reduction at a time
     if (o->reduce != 0 && o->reduce != SPC_REDUCE_ONE_SHELL && o->reduce != SPC_REDUCE_EQUIVALENCE)
         return SPC_ERR_INVALID_ARG;
+    if (o->propagation > SPC_PROPAGATE_AUTO || o->reserved != 0) return SPC_ERR_INVALID_ARG;
     if (o->dist_bits != 0 && o->dist_bits != 8 && o->dist_bits != 16) return SPC_ERR_INVALID_ARG;
     uint64_t N64 = 0, NNZ = 0;
     uint32_t n_order = 0, n_tie = 0, n_dev = 0;
@@ -2136,6 +2292,7 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     }
     B.N = (uint32_t)N64;
     B.NNZ = NNZ;
+    B.prop = o->propagation;
     B.k = k;
     B.db = db;
     {

@@ -73,7 +73,8 @@ class SpcGraph(C.Structure):
 
 class SpcBuildOpts(C.Structure):
     _fields_ = [("dist_bits", C.c_uint32), ("round_cap", C.c_uint32),
-                ("mem_budget", C.c_uint64), ("validate", C.c_uint32), ("reduce", C.c_uint32)]
+                ("mem_budget", C.c_uint64), ("validate", C.c_uint32), ("reduce", C.c_uint32),
+                ("propagation", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 _lib = None

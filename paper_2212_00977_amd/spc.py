@@ -94,6 +94,7 @@ class BuildOptions:
     validate: bool = True
     one_shell: bool = False  # SPC_REDUCE_ONE_SHELL: label the 2-core only
     equivalence: bool = False  # SPC_REDUCE_EQUIVALENCE: one weighted vertex per class of twins
+    propagation: str = "pull"  # "pull" (Alg. 2), "push" (Alg. 1) or "auto" (chosen per round)
 
     def struct(self):
         o = native.SpcBuildOpts()
@@ -102,6 +103,8 @@ class BuildOptions:
         o.mem_budget = self.mem_budget
         o.validate = 1 if self.validate else 0
         o.reduce = (1 if self.one_shell else 0) | (2 if self.equivalence else 0)
+        o.propagation = {"pull": 0, "push": 1, "auto": 2}[self.propagation]
+        o.reserved = 0
         return o
 
 

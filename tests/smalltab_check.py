@@ -62,6 +62,17 @@ def main():
             rd, rc = red.query(s, t)
             assert np.array_equal(d, rd) and np.array_equal(c, rc), (g.name, kind)
             ix.free()
+    # PUSH rounds: the merged pushes through one virtual neighbour, same paths
+    for g in (inputs.rmat(12, 16, seed=5), inputs.chung_lu(1 << 13, seed=2)):
+        print(f"[case] small tables push: {g.name} n={g.n}", flush=True)
+        ix = spc.build_graph(g, opts=spc.BuildOptions(propagation="push"))
+        ref = oracle.build_graph(g, method="pull")
+        assert_labels_equal(ix.export(), ref, f"{g.name} push")
+        rs = ix.round_stats()
+        k = len(ref.stats["kept"])
+        for key in ("raw", "merged", "kept"):
+            assert np.array_equal(rs[key][:k], ref.stats[key]), (g.name, key, "push")
+        ix.free()
     print("small tables ok", flush=True)
     return 0
 

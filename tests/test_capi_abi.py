@@ -73,7 +73,13 @@ def test_bad_options_rejected_on_host(lib):
     o.dist_bits = 12
     assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
     o.dist_bits = 0
-    o.reduce = 6  # only SPC_REDUCE_ONE_SHELL is defined
+    o.reduce = 6  # one reduction at a time
+    assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
+    o.reduce = 0
+    o.propagation = 3  # pull, push or auto
+    assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
+    o.propagation = 0
+    o.reserved = 1
     assert lib.spc_build_index(C.byref(g), C.byref(o), None, C.byref(out)) == 1
     assert out.value is None
 
