@@ -83,6 +83,26 @@ class ServeStats:
                 "makespan_s": self.makespan_s}
 
 
+def take_batch(queue, used: int, budget: int, any_inflight: bool, coalesce: bool, max_batch: int) -> int:
+    """How many requests from the head of `queue` (arrival order) the next
+    launch takes: while their inputs and outputs fit the I/O budget beside
+    the `used` bytes in flight (a request larger than the whole budget still
+    runs alone once nothing is in flight), all of one graph, at most
+    max_batch queries together, one request when not coalescing.  0 means
+    the head request waits for memory."""
+    n, nb, nq = 0, 0, 0
+    for r in queue:
+        need = int(r.s.shape[0]) * BYTES_PER_QUERY_IO
+        if used + nb + need > budget and (n or any_inflight):
+            break
+        if n and (not coalesce or nq + int(r.s.shape[0]) > max_batch or r.graph_id != queue[0].graph_id):
+            break
+        n += 1
+        nb += need
+        nq += int(r.s.shape[0])
+    return n
+
+
 class Server:
     """Continuous-batching query server over one resident index.
 
@@ -187,18 +207,8 @@ class Server:
                 k = min(range(len(self.streams)), key=lambda i: busy[i])
                 if busy[k] >= 2:
                     break
-                batch, nb = [], 0
-                while queue:
-                    r = queue[0]
-                    need = int(r.s.shape[0]) * BYTES_PER_QUERY_IO
-                    if used + nb + need > self.budget and (batch or inflight):
-                        break
-                    if batch and (not self.coalesce or
-                                  sum(x.s.shape[0] for x in batch) + r.s.shape[0] > self.max_batch
-                                  or r.graph_id != batch[0].graph_id):
-                        break
-                    batch.append(queue.popleft())
-                    nb += need
+                n = take_batch(queue, used, self.budget, bool(inflight), self.coalesce, self.max_batch)
+                batch = [queue.popleft() for _ in range(n)]
                 if not batch:
                     deferred.update(r.rid for r in queue)  # waiting for memory
                     break
