@@ -1,0 +1,24 @@
+"""bench.py's command line on the host: more than one GPU is refused with a
+message before any device work, and the help lists the workloads."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_help_lists_workloads_and_options():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 0
+    for w in ("chunglu", "rmat_batch", "rmat_served", "grid", "--propagation", "--one-shell", "--equivalence"):
+        assert w in r.stdout, w
