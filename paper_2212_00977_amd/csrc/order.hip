@@ -47,15 +47,7 @@ spc_status hybrid_order_impl(const spc_graph *g, uint32_t delta, uint32_t *order
         if (adj[v].size() <= delta) heap.push({(uint32_t)adj[v].size(), v});
     std::vector<uint32_t> elim;
     elim.reserve(n);
-    auto link = [&](uint32_t a, uint32_t b) {  // add edge a-b if absent
-        auto &x = adj[a];
-        auto it = std::lower_bound(x.begin(), x.end(), b);
-        if (it != x.end() && *it == b) return false;
-        x.insert(it, b);
-        auto &y = adj[b];
-        y.insert(std::lower_bound(y.begin(), y.end(), a), a);
-        return true;
-    };
+    std::vector<uint32_t> merged;
     while (!heap.empty()) {
         const Item top = heap.top();
         heap.pop();
@@ -66,12 +58,27 @@ spc_status hybrid_order_impl(const spc_graph *g, uint32_t delta, uint32_t *order
         elim.push_back(v);
         const std::vector<uint32_t> nb = std::move(adj[v]);
         adj[v].clear();
+        // each remaining neighbour loses v and gains the others (fill-in):
+        // one sorted union per neighbour rather than one insertion per edge
         for (uint32_t a : nb) {
-            auto &x = adj[a];
-            x.erase(std::lower_bound(x.begin(), x.end(), v));
+            const auto &x = adj[a];
+            merged.clear();
+            merged.reserve(x.size() + nb.size());
+            size_t i = 0, j = 0;
+            while (i < x.size() || j < nb.size()) {
+                uint32_t c;
+                if (j >= nb.size() || (i < x.size() && x[i] < nb[j])) {
+                    c = x[i++];
+                } else if (i >= x.size() || nb[j] < x[i]) {
+                    c = nb[j++];
+                } else {
+                    c = x[i++];
+                    j++;
+                }
+                if (c != a && c != v) merged.push_back(c);
+            }
+            adj[a].swap(merged);
         }
-        for (size_t i = 0; i < nb.size(); i++)
-            for (size_t j = i + 1; j < nb.size(); j++) link(nb[i], nb[j]);
         for (uint32_t a : nb)
             if (adj[a].size() <= delta) heap.push({(uint32_t)adj[a].size(), a});
     }
