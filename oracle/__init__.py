@@ -31,8 +31,8 @@ _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 def build_oracle(force: bool = True) -> str:
     """Compile liboracle.so in-tree with gcc."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=199309L", "-Wall", "-Wextra",
-               "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
+        cmd = ["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-Wall", "-Wextra",
+               "-shared", "-fPIC", "-pthread", "-o", _LIB + ".tmp", _SRC]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -63,6 +63,15 @@ def lib():
         f = getattr(L, nm)
         f.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32]
         f.restype = vp
+    L.oracle_build_pull_threads.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, C.c_uint32]
+    L.oracle_build_pull_threads.restype = vp
+    L.oracle_index_model_stats.argtypes = [vp, _u64p, _u64p, _u64p]
+    L.oracle_index_model_stats.restype = None
+    L.oracle_query_arrays_threads.argtypes = [_u64p, _u32p, _u32p, _u64p, C.c_uint64, _u32p,
+                                              _u32p, _u32p, _u64p, C.c_uint32]
+    L.oracle_query_arrays_threads.restype = None
+    L.oracle_label_hubs.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, _u32p, _u32p]
+    L.oracle_label_hubs.restype = C.c_uint64
     L.oracle_build_definition_weighted.argtypes = [C.c_uint32, _u64p, _u32p, _u64p, C.c_uint32]
     L.oracle_build_definition_weighted.restype = vp
     L.oracle_build_pruned.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, C.c_uint32,
@@ -165,14 +174,35 @@ class Labels:
         return query_arrays(self.off, self.hub, self.dist, self.count, s, t)
 
 
-def query_arrays(off, hub, dist, count, s, t):
-    """Query over label arrays (ids in the labels' own space)."""
+def query_arrays(off, hub, dist, count, s, t, threads: int = 1):
+    """Query over label arrays (ids in the labels' own space); `threads`
+    splits the batch over that many host threads."""
     s, t = _u32(s), _u32(t)
     q = s.shape[0]
     od = np.zeros(q, dtype=np.uint32)
     oc = np.zeros(q, dtype=np.uint64)
-    lib().oracle_query_arrays(_u64(off), _u32(hub), _u32(dist), _u64(count), q, s, t, od, oc)
+    lib().oracle_query_arrays_threads(_u64(off), _u32(hub), _u32(dist), _u64(count), q, s, t,
+                                      od, oc, max(1, int(threads)))
     return od, oc
+
+
+def label_hubs(roff, radj, s: int):
+    """Hubs of L(s) and their distances from the definition, without counts
+    (rank-space graph): (hub uint32[], dist uint32[]) in hub order."""
+    roff, radj = _u64(roff), _u32(radj)
+    n = roff.shape[0] - 1
+    h = np.zeros(max(n, 1), dtype=np.uint32)
+    d = np.zeros(max(n, 1), dtype=np.uint32)
+    k = lib().oracle_label_hubs(n, roff, radj, int(s), h, d)
+    return h[:k].copy(), d[:k].copy()
+
+
+def host_threads() -> int:
+    """Threads the host offers this process (its CPU affinity)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def _collect(h, n, order, with_stats: bool) -> Labels:
@@ -188,9 +218,12 @@ def _collect(h, n, order, with_stats: bool) -> Labels:
         stats = None
         if with_stats:
             k = rounds + 1
-            raw, mer, kept, scan = (np.zeros(k, dtype=np.uint64) for _ in range(4))
+            raw, mer, kept, scan, act, act_adj, staged = (np.zeros(k, dtype=np.uint64)
+                                                          for _ in range(7))
             L.oracle_index_round_stats(h, raw, mer, kept, scan)
-            stats = dict(raw=raw, merged=mer, kept=kept, scanned=scan)
+            L.oracle_index_model_stats(h, act, act_adj, staged)
+            stats = dict(raw=raw, merged=mer, kept=kept, scanned=scan, active=act,
+                         active_adj=act_adj, staged=staged)
         return Labels(n, off, hub, dist, cnt, order, int(rounds), int(L.oracle_index_hubs_done(h)),
                       stats)
     finally:
@@ -207,8 +240,10 @@ def _prep(off, adj, order, tie_key):
 
 
 def build(off, adj, order=None, tie_key=None, method: str = "pruned", depth_cap: int = 0,
-          max_hubs: int = 0, time_limit_s: float = 0.0) -> Labels:
-    """Build the label index; method in {"definition", "pruned", "pull"}."""
+          max_hubs: int = 0, time_limit_s: float = 0.0, threads: int = 1) -> Labels:
+    """Build the label index; method in {"definition", "pruned", "pull"};
+    `threads` spreads each PULL round's pullers over that many host
+    threads (same result)."""
     n, roff, radj, order = _prep(off, adj, order, tie_key)
     L = lib()
     if method == "definition":
@@ -216,7 +251,7 @@ def build(off, adj, order=None, tie_key=None, method: str = "pruned", depth_cap:
     elif method == "pruned":
         h = L.oracle_build_pruned(n, roff, radj, depth_cap, max_hubs, time_limit_s)
     elif method == "pull":
-        h = L.oracle_build_pull(n, roff, radj, depth_cap)
+        h = L.oracle_build_pull_threads(n, roff, radj, depth_cap, max(1, int(threads)))
     else:
         raise ValueError(method)
     return _collect(h, n, order, with_stats=(method == "pull"))

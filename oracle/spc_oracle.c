@@ -33,6 +33,7 @@
  */
 #include "spc_oracle.h"
 
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
@@ -215,7 +216,8 @@ struct oracle_index {
     uint32_t rounds;
     uint32_t hubs_done;
     uint64_t *st_raw, *st_merged, *st_kept, *st_scanned;
-    uint32_t st_cap;
+    uint64_t *st_active, *st_active_adj, *st_staged;
+    uint32_t st_cap, st_model_cap;
 };
 
 static oracle_index *index_new(uint32_t n)
@@ -260,6 +262,33 @@ static void stats_round(oracle_index *ix, uint32_t d, uint64_t raw, uint64_t mer
     ix->st_merged[d] = merged;
     ix->st_kept[d] = kept;
     ix->st_scanned[d] = scanned;
+}
+
+/* Byte-model inputs of round d (PULL builds; rounds_stats must have run for
+ * d first): pullers with at least one candidate passing the rank rule, their
+ * adjacency slots, and the label entries (all of distance < d) of the
+ * pullers with at least one merged candidate. */
+static void stats_model(oracle_index *ix, uint32_t d, uint64_t active, uint64_t active_adj,
+                        uint64_t staged)
+{
+    if (!ix->st_active) {
+        ix->st_active = xcalloc(ix->st_cap, sizeof(uint64_t));
+        ix->st_active_adj = xcalloc(ix->st_cap, sizeof(uint64_t));
+        ix->st_staged = xcalloc(ix->st_cap, sizeof(uint64_t));
+        ix->st_model_cap = ix->st_cap;
+    }
+    if (ix->st_model_cap < ix->st_cap) {
+        ix->st_active = realloc(ix->st_active, sizeof(uint64_t) * ix->st_cap);
+        ix->st_active_adj = realloc(ix->st_active_adj, sizeof(uint64_t) * ix->st_cap);
+        ix->st_staged = realloc(ix->st_staged, sizeof(uint64_t) * ix->st_cap);
+        if (!ix->st_active || !ix->st_active_adj || !ix->st_staged) abort();
+        for (uint32_t i = ix->st_model_cap; i < ix->st_cap; i++)
+            ix->st_active[i] = ix->st_active_adj[i] = ix->st_staged[i] = 0;
+        ix->st_model_cap = ix->st_cap;
+    }
+    ix->st_active[d] = active;
+    ix->st_active_adj[d] = active_adj;
+    ix->st_staged[d] = staged;
 }
 
 static uint32_t max_label_dist(const oracle_index *ix)
@@ -465,12 +494,208 @@ oracle_index *oracle_build_pruned(uint32_t n, const uint64_t *off, const uint32_
 /* < d can give a distance < d, so the query reads no entry of round d and   */
 /* the rounds have no intra-round dependency.  The build stops after the     */
 /* first round with no survivor (or at the depth cap).                       */
+/*                                                                           */
+/* Within a round the pullers are independent (the paper's parallel         */
+/* construction runs them on threads), so the same per-puller step can run  */
+/* on several threads: each takes blocks of pullers from a shared counter,  */
+/* and the survivors are put in puller order before round d is inserted.    */
+/* The result does not depend on the thread count.                          */
 /* ------------------------------------------------------------------------ */
-oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t *adj,
-                                uint32_t depth_cap)
+typedef struct {
+    uint64_t *acc;     /* merged count per hub */
+    uint8_t *seen;     /* hub collected for this u */
+    uint32_t *touched; /* hubs collected for this u */
+    uint32_t *udist;   /* d_u(h) over u's entries (all of distance < d) */
+} pull_scratch;
+
+typedef struct { /* survivors of the pullers one thread handled, in its order */
+    uint32_t *hub;
+    uint64_t *cnt;
+    uint64_t len, cap;
+} pull_out;
+
+typedef struct {
+    uint64_t raw, merged, kept, scanned;
+    uint64_t active, active_adj, staged; /* inputs of the byte model, see below */
+} pull_counts;
+
+static void pull_scratch_init(pull_scratch *sc, uint32_t n)
+{
+    sc->acc = xcalloc(n, sizeof(uint64_t));
+    sc->seen = xcalloc(n, 1);
+    sc->touched = xmalloc(sizeof(uint32_t) * (size_t)n);
+    sc->udist = xmalloc(sizeof(uint32_t) * (size_t)n);
+    for (uint32_t i = 0; i < n; i++) sc->udist[i] = ORACLE_INF;
+}
+
+static void pull_scratch_free(pull_scratch *sc)
+{
+    free(sc->acc);
+    free(sc->seen);
+    free(sc->touched);
+    free(sc->udist);
+}
+
+static void pull_out_push(pull_out *o, uint32_t hub, uint64_t cnt)
+{
+    if (o->len == o->cap) {
+        o->cap = o->cap ? 2 * o->cap : 1024;
+        o->hub = realloc(o->hub, sizeof(uint32_t) * o->cap);
+        o->cnt = realloc(o->cnt, sizeof(uint64_t) * o->cap);
+        if (!o->hub || !o->cnt) abort();
+    }
+    o->hub[o->len] = hub;
+    o->cnt[o->len] = cnt;
+    o->len++;
+}
+
+/* Round d for one puller u: appends u's survivors (hub order) to `out`.
+ * Reads the labels (entries of distance < d) and the round d-1 entries
+ * prev_*; writes nothing shared. */
+static void pull_vertex(const oracle_index *ix, const uint64_t *off, const uint32_t *adj,
+                        const uint64_t *prev_off, const uint32_t *prev_hub,
+                        const uint64_t *prev_cnt, uint32_t u, uint32_t d, pull_scratch *sc,
+                        pull_out *out, pull_counts *ct)
+{
+    const olabel *lu = &ix->lab[u];
+    uint64_t raw = 0;
+    /* all entries of u so far have distance < d */
+    for (uint64_t i = 0; i < lu->len; i++) sc->udist[lu->hub[i]] = lu->dist[i];
+    uint32_t ntouch = 0;
+    for (uint64_t k = off[u]; k < off[u + 1]; k++) {
+        uint32_t v = adj[k];
+        for (uint64_t i = prev_off[v]; i < prev_off[v + 1]; i++) {
+            uint32_t w = prev_hub[i];
+            if (w >= u) continue; /* rank rule: w must outrank u */
+            raw++;
+            if (sc->udist[w] != ORACLE_INF) continue; /* Label Elimination */
+            if (!sc->seen[w]) {
+                sc->seen[w] = 1;
+                sc->touched[ntouch++] = w;
+            }
+            sc->acc[w] = sat_add(sc->acc[w], prev_cnt[i]); /* Label Merging */
+        }
+    }
+    ct->raw += raw;
+    if (raw) {
+        ct->active++;
+        ct->active_adj += off[u + 1] - off[u];
+    }
+    ct->merged += ntouch;
+    if (ntouch) ct->staged += lu->len;
+    qsort(sc->touched, ntouch, sizeof(uint32_t), cmp_u32);
+    for (uint32_t j = 0; j < ntouch; j++) {
+        uint32_t w = sc->touched[j];
+        /* Query(w, u, entries of distance < d).  The counter `scanned` is the
+         * number of entries a scan of L(w) in hub order reads up to and
+         * including the first hub that proves a shorter distance (all of L(w)
+         * when none does); L(w) is stored here in insertion order, so it
+         * counts the entries whose hub is at most the smallest proving hub. */
+        const olabel *lw = &ix->lab[w];
+        int pruned = 0;
+        uint32_t hmin = ORACLE_INF;
+        for (uint64_t i = 0; i < lw->len; i++) {
+            uint32_t du = sc->udist[lw->hub[i]];
+            if (lw->dist[i] >= d) continue; /* entries of round >= d are not read */
+            if (du != ORACLE_INF && du + lw->dist[i] < d) {
+                pruned = 1;
+                if (lw->hub[i] < hmin) hmin = lw->hub[i];
+            }
+        }
+        if (pruned) {
+            for (uint64_t i = 0; i < lw->len; i++) ct->scanned += lw->hub[i] <= hmin;
+        } else {
+            ct->scanned += lw->len;
+            pull_out_push(out, w, sc->acc[w]);
+            ct->kept++;
+        }
+        sc->acc[w] = 0;
+        sc->seen[w] = 0;
+    }
+    for (uint64_t i = 0; i < lu->len; i++) sc->udist[lu->hub[i]] = ORACLE_INF;
+}
+
+#define PULL_BLOCK 64u
+
+typedef struct pull_round pull_round;
+typedef struct {
+    pull_round *r;
+    pull_scratch sc;
+    pull_out out;
+    pull_counts ct;
+    uint32_t id;
+} pull_worker;
+
+struct pull_round { /* shared by the workers of one round */
+    oracle_index *ix;
+    const uint64_t *off;
+    const uint32_t *adj;
+    const uint64_t *prev_off;
+    const uint32_t *prev_hub;
+    const uint64_t *prev_cnt;
+    uint32_t n, d;
+    uint32_t next;     /* next block of pullers (atomic) */
+    uint32_t *owner;   /* per u: worker that pulled it */
+    uint64_t *ustart;  /* per u: first survivor in that worker's buffer */
+    uint64_t *ulen;    /* per u: survivors */
+    uint64_t *cur_off; /* phase 2: round d in puller order */
+    uint32_t *cur_hub;
+    uint64_t *cur_cnt;
+    pull_worker *w;
+    int phase;         /* 1: pull; 2: gather + insert */
+};
+
+static void *pull_worker_run(void *arg)
+{
+    pull_worker *me = arg;
+    pull_round *r = me->r;
+    for (;;) {
+        uint32_t b = __atomic_fetch_add(&r->next, PULL_BLOCK, __ATOMIC_RELAXED);
+        if (b >= r->n) break;
+        uint32_t e = (r->n - b < PULL_BLOCK) ? r->n : b + PULL_BLOCK;
+        for (uint32_t u = b; u < e; u++) {
+            if (r->phase == 1) {
+                r->owner[u] = me->id;
+                r->ustart[u] = me->out.len;
+                pull_vertex(r->ix, r->off, r->adj, r->prev_off, r->prev_hub, r->prev_cnt, u, r->d,
+                            &me->sc, &me->out, &me->ct);
+                r->ulen[u] = me->out.len - r->ustart[u];
+            } else { /* copy u's survivors into puller order and insert round d */
+                const pull_out *src = &r->w[r->owner[u]].out;
+                for (uint64_t i = 0; i < r->ulen[u]; i++) {
+                    uint64_t k = r->cur_off[u] + i;
+                    r->cur_hub[k] = src->hub[r->ustart[u] + i];
+                    r->cur_cnt[k] = src->cnt[r->ustart[u] + i];
+                    label_push(&r->ix->lab[u], r->cur_hub[k], r->d, r->cur_cnt[k]);
+                }
+            }
+        }
+    }
+    return NULL;
+}
+
+/* Runs the current phase on nthreads workers (inline when there is one). */
+static void pull_phase(pull_round *r, uint32_t nthreads, int phase)
+{
+    r->phase = phase;
+    r->next = 0;
+    if (nthreads <= 1) {
+        pull_worker_run(&r->w[0]);
+        return;
+    }
+    pthread_t *th = xmalloc(sizeof(pthread_t) * nthreads);
+    for (uint32_t i = 0; i < nthreads; i++)
+        if (pthread_create(&th[i], NULL, pull_worker_run, &r->w[i]) != 0) abort();
+    for (uint32_t i = 0; i < nthreads; i++) pthread_join(th[i], NULL);
+    free(th);
+}
+
+oracle_index *oracle_build_pull_threads(uint32_t n, const uint64_t *off, const uint32_t *adj,
+                                        uint32_t depth_cap, uint32_t nthreads)
 {
     oracle_index *ix = index_new(n);
     if (n == 0) return ix;
+    if (nthreads == 0) nthreads = 1;
     /* previous-round entries of each vertex: prev_hub/prev_cnt at prev_off */
     uint64_t *prev_off = xcalloc((size_t)n + 1, sizeof(uint64_t));
     uint32_t *prev_hub = xmalloc(sizeof(uint32_t) * (size_t)n);
@@ -484,11 +709,21 @@ oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t 
     prev_off[n] = n;
     stats_round(ix, 0, 0, 0, n, 0);
 
-    uint64_t *acc = xcalloc(n, sizeof(uint64_t));   /* merged count per hub */
-    uint8_t *seen = xcalloc(n, 1);                   /* hub collected this u */
-    uint32_t *touched = xmalloc(sizeof(uint32_t) * (size_t)n);
-    uint32_t *udist = xmalloc(sizeof(uint32_t) * (size_t)n); /* d_u(h), entries < d */
-    for (uint32_t i = 0; i < n; i++) udist[i] = ORACLE_INF;
+    pull_round r;
+    memset(&r, 0, sizeof(r));
+    r.ix = ix;
+    r.off = off;
+    r.adj = adj;
+    r.n = n;
+    r.owner = xmalloc(sizeof(uint32_t) * (size_t)n);
+    r.ustart = xmalloc(sizeof(uint64_t) * (size_t)n);
+    r.ulen = xmalloc(sizeof(uint64_t) * (size_t)n);
+    r.w = xcalloc(nthreads, sizeof(pull_worker));
+    for (uint32_t i = 0; i < nthreads; i++) {
+        r.w[i].r = &r;
+        r.w[i].id = i;
+        pull_scratch_init(&r.w[i].sc, n);
+    }
 
     uint32_t d = 1, last = 0;
     for (;; d++) {
@@ -496,86 +731,43 @@ oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t 
             last = d - 1;
             break;
         }
-        uint64_t *cur_off = xcalloc((size_t)n + 1, sizeof(uint64_t));
-        uint64_t cur_cap = 1024, cur_len = 0;
-        uint32_t *cur_hub = xmalloc(sizeof(uint32_t) * cur_cap);
-        uint64_t *cur_cnt = xmalloc(sizeof(uint64_t) * cur_cap);
-        uint64_t s_raw = 0, s_merged = 0, s_kept = 0, s_scanned = 0;
-        for (uint32_t u = 0; u < n; u++) {
-            cur_off[u] = cur_len;
-            olabel *lu = &ix->lab[u];
-            /* all entries of u so far have distance < d */
-            for (uint64_t i = 0; i < lu->len; i++) udist[lu->hub[i]] = lu->dist[i];
-            uint32_t ntouch = 0;
-            for (uint64_t k = off[u]; k < off[u + 1]; k++) {
-                uint32_t v = adj[k];
-                for (uint64_t i = prev_off[v]; i < prev_off[v + 1]; i++) {
-                    uint32_t w = prev_hub[i];
-                    if (w >= u) continue; /* rank rule: w must outrank u */
-                    s_raw++;
-                    if (udist[w] != ORACLE_INF) continue; /* Label Elimination */
-                    if (!seen[w]) {
-                        seen[w] = 1;
-                        touched[ntouch++] = w;
-                    }
-                    acc[w] = sat_add(acc[w], prev_cnt[i]); /* Label Merging */
-                }
-            }
-            s_merged += ntouch;
-            qsort(touched, ntouch, sizeof(uint32_t), cmp_u32);
-            for (uint32_t j = 0; j < ntouch; j++) {
-                uint32_t w = touched[j];
-                /* Query(w, u, entries of distance < d).  The counter `scanned`
-                 * is the number of entries a scan of L(w) in hub order reads
-                 * up to and including the first hub that proves a shorter
-                 * distance (all of L(w) when none does); L(w) is stored here
-                 * in insertion order, so it counts the entries whose hub is at
-                 * most the smallest proving hub. */
-                olabel *lw = &ix->lab[w];
-                int pruned = 0;
-                uint32_t hmin = ORACLE_INF;
-                for (uint64_t i = 0; i < lw->len; i++) {
-                    uint32_t du = udist[lw->hub[i]];
-                    if (lw->dist[i] >= d) continue; /* entries of round >= d are not read */
-                    if (du != ORACLE_INF && du + lw->dist[i] < d) {
-                        pruned = 1;
-                        if (lw->hub[i] < hmin) hmin = lw->hub[i];
-                    }
-                }
-                if (pruned) {
-                    for (uint64_t i = 0; i < lw->len; i++) s_scanned += lw->hub[i] <= hmin;
-                } else {
-                    s_scanned += lw->len;
-                }
-                if (!pruned) {
-                    if (cur_len == cur_cap) {
-                        cur_cap *= 2;
-                        cur_hub = realloc(cur_hub, sizeof(uint32_t) * cur_cap);
-                        cur_cnt = realloc(cur_cnt, sizeof(uint64_t) * cur_cap);
-                        if (!cur_hub || !cur_cnt) abort();
-                    }
-                    cur_hub[cur_len] = w;
-                    cur_cnt[cur_len] = acc[w];
-                    cur_len++;
-                }
-                acc[w] = 0;
-                seen[w] = 0;
-            }
-            for (uint64_t i = 0; i < lu->len; i++) udist[lu->hub[i]] = ORACLE_INF;
+        r.d = d;
+        r.prev_off = prev_off;
+        r.prev_hub = prev_hub;
+        r.prev_cnt = prev_cnt;
+        for (uint32_t i = 0; i < nthreads; i++) {
+            r.w[i].out.len = 0;
+            memset(&r.w[i].ct, 0, sizeof(pull_counts));
         }
-        cur_off[n] = cur_len;
-        /* insert round d after every u has been processed */
-        for (uint32_t u = 0; u < n; u++)
-            for (uint64_t i = cur_off[u]; i < cur_off[u + 1]; i++)
-                label_push(&ix->lab[u], cur_hub[i], d, cur_cnt[i]);
-        s_kept = cur_len;
-        stats_round(ix, d, s_raw, s_merged, s_kept, s_scanned);
+        pull_phase(&r, nthreads, 1);
+        pull_counts ct;
+        memset(&ct, 0, sizeof(ct));
+        for (uint32_t i = 0; i < nthreads; i++) {
+            ct.raw += r.w[i].ct.raw;
+            ct.merged += r.w[i].ct.merged;
+            ct.kept += r.w[i].ct.kept;
+            ct.scanned += r.w[i].ct.scanned;
+            ct.active += r.w[i].ct.active;
+            ct.active_adj += r.w[i].ct.active_adj;
+            ct.staged += r.w[i].ct.staged;
+        }
+        /* round d in puller order, then inserted after every u was pulled */
+        uint64_t *cur_off = xmalloc(sizeof(uint64_t) * ((size_t)n + 1));
+        cur_off[0] = 0;
+        for (uint32_t u = 0; u < n; u++) cur_off[u + 1] = cur_off[u] + r.ulen[u];
+        uint64_t cur_len = cur_off[n];
+        r.cur_off = cur_off;
+        r.cur_hub = xmalloc(sizeof(uint32_t) * (size_t)(cur_len ? cur_len : 1));
+        r.cur_cnt = xmalloc(sizeof(uint64_t) * (size_t)(cur_len ? cur_len : 1));
+        pull_phase(&r, nthreads, 2);
+        stats_round(ix, d, ct.raw, ct.merged, ct.kept, ct.scanned);
+        stats_model(ix, d, ct.active, ct.active_adj, ct.staged);
         free(prev_off);
         free(prev_hub);
         free(prev_cnt);
         prev_off = cur_off;
-        prev_hub = cur_hub;
-        prev_cnt = cur_cnt;
+        prev_hub = r.cur_hub;
+        prev_cnt = r.cur_cnt;
         if (cur_len == 0) {
             last = d;
             break;
@@ -585,13 +777,24 @@ oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t 
     free(prev_off);
     free(prev_hub);
     free(prev_cnt);
-    free(acc);
-    free(seen);
-    free(touched);
-    free(udist);
+    for (uint32_t i = 0; i < nthreads; i++) {
+        pull_scratch_free(&r.w[i].sc);
+        free(r.w[i].out.hub);
+        free(r.w[i].out.cnt);
+    }
+    free(r.w);
+    free(r.owner);
+    free(r.ustart);
+    free(r.ulen);
     sort_labels_by_hub(ix);
     ix->hubs_done = n;
     return ix;
+}
+
+oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t *adj,
+                                uint32_t depth_cap)
+{
+    return oracle_build_pull_threads(n, off, adj, depth_cap, 1);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -633,6 +836,17 @@ void oracle_index_round_stats(const oracle_index *ix, uint64_t *raw, uint64_t *m
     }
 }
 
+void oracle_index_model_stats(const oracle_index *ix, uint64_t *active, uint64_t *active_adj,
+                              uint64_t *staged)
+{
+    for (uint32_t d = 0; d <= ix->rounds; d++) {
+        int have = ix->st_active && d < ix->st_model_cap;
+        active[d] = have ? ix->st_active[d] : 0;
+        active_adj[d] = have ? ix->st_active_adj[d] : 0;
+        staged[d] = have ? ix->st_staged[d] : 0;
+    }
+}
+
 void oracle_index_free(oracle_index *ix)
 {
     if (!ix) return;
@@ -646,6 +860,9 @@ void oracle_index_free(oracle_index *ix)
     free(ix->st_merged);
     free(ix->st_kept);
     free(ix->st_scanned);
+    free(ix->st_active);
+    free(ix->st_active_adj);
+    free(ix->st_staged);
     free(ix);
 }
 
@@ -706,4 +923,94 @@ void oracle_query_arrays(const uint64_t *off, const uint32_t *hub, const uint32_
         merge_query(hub + a0, dist + a0, count + a0, a1 - a0, hub + b0, dist + b0, count + b0,
                     b1 - b0, &out_d[i], &out_c[i]);
     }
+}
+
+typedef struct {
+    const uint64_t *off;
+    const uint32_t *hub, *dist;
+    const uint64_t *count;
+    const uint32_t *s, *t;
+    uint32_t *out_d;
+    uint64_t *out_c;
+    uint64_t q0, q1;
+} query_part;
+
+static void *query_part_run(void *arg)
+{
+    query_part *p = arg;
+    oracle_query_arrays(p->off, p->hub, p->dist, p->count, p->q1 - p->q0, p->s + p->q0,
+                        p->t + p->q0, p->out_d + p->q0, p->out_c + p->q0);
+    return NULL;
+}
+
+void oracle_query_arrays_threads(const uint64_t *off, const uint32_t *hub, const uint32_t *dist,
+                                 const uint64_t *count, uint64_t q, const uint32_t *s,
+                                 const uint32_t *t, uint32_t *out_d, uint64_t *out_c,
+                                 uint32_t nthreads)
+{
+    if (nthreads <= 1 || q < 2) {
+        oracle_query_arrays(off, hub, dist, count, q, s, t, out_d, out_c);
+        return;
+    }
+    pthread_t *th = xmalloc(sizeof(pthread_t) * nthreads);
+    query_part *pt = xmalloc(sizeof(query_part) * nthreads);
+    for (uint32_t i = 0; i < nthreads; i++) {
+        query_part p = {off, hub, dist, count, s, t, out_d, out_c, q * i / nthreads,
+                        q * (i + 1) / nthreads};
+        pt[i] = p;
+        if (pthread_create(&th[i], NULL, query_part_run, &pt[i]) != 0) abort();
+    }
+    for (uint32_t i = 0; i < nthreads; i++) pthread_join(th[i], NULL);
+    free(th);
+    free(pt);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The hubs of one label, from the definition, without their counts: w is a */
+/* hub of L(s) iff w = s or some shortest s-w path has every vertex other   */
+/* than w ranked strictly below w (larger rank-space id).  One BFS from s   */
+/* gives, for every x, top(x) = the largest over the shortest s-x paths of  */
+/* the smallest id among the path's vertices other than x (top(s) = none);  */
+/* then w is a hub iff w = s or w < top(w).  Writes the hubs in increasing   */
+/* order with their distances; returns how many.  Arrays: room for n.       */
+/* ------------------------------------------------------------------------ */
+uint64_t oracle_label_hubs(uint32_t n, const uint64_t *off, const uint32_t *adj, uint32_t s,
+                           uint32_t *out_hub, uint32_t *out_dist)
+{
+    if (s >= n) return 0;
+    uint32_t *dist = xmalloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *top = xmalloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t *queue = xmalloc(sizeof(uint32_t) * (size_t)n);
+    for (uint32_t i = 0; i < n; i++) dist[i] = ORACLE_INF;
+    uint64_t head = 0, tail = 0;
+    dist[s] = 0;
+    top[s] = ORACLE_INF; /* the path s has no vertex other than s */
+    queue[tail++] = s;
+    while (head < tail) { /* level order: top(v) is final when v is popped */
+        uint32_t v = queue[head++];
+        uint32_t via = top[v] < v ? top[v] : v; /* smallest id on the path to v, v included */
+        for (uint64_t k = off[v]; k < off[v + 1]; k++) {
+            uint32_t x = adj[k];
+            if (dist[x] == ORACLE_INF) {
+                dist[x] = dist[v] + 1;
+                top[x] = via;
+                queue[tail++] = x;
+            } else if (dist[x] == dist[v] + 1 && via > top[x]) {
+                top[x] = via;
+            }
+        }
+    }
+    uint64_t k = 0;
+    for (uint32_t w = 0; w <= s; w++) {
+        if (dist[w] == ORACLE_INF) continue;
+        if (w == s || w < top[w]) {
+            out_hub[k] = w;
+            out_dist[k] = dist[w];
+            k++;
+        }
+    }
+    free(dist);
+    free(top);
+    free(queue);
+    return k;
 }

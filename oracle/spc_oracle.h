@@ -55,6 +55,10 @@ oracle_index *oracle_build_pruned(uint32_t n, const uint64_t *off,
                                   uint32_t max_hubs, double time_limit_s);
 oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t *adj,
                                 uint32_t depth_cap);
+/* oracle_build_pull with the pullers of each round spread over nthreads
+ * threads (0 or 1: the calling thread).  Same index and counters. */
+oracle_index *oracle_build_pull_threads(uint32_t n, const uint64_t *off, const uint32_t *adj,
+                                        uint32_t depth_cap, uint32_t nthreads);
 /* The definition builder with vertex weights weight[rank]: an entry's count
  * sums, over its trough shortest paths, the product of the weights of the
  * path's inner vertices (all weights 1: the plain index). */
@@ -75,6 +79,12 @@ void oracle_index_export(const oracle_index *ix, uint64_t *off, uint32_t *hub,
  * kept = entries inserted, scanned = probe entries scanned in hub order. */
 void oracle_index_round_stats(const oracle_index *ix, uint64_t *raw, uint64_t *merged,
                               uint64_t *kept, uint64_t *scanned);
+/* Byte-model inputs of a PULL build, rounds 0..rounds: active = pullers with
+ * at least one candidate passing the rank rule, active_adj = their adjacency
+ * slots, staged = label entries (distance < d) of the pullers with at least
+ * one merged candidate.  Zeros for other builders. */
+void oracle_index_model_stats(const oracle_index *ix, uint64_t *active, uint64_t *active_adj,
+                              uint64_t *staged);
 void oracle_index_free(oracle_index *ix);
 
 /* SPC query over an index (rank ids): minimum of d_s+d_t over common hubs and
@@ -89,5 +99,17 @@ void oracle_query_batch(const oracle_index *ix, uint64_t q, const uint32_t *s,
 void oracle_query_arrays(const uint64_t *off, const uint32_t *hub, const uint32_t *dist,
                          const uint64_t *count, uint64_t q, const uint32_t *s,
                          const uint32_t *t, uint32_t *out_d, uint64_t *out_c);
+
+/* oracle_query_arrays with the queries split over nthreads threads. */
+void oracle_query_arrays_threads(const uint64_t *off, const uint32_t *hub, const uint32_t *dist,
+                                 const uint64_t *count, uint64_t q, const uint32_t *s,
+                                 const uint32_t *t, uint32_t *out_d, uint64_t *out_c,
+                                 uint32_t nthreads);
+
+/* Hubs of L(s) and their distances from the definition (no counts), by one
+ * BFS from s (rank-space graph); increasing hub order; returns how many.
+ * out_hub, out_dist need room for n entries. */
+uint64_t oracle_label_hubs(uint32_t n, const uint64_t *off, const uint32_t *adj, uint32_t s,
+                           uint32_t *out_hub, uint32_t *out_dist);
 
 #endif

@@ -13,6 +13,7 @@ generators stand in for them with the shapes the workloads name.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -59,10 +60,11 @@ def csr_from_edges(n: int, e: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
         a, b = key // n, key % n
     else:
         a = b = np.zeros(0, dtype=np.int64)
-    src = np.concatenate([a, b])
-    dst = np.concatenate([b, a])
-    order = np.lexsort((dst, src))
-    src, dst = src[order], dst[order]
+    # both directions, ordered by (source, target): one sort of the packed
+    # pair (n * n < 2^63 for every n < 2^31)
+    both = np.concatenate([a * np.int64(n) + b, b * np.int64(n) + a])
+    both.sort()
+    src, dst = (both // n, both % n) if both.size else (both, both)
     counts = np.bincount(src, minlength=n).astype(np.uint64)
     off = np.zeros(n + 1, dtype=np.uint64)
     np.cumsum(counts, out=off[1:])
@@ -163,19 +165,48 @@ def chung_lu(n: int, seed: int, exponent: float = 2.1, wmin: float = 2.0,
 
 def rmat(scale: int, edge_factor: int, seed, a=0.57, b=0.19, c=0.19) -> Graph:
     """R-MAT: edge_factor * 2^scale sampled edges, no noise; symmetrised,
-    deduplicated, loops dropped; all 2^scale vertices kept."""
-    rng = np.random.default_rng(seed)
+    deduplicated, loops dropped; all 2^scale vertices kept.
+
+    Edge i takes, at recursion level L, the uniform number at position
+    L * k + i of the stream of ``default_rng(seed)`` (k sampled edges): the
+    levels are drawn one after another, each as one block of k numbers.
+    Large graphs draw their blocks in parallel, each worker jumping the
+    PCG64 stream to its slice (one 64-bit output per double), so the graph
+    is the same as with one sequential stream."""
     n = 1 << scale
     k = edge_factor * n
     src = np.zeros(k, dtype=np.int64)
     dst = np.zeros(k, dtype=np.int64)
-    for level in range(scale):
-        r = rng.random(k)
-        bit = np.int64(1) << np.int64(scale - 1 - level)
-        right = ((r >= a) & (r < a + b)) | (r >= a + b + c)
-        down = r >= a + b
-        src += down.astype(np.int64) * bit
-        dst += right.astype(np.int64) * bit
+
+    def fill(i0, i1, rng_at):
+        s, d = src[i0:i1], dst[i0:i1]
+        for level in range(scale):
+            r = rng_at(level * k + i0).random(i1 - i0)
+            bit = np.int64(1) << np.int64(scale - 1 - level)
+            down = r >= a + b
+            right = ((r >= a) & (r < a + b)) | (r >= a + b + c)
+            np.add(s, bit, out=s, where=down)
+            np.add(d, bit, out=d, where=right)
+
+    base = np.random.default_rng(seed).bit_generator
+    if k < (1 << 20):
+        rng = np.random.Generator(base)
+        fill(0, k, lambda pos: rng)  # sequential: the stream is at pos already
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+
+        state = base.state
+
+        def rng_at(pos):
+            bg = np.random.PCG64()
+            bg.state = state
+            bg.advance(pos)
+            return np.random.Generator(bg)
+
+        workers = max(1, min(16, os.cpu_count() or 1))
+        chunk = -(-k // (4 * workers))
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(lambda i0: fill(i0, min(k, i0 + chunk), rng_at), range(0, k, chunk)))
     return from_edges(n, np.stack([src, dst], axis=1),
                       name=f"rmat_s{scale}_ef{edge_factor}", scale=scale)
 
