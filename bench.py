@@ -1,16 +1,21 @@
 """Benchmark: SPC label index build + batched SPC queries on one MI355X.
 
-One step = the whole hot path over one synthetic graph: vertex ordering,
-the distance rounds, the count array (the index build), then one batch of
-uniform random SPC queries against the built index.  Inputs (CSR and query
-pairs) are resident in HBM before the timed region starts.
+Default line (the largest single-GPU workload): R-MAT scale 21 (2,097,152
+vertices, edge factor 16, a,b,c,d = 0.57,0.19,0.19,0.05, seed 5), degree
+order.  The index is built once, timed (host clock around the build call,
+CSR resident in HBM); then each step is one batch of 10M uniform SPC queries
+on the resident index (HIP events around the launch); then the served
+level at 1.0x saturation (Poisson arrivals, batch sizes log-uniform in
+1..65536) gives p50/p99 latency beside a one-request-at-a-time FIFO.
+`value` is label entries built per second; `queries_per_s` and p50/p99 sit
+beside it.  A side object repeats the Chung-Lu n = 2^20 build (where the
+oracle's byte model of the build exists) with its own roofline.
 
-Workload: Chung-Lu graph, n = 2^20, expected degrees from a power law with
-exponent 2.1 clipped to [2, 20000], mean degree exactly 10, seed 2; degree
-order (ties by id); 10M uniform query pairs.
+Other workloads (--workload): chunglu (the Chung-Lu line on its own),
+rmat_batch (512 R-MAT graphs, batched vs plain), rmat_served (offered-load
+sweep), grid (k x k grid, round cap or ordering variants).
 
-Prints one JSON line.  `value` is label entries built per second of build
-time; `queries_per_s` is the query batch rate; ms_per_step covers both.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,6 +33,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "label entries built/sec + SPC queries/sec (bit-exact); p50/p99 query latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_round_chunglu_n2e20_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def source_hash() -> str:
@@ -379,26 +385,394 @@ def reduced_side(kind, off_d, adj_d, s_d, t_d, dev, stream, cfg, ref_d, ref_c, l
     return out
 
 
+def _profile_json(name):
+    """A committed summary under profiles/ (None if absent)."""
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
+        return None
+    try:
+        return json.load(open(path))
+    except Exception:
+        return None
+
+
+def _roofline(kernel, bytes_total, ms_total, launches, model, traffic=None, **extra):
+    """Roofline object of one kernel: algorithmic bytes per launch over the
+    average launch duration (HIP events on the kernel's stream)."""
+    avg_ms = ms_total / max(launches, 1)
+    per_launch = bytes_total / max(launches, 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "launches": launches, "avg_launch_ms": avg_ms, "alg_bytes_per_launch": per_launch,
+            "bytes_model": model, **extra}
+
+
+def _s8d_round_kernel_bytes(prof, rounds_from=2):
+    """The oracle's byte model summed over the rounds the round kernel runs
+    (round 1 of a simple graph takes the sort path, not the round kernel)."""
+    return sum(r["total"] for r in prof["rounds"] if r["round"] >= rounds_from)
+
+
+def cpu_baselines(g_main, log, threads_sample_scale=17):
+    """The oracle on the host cores, same run: (1) the threaded PULL build
+    (all host threads) of R-MAT scale `threads_sample_scale`, edge factor
+    16, seed 5 (the main workload's generator at a size the oracle finishes
+    in seconds), and its threaded merge-join over 1M uniform queries; (2) the
+    sequential pruned BFS on the main workload's graph itself for 10 s."""
+    import oracle
+    from paper_2212_00977_amd import inputs
+
+    threads = oracle.host_threads()
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    gs = inputs.rmat(threads_sample_scale, 16, seed=5)
+    t0 = time.perf_counter()
+    L = oracle.build_graph(gs, method="pull", threads=threads)
+    bt = time.perf_counter() - t0
+    s, t = inputs.queries(gs.n, 1_000_000, seed=2)
+    rk = L.rank_of()
+    rs, rt = rk[s], rk[t]
+    t0 = time.perf_counter()
+    oracle.query_arrays(L.off, L.hub, L.dist, L.count, rs, rt, threads=threads)
+    qt = time.perf_counter() - t0
+    log(f"cpu oracle: threaded PULL {L.entries} entries in {bt:.1f} s, 1M queries in {qt:.2f} s "
+        f"({threads} threads)")
+    one = cpu_baseline(g_main, 10.0)
+    return {"value": L.entries / bt, "unit": "label entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"the oracle's threaded PULL build on {threads} host threads of R-MAT scale "
+                      f"{threads_sample_scale}, edge factor 16, seed 5 (the workload's generator at "
+                      f"1/{1 << (21 - threads_sample_scale)} of its vertices; {L.entries} entries, "
+                      f"{bt:.1f} s): the full index of the workload is beyond the oracle",
+            "queries_per_s": 1_000_000 / qt,
+            "query_sample": f"the oracle's merge-join on {threads} threads, 1M uniform pairs over "
+                            f"that index ({qt:.2f} s)",
+            "single_core": one, "nproc": os.cpu_count(), "cpu_model": model}
+
+
+def bench_rmat21(args, dev, log):
+    """The default line: R-MAT scale 21, edge factor 16, seed 5.  One timed
+    build; K steps of one 10M-query batch each on the resident index; the
+    served level at 1.0x saturation against FIFO; the Chung-Lu build as a
+    side object; the oracle on the host cores."""
+    import numpy as np
+    import torch
+
+    from paper_2212_00977_amd import inputs, serve, spc
+
+    scale = 21 - args.scale_down
+    log(f"generating R-MAT scale {scale}")
+    g = inputs.rmat(scale, 16, seed=5)
+    off_d = torch.from_numpy(g.off.view(np.int64)).to(dev)
+    adj_d = torch.from_numpy(g.adj.view(np.int32)).to(dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    st = ix.stats()
+    rs = {k: v.tolist() for k, v in {**ix.round_stats(), **ix.round_profile()}.items()}
+    log(f"build {build_ms:.0f} ms, {st['entries']} entries, {st['rounds']} rounds, "
+        f"{st['round_kernel_launches']} round-kernel launches, "
+        f"peak {st['peak_build_bytes'] / 2**30:.1f} GiB")
+    for r in range(len(rs["kept"])):
+        log("round %d: raw %d merged %d kept %d  %.1f ms" % (r, rs["raw"][r], rs["merged"][r], rs["kept"][r],
+                                                             rs["kernel_ms"][r]))
+    del off_d, adj_d
+    spc.release_cached_memory()
+    torch.cuda.empty_cache()
+    nq = args.queries
+    ts, tt = inputs.queries(g.n, 1_000_000, seed=3)
+    qcfg = ix.tune_queries(ts, tt, stream=stream)
+    log(f"query autotuner: configuration {qcfg} {spc.query_configs()[qcfg]}")
+    s_np, t_np = inputs.queries(g.n, nq, seed=2)
+    s_d = torch.from_numpy(s_np.view(np.int32)).to(dev)
+    t_d = torch.from_numpy(t_np.view(np.int32)).to(dev)
+    dist_o = torch.empty(nq, dtype=torch.uint8 if ix.dist_bits == 8 else torch.int16, device=dev)
+    cnt_o = torch.empty(nq, dtype=torch.int64, device=dev)
+    flg_o = torch.empty(nq, dtype=torch.uint8, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    qms = []
+    for i in range(args.warmup + args.steps):
+        ev0.record(stream)
+        ix.query(s_d, t_d, stream=stream, out=(dist_o, cnt_o, flg_o))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            qms.append(ev0.elapsed_time(ev1))
+    query_ms = float(np.mean(qms))
+    log(f"{args.steps} query steps: {query_ms:.1f} ms per 10M-query batch")
+
+    # served: saturation (a burst), then Poisson arrivals at 1.0x of it
+    mean_batch = 65536 / np.log(65537) - 0.5
+    srv_kw = dict(io_budget_bytes=1 << 30, streams=4, max_batch=1 << 18)
+    burst = serve.requests_from(inputs.poisson_requests(g.n, 1e9, args.serve_requests, seed=6))
+    for r in burst:
+        r.arrival = 0.0
+    srv = serve.Server(ix, **srv_kw)
+    srv.run(burst[:20])  # warm the streams and pinned host buffers
+    serve.fifo_baseline(ix, burst[:20])
+    sat = srv.run(burst).summary()
+    rate = sat["queries_per_s"] / mean_batch
+    reqs = serve.requests_from(inputs.poisson_requests(g.n, rate, args.serve_requests, seed=107))
+    served = srv.run(reqs).summary()
+    fifo = serve.fifo_baseline(ix, reqs).summary()
+    log(f"served 1.0x: {served['queries_per_s']:.3g} q/s p50 {served['p50_ms']:.2f} ms p99 "
+        f"{served['p99_ms']:.2f} ms | fifo p50 {fifo['p50_ms']:.2f} p99 {fifo['p99_ms']:.2f}")
+    ix.free()
+    spc.release_cached_memory()
+
+    # rooflines: the round kernel (the build's dominant kernel) and the query kernel
+    rk = _roofline("k_round", st["alg_bytes_round_kernel"], st["ms_round_kernel"],
+                   st["round_kernel_launches"],
+                   "kernel-counted: pulled entries (12 B), staged label entries, landmark-row "
+                   "slices needed, probe entries up to the first proving one, label offsets, "
+                   "survivors written; the oracle cannot rebuild this index, so the byte model "
+                   "from the definitions is reported for the same kernel on the Chung-Lu side line")
+    qb = _profile_json("oracle_bytes_k_query_rmat21.json")
+    q_roof = None
+    if qb and qb.get("n") == g.n and qb.get("m") == g.m:
+        q_roof = _roofline("k_query", qb["mean_bytes"] * nq, query_ms, 1,
+                           "oracle: (|L(s)|+|L(t)|)(4+delta) + 16 k* + 8 + (delta+8+1) per query, "
+                           f"mean over {qb['queries']} sampled pairs of the query stream "
+                           f"(standard error {qb['stderr_bytes']:.0f} B)",
+                           bytes_per_query=qb["mean_bytes"])
+    out = {
+        "metric": METRIC,
+        "value": st["entries"] / (build_ms * 1e-3),
+        "unit": "label entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": query_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {scale}, edge factor 16, a,b,c,d = 0.57,0.19,0.19,0.05, "
+                               f"seed 5, degree order: one index build (value), then steps of {nq} "
+                               "uniform SPC queries on the resident index, then Poisson requests "
+                               "at 1.0x saturation (p50/p99)",
+                   "step": f"one batch of {nq} uniform queries on the resident index "
+                           "(the build is timed once, before the steps)",
+                   "n": g.n, "m": g.m, "entries": st["entries"], "rounds": st["rounds"],
+                   "max_dist": st["max_dist"], "queries": nq, "parallelism": "single-gpu"},
+        "build_ms": build_ms,
+        "build_entries_per_s": st["entries"] / (build_ms * 1e-3),
+        "queries_per_s": nq / (query_ms * 1e-3),
+        "query_ms": query_ms,
+        "p50_ms": served["p50_ms"],
+        "p99_ms": served["p99_ms"],
+        "served_1x": {"queries_per_s": served["queries_per_s"], "p50_ms": served["p50_ms"],
+                      "p99_ms": served["p99_ms"], "requests": served["requests"],
+                      "deferred": served["deferred"], "launches": served["launches"],
+                      "offered_queries_per_s": sat["queries_per_s"],
+                      "fifo_queries_per_s": fifo["queries_per_s"], "fifo_p50_ms": fifo["p50_ms"],
+                      "fifo_p99_ms": fifo["p99_ms"], "saturation_queries_per_s": sat["queries_per_s"]},
+        "query_config": dict(zip(("stage", "tiles"), spc.query_configs()[qcfg])),
+        "build_breakdown_ms": {"order": st["ms_order"], "rounds": st["ms_rounds"],
+                               "finalize": st["ms_finalize"], "device_total": st["ms_total"],
+                               "round_kernel": st["ms_round_kernel"]},
+        "round_kernel_launches": st["round_kernel_launches"],
+        "rounds": {k: rs[k] for k in ("raw", "merged", "kept", "kernel_ms")},
+        "roofline": rk,
+        "query_roofline": q_roof,
+        "index_bytes": st["index_bytes"],
+        "peak_build_bytes": st["peak_build_bytes"],
+    }
+    if not args.no_side:
+        log("side line: Chung-Lu n=2^20")
+        out["chunglu"] = bench_chunglu(args, dev, log, steps=2, warmup=1, side=True)
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baselines(g, log)
+    if args.scale_down:
+        out["note"] = "scaled-down smoke run, not the benchmark workload"
+    print(json.dumps(out), flush=True)
+
+
+def bench_chunglu(args, dev, log, steps, warmup, side=False):
+    """Chung-Lu n = 2^20 (power law 2.1 clipped to [2, 20000], mean degree
+    10, seed 2), degree order: each step builds the index and answers 10M
+    uniform queries.  Returns the JSON object (its roofline uses the oracle's
+    byte model of the build when profiles/ holds it)."""
+    import numpy as np
+    import torch
+
+    from paper_2212_00977_amd import inputs, spc
+
+    log("generating Chung-Lu graph")
+    g = inputs.workload("chunglu", scale_down=args.scale_down)
+    nq = args.queries
+    s_np, t_np = inputs.queries(g.n, nq, seed=2)
+    off_d = torch.from_numpy(g.off.view(np.int64)).to(dev)
+    adj_d = torch.from_numpy(g.adj.view(np.int32)).to(dev)
+    s_d = torch.from_numpy(s_np.view(np.int32)).to(dev)
+    t_d = torch.from_numpy(t_np.view(np.int32)).to(dev)
+    dist_o = torch.empty(nq, dtype=torch.uint8, device=dev)
+    cnt_o = torch.empty(nq, dtype=torch.int64, device=dev)
+    flg_o = torch.empty(nq, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts_np, tt_np = inputs.queries(g.n, min(nq, 1_000_000), seed=3)
+    torch.cuda.synchronize()
+    qcfg = [None]
+    bopts = spc.BuildOptions(propagation=args.propagation)
+
+    def step(keep=False):
+        t0 = time.perf_counter()
+        ix = spc.build_index(off_d, adj_d, device=dev, stream=stream, opts=bopts)
+        t1 = time.perf_counter()
+        ix.set_query_config(qcfg[0])
+        if ix.dist_bits != 8:
+            raise RuntimeError("Chung-Lu index with 16-bit outputs: outputs sized for 8 bits")
+        ev0.record(stream)
+        ix.query(s_d, t_d, stream=stream, out=(dist_o, cnt_o, flg_o))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st = ix.stats()
+        st["_rounds"] = {k: v.tolist() for k, v in {**ix.round_stats(), **ix.round_profile()}.items()}
+        if not keep:
+            ix.free()
+            ix = None
+        return dict(build_ms=(t1 - t0) * 1e3, query_ms=ev0.elapsed_time(ev1),
+                    step_ms=(t2 - t0) * 1e3, stats=st, index=ix)
+
+    # query autotuner, before any timed work: one build, every launch
+    # configuration timed on a separate sample
+    ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
+    qcfg[0] = ix.tune_queries(ts_np, tt_np, stream=stream)
+    ix.free()
+    log(f"query autotuner: configuration {qcfg[0]} {spc.query_configs()[qcfg[0]]}")
+    for i in range(warmup):
+        r = step()
+        log(f"warmup {i}: build {r['build_ms']:.1f} ms, query {r['query_ms']:.1f} ms, "
+            f"entries {r['stats']['entries']}")
+    torch.cuda.synchronize()
+    runs = []
+    tt0 = time.perf_counter()
+    for i in range(steps):
+        r = step(keep=(i == steps - 1))
+        runs.append(r)
+        log(f"step {i}: build {r['build_ms']:.1f} ms, query {r['query_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - tt0) * 1e3
+
+    st = runs[-1]["stats"]
+    rs = st["_rounds"]
+    for r in range(len(rs["kept"])):
+        log("round %d: raw %d merged %d kept %d tail %d staged %d rowB %d hdr %d  %.1f ms" % (
+            r, rs["raw"][r], rs["merged"][r], rs["kept"][r], rs["scanned"][r], rs["staged"][r],
+            rs["row_bytes"][r], rs["headers"][r], rs["kernel_ms"][r]))
+    entries = st["entries"]
+    build_ms = float(np.mean([r["build_ms"] for r in runs]))
+    query_ms = float(np.mean([r["query_ms"] for r in runs]))
+    rk_ms = float(np.mean([r["stats"]["ms_round_kernel"] for r in runs]))
+    launches = st["round_kernel_launches"]
+    traffic = measured_traffic(launches)
+    kc = _roofline("k_round", st["alg_bytes_round_kernel"], rk_ms, launches,
+                   "kernel-counted (the kernel's own count of what it must read and write)",
+                   traffic=traffic)
+    prof = _profile_json("oracle_bytes_k_round_chunglu_n2e20.json")
+    roof = kc
+    build_roof = None
+    if prof and prof.get("n") == g.n and prof.get("m") == g.m and prof.get("entries") == entries:
+        b_rk = _s8d_round_kernel_bytes(prof)
+        roof = _roofline("k_round", b_rk, rk_ms, launches,
+                         "oracle byte model (B_csr + B_expand + B_stage + B_probe + B_write of "
+                         "rounds 2.., from the oracle's threaded PULL build)",
+                         traffic=traffic, frac_kernel_counted=kc["frac"],
+                         achieved_kernel_counted=kc["achieved"])
+        build_roof = {"bytes": prof["total"], "build_ms": build_ms,
+                      "achieved": prof["total"] / (build_ms * 1e-3) / 1e9,
+                      "frac": prof["total"] / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "bytes_model": "oracle byte model of the whole build (all rounds + finalize)"}
+    qb = _profile_json("oracle_bytes_k_query_chunglu_n2e20.json")
+    q_roof = None
+    if qb and qb.get("n") == g.n and qb.get("m") == g.m:
+        q_roof = _roofline("k_query", qb["mean_bytes"] * nq, query_ms, 1,
+                           f"oracle: B_q, mean over {qb['queries']} sampled pairs of the query stream",
+                           bytes_per_query=qb["mean_bytes"])
+    out = {
+        "metric": METRIC,
+        "value": entries / (build_ms * 1e-3),
+        "unit": "label entries/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": total_ms / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"chung-lu n=2^{20 - args.scale_down} exp 2.1 clip [2,20000] "
+                               f"mean deg 10 seed 2, degree order, {args.propagation} propagation, "
+                               f"{nq} uniform queries",
+                   "n": g.n, "m": g.m, "entries": entries, "rounds": st["rounds"],
+                   "max_dist": st["max_dist"], "queries": nq, "parallelism": "single-gpu"},
+        "build_ms": build_ms,
+        "query_ms": query_ms,
+        "query_config": dict(zip(("stage", "tiles"), spc.query_configs()[qcfg[0]])),
+        "queries_per_s": nq / (query_ms * 1e-3),
+        "build_breakdown_ms": {"order": st["ms_order"], "rounds": st["ms_rounds"],
+                               "finalize": st["ms_finalize"], "device_total": st["ms_total"],
+                               "round_kernel": rk_ms},
+        "roofline": roof,
+        "roofline_kernel_counted": kc,
+        "build_roofline": build_roof,
+        "query_roofline": q_roof,
+        "index_bytes": st["index_bytes"],
+        "peak_build_bytes": st["peak_build_bytes"],
+    }
+    last_ix = runs[-1]["index"]
+    if not side and not args.no_reductions:
+        for kind in ("one_shell", "equivalence"):
+            out[kind] = reduced_side(kind, off_d, adj_d, s_d, t_d, dev, stream, qcfg[0], dist_o, cnt_o, log)
+    if not side and (args.serve_seconds > 0 or args.serve_sweep):
+        out["serve"] = serve_runs(last_ix, g.n, args, out["queries_per_s"], log)
+    last_ix.free()
+    if not side and not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+    if side:
+        for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+            out.pop(k)
+    del off_d, adj_d, s_d, t_d, dist_o, cnt_o, flg_o
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--queries", type=int, default=10_000_000)
     ap.add_argument("--scale-down", type=int, default=0,
                     help="shrink n by 2^k (smoke runs only; not the benchmark workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side", action="store_true", help="default line: skip the Chung-Lu side line")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
-                    help="length of the served-load run on the last index (0 = skip)")
+                    help="chunglu: length of the served-load run on the last index (0 = skip)")
     ap.add_argument("--serve-sweep", action="store_true",
-                    help="after the steps, sweep the offered load (0.25..1.25 x saturation) "
+                    help="chunglu: after the steps, sweep the offered load (0.25..1.25 x saturation) "
                          "and print one JSON line per level")
-    ap.add_argument("--workload", default="chunglu", choices=["chunglu", "rmat_batch", "rmat_served", "grid"],
-                    help="chunglu: the benchmark line; rmat_batch: 512 R-MAT graphs built as one "
-                         "batch vs one build per graph; rmat_served: offered-load sweep on a "
-                         "resident R-MAT scale-21 index; grid: k x k grid with a round "
-                         "cap (separate JSON lines)")
+    ap.add_argument("--workload", default="rmat21",
+                    choices=["rmat21", "chunglu", "rmat_batch", "rmat_served", "grid"],
+                    help="rmat21: the benchmark line; chunglu: the Chung-Lu build line alone; "
+                         "rmat_batch: 512 R-MAT graphs built as one batch vs one build per graph; "
+                         "rmat_served: offered-load sweep on a resident R-MAT scale-21 index; "
+                         "grid: k x k grid with a round cap (separate JSON lines)")
     ap.add_argument("--grid-k", type=int, default=2048, help="grid side (grid workload)")
     ap.add_argument("--round-cap", type=int, default=64,
                     help="round cap D for the grid workload (0 = complete index)")
@@ -409,8 +783,8 @@ def main():
     ap.add_argument("--serve-max-batch", type=int, default=1 << 18,
                     help="queries per coalesced launch (rmat_served)")
     ap.add_argument("--serve-streams", type=int, default=4, help="streams of the server (rmat_served)")
-    ap.add_argument("--serve-requests", type=int, default=10000,
-                    help="requests per offered-load level (rmat_served)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per offered-load level (rmat21, rmat_served)")
     ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--no-reductions", action="store_true",
                     help="skip the side measurements of the reduced builds")
@@ -430,10 +804,7 @@ def main():
                                    "sharding of the build is a design note, not built"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    from paper_2212_00977_amd import inputs, spc
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -454,126 +825,13 @@ def main():
         return bench_served(args, dev, log)
     if args.workload == "grid":
         return bench_grid(args, dev, log)
-
-    log("generating graph")
-    g = inputs.workload("chunglu", scale_down=args.scale_down)
-    s_np, t_np = inputs.queries(g.n, args.queries, seed=2)
-    off_d = torch.from_numpy(g.off.view(np.int64)).to(dev)
-    adj_d = torch.from_numpy(g.adj.view(np.int32)).to(dev)
-    s_d = torch.from_numpy(s_np.view(np.int32)).to(dev)
-    t_d = torch.from_numpy(t_np.view(np.int32)).to(dev)
-    dist_o = torch.empty(args.queries, dtype=torch.uint8, device=dev)
-    cnt_o = torch.empty(args.queries, dtype=torch.int64, device=dev)
-    flg_o = torch.empty(args.queries, dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # a separate sample for the query autotuner (untimed)
-    ts_np, tt_np = inputs.queries(g.n, min(args.queries, 1_000_000), seed=3)
-    torch.cuda.synchronize()
-    qcfg = [None]
-
-    bopts = spc.BuildOptions(propagation=args.propagation)
-
-    def step(keep=False):
-        t0 = time.perf_counter()
-        ix = spc.build_index(off_d, adj_d, device=dev, stream=stream, opts=bopts)
-        t1 = time.perf_counter()
-        ix.set_query_config(qcfg[0])
-        ev0.record(stream)
-        ix.query(s_d, t_d, stream=stream, out=(dist_o, cnt_o, flg_o))
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        st = ix.stats()
-        st["_rounds"] = {k: v.tolist() for k, v in {**ix.round_stats(), **ix.round_profile()}.items()}
-        st["_launches"] = ix.round_kernel_launches()
-        if not keep:
-            ix.free()
-            ix = None
-        return dict(build_ms=(t1 - t0) * 1e3, query_ms=ev0.elapsed_time(ev1),
-                    step_ms=(t2 - t0) * 1e3, stats=st, index=ix)
-
-    # query autotuner, before any timed work: one build, every launch
-    # configuration timed on a separate sample
-    ix = spc.build_index(off_d, adj_d, device=dev, stream=stream)
-    qcfg[0] = ix.tune_queries(ts_np, tt_np, stream=stream)
-    ix.free()
-    log(f"query autotuner: configuration {qcfg[0]} {spc.query_configs()[qcfg[0]]}")
-    for i in range(args.warmup):
-        r = step()
-        log(f"warmup {i}: build {r['build_ms']:.1f} ms, query {r['query_ms']:.1f} ms, "
-            f"entries {r['stats']['entries']}")
-    torch.cuda.synchronize()
-    runs = []
-    tt0 = time.perf_counter()
-    for i in range(args.steps):
-        r = step(keep=(i == args.steps - 1))
-        runs.append(r)
-        log(f"step {i}: build {r['build_ms']:.1f} ms, query {r['query_ms']:.1f} ms")
-    torch.cuda.synchronize()
-    total_ms = (time.perf_counter() - tt0) * 1e3
-
-    st = runs[-1]["stats"]
-    rs = st["_rounds"]
-    for r in range(len(rs["kept"])):
-        log("round %d: raw %d merged %d kept %d tail %d staged %d rowB %d hdr %d  %.1f ms" % (
-            r, rs["raw"][r], rs["merged"][r], rs["kept"][r], rs["scanned"][r], rs["staged"][r],
-            rs["row_bytes"][r], rs["headers"][r], rs["kernel_ms"][r]))
-    entries = st["entries"]
-    build_ms = float(np.mean([r["build_ms"] for r in runs]))
-    query_ms = float(np.mean([r["query_ms"] for r in runs]))
-    rk_ms = float(np.mean([r["stats"]["ms_round_kernel"] for r in runs]))
-    alg = st["alg_bytes_round_kernel"]
-    achieved = alg / (rk_ms * 1e-3) / 1e9 if rk_ms > 0 else 0.0
-    launches = st["_launches"]
-    traffic = measured_traffic(launches)
-    out = {
-        "metric": METRIC,
-        "value": entries / (build_ms * 1e-3),
-        "unit": "label entries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": total_ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": f"chung-lu n=2^{20 - args.scale_down} exp 2.1 clip [2,20000] "
-                               f"mean deg 10 seed 2, degree order, {args.propagation} propagation, "
-                               f"{args.queries} uniform queries",
-                   "n": g.n, "m": g.m, "entries": entries, "rounds": st["rounds"],
-                   "max_dist": st["max_dist"], "queries": args.queries,
-                   "parallelism": "single-gpu"},
-        "build_ms": build_ms,
-        "query_ms": query_ms,
-        "query_config": dict(zip(("stage", "tiles"), spc.query_configs()[qcfg[0]])),
-        "queries_per_s": args.queries / (query_ms * 1e-3),
-        "build_breakdown_ms": {"order": st["ms_order"], "rounds": st["ms_rounds"],
-                               "finalize": st["ms_finalize"], "device_total": st["ms_total"],
-                               "round_kernel": rk_ms},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_round", "launches_per_build": launches,
-                     "avg_launch_ms": rk_ms / max(launches, 1),
-                     "alg_bytes_per_launch": alg / max(launches, 1)},
-        "index_bytes": st["index_bytes"],
-        "peak_build_bytes": st["peak_build_bytes"],
-    }
-    last_ix = runs[-1]["index"]
-    if not args.no_reductions:
-        for kind in ("one_shell", "equivalence"):
-            out[kind] = reduced_side(kind, off_d, adj_d, s_d, t_d, dev, stream, qcfg[0], dist_o, cnt_o, log)
-    if args.serve_seconds > 0 or args.serve_sweep:
-        out["serve"] = serve_runs(last_ix, g.n, args, out["queries_per_s"], log)
-    last_ix.free()
-    if args.scale_down:
-        out["note"] = "scaled-down smoke run, not the benchmark workload"
-    if not args.no_cpu_baseline:
-        log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    if args.workload == "chunglu":
+        out = bench_chunglu(args, dev, log, args.steps, args.warmup)
+        if args.scale_down:
+            out["note"] = "scaled-down smoke run, not the benchmark workload"
+        print(json.dumps(out), flush=True)
+        return
+    return bench_rmat21(args, dev, log)
 
 
 if __name__ == "__main__":

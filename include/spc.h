@@ -84,6 +84,23 @@ typedef struct {
     const uint32_t *order;
     const uint64_t *tie_key; /* [n] or NULL */
     int32_t on_device;
+    /* Nonzero: a directed graph (Section "2-Hop Labeling for Shortest Path
+     * Counting").  row_off/col then hold each arc a -> b once, in row a
+     * (nnz = arcs); no self loops or repeated arcs (checked when
+     * opts.validate is set).  The index holds an out-label and an in-label
+     * per vertex: L_out(v) = {(w, sd(v,w), c)} and L_in(v) = {(w, sd(w,v), c)}
+     * for hubs w ranked at or above v that reach v (or are reached) along a
+     * shortest path on which every other vertex ranks below w, c counting
+     * those paths; spc_query_batch answers SPC(s, t) for paths from s to t
+     * by Eq. (con:spc1)-(con:spc2) over L_out(s) and L_in(t).  Without an
+     * explicit order, vertices rank by total degree (out + in) descending,
+     * ties by tie_key, then id (the paper fixes no directed order).  One
+     * graph per build (spc_build_index_batch: SPC_ERR_UNSUPPORTED), no
+     * reduction (SPC_ERR_INVALID_ARG), and every round pulls whatever
+     * propagation asks.  Exports (spc_graph_entries, spc_export_labels) cover
+     * 2n label rows: rank r's out-label, then at n + r its in-label; the
+     * order export has n entries. */
+    int32_t directed;
 } spc_graph;
 
 typedef struct {
@@ -153,6 +170,8 @@ typedef struct {
     uint32_t fringe_depth;           /* largest fringe depth */
     uint32_t twin_vertices;          /* vertices merged into a representative by
                                         SPC_REDUCE_EQUIVALENCE (0 otherwise) */
+    uint32_t directed;               /* 1 for an index of a directed graph (entries
+                                        count both label sets) */
 } spc_stats;
 
 /* Build the index of one graph (Alg. 2 rounds until a round adds no entry).
@@ -193,6 +212,37 @@ spc_status spc_build_index_batch(const spc_graph *gs, uint32_t k, const spc_buil
 spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
                            const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
                            uint8_t *flags_out, void *stream);
+
+/* SPC queries over several graphs of an index in one call ("Query
+ * Evaluation in Parallel": queries are independent, so they can be grouped
+ * freely).  Query i asks SPC(s[i], t[i]) on graph graph_ids[i] (device
+ * uint32[nq]; NULL: every query on graph 0); answers, flags and output
+ * widths as spc_query_batch (an id past the index's graphs, or a vertex id
+ * past its graph, gives SPC_FLAG_INVALID).  The queries are first grouped by
+ * their work, |L(s)| + |L(t)|: short ones are answered by 16 lanes each
+ * (four per wave), the others by a wave each with the index's query
+ * configuration, so graphs with short labels do not leave most of a wave
+ * idle.  Scratch: 4 bytes per query (at most 2^24 at a time) taken from the
+ * device's stream-ordered allocator on `stream` and given back on it.
+ * Asynchronous on `stream`; nq == 0 is a no-op; SPC_ERR_INVALID_ARG for a
+ * NULL index or a NULL s, t, dist_out or count_out with nq > 0. */
+spc_status spc_query_batch_multi(const spc_index *ix, const uint32_t *graph_ids, const uint32_t *s,
+                                 const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                                 uint8_t *flags_out, void *stream);
+
+/* Bucketing of spc_query_batch_multi: queries with |L(s)| + |L(t)| at most
+ * `small` take the 16-lanes-per-query path; 0 turns bucketing off (every
+ * query a wave).  A new index starts at 256.  The tuner times the
+ * thresholds 0, 64, 128, ..., 2048 on the sample queries (device pointers;
+ * graph_ids may be NULL), twice each with events on `stream`, checks that
+ * every threshold's answers equal those of 0 (SPC_ERR_DEVICE if not), keeps
+ * the fastest and returns it in *small_out (may be NULL).  The tuner
+ * allocates scratch, synchronises `stream`, and must not run concurrently
+ * with queries on the same index; so must not spc_set_query_buckets.
+ * SPC_ERR_INVALID_ARG for a NULL index (or NULL samples, nq == 0). */
+spc_status spc_tune_query_buckets(spc_index *ix, const uint32_t *graph_ids, const uint32_t *s,
+                                  const uint32_t *t, uint64_t nq, void *stream, uint32_t *small_out);
+spc_status spc_set_query_buckets(spc_index *ix, uint32_t small);
 
 /* Release the index (waits for the device to finish work that may still
  * read it).  Its device blocks go to the library's per-device block cache,

@@ -65,11 +65,15 @@ def lib():
         f.restype = vp
     L.oracle_build_pull_threads.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, C.c_uint32]
     L.oracle_build_pull_threads.restype = vp
+    L.oracle_set_progress.argtypes = [C.c_int]
+    L.oracle_set_progress.restype = None
     L.oracle_index_model_stats.argtypes = [vp, _u64p, _u64p, _u64p]
     L.oracle_index_model_stats.restype = None
     L.oracle_query_arrays_threads.argtypes = [_u64p, _u32p, _u32p, _u64p, C.c_uint64, _u32p,
                                               _u32p, _u32p, _u64p, C.c_uint32]
     L.oracle_query_arrays_threads.restype = None
+    L.oracle_build_directed_definition.argtypes = [C.c_uint32, _u64p, _u32p, _u64p, _u32p]
+    L.oracle_build_directed_definition.restype = vp
     L.oracle_label_hubs.argtypes = [C.c_uint32, _u64p, _u32p, C.c_uint32, _u32p, _u32p]
     L.oracle_label_hubs.restype = C.c_uint64
     L.oracle_build_definition_weighted.argtypes = [C.c_uint32, _u64p, _u32p, _u64p, C.c_uint32]
@@ -255,6 +259,27 @@ def build(off, adj, order=None, tie_key=None, method: str = "pruned", depth_cap:
     else:
         raise ValueError(method)
     return _collect(h, n, order, with_stats=(method == "pull"))
+
+
+def pull_stats(off, adj, order=None, tie_key=None, depth_cap: int = 0, threads: int = 1) -> dict:
+    """The threaded PULL build's per-round counters, entry count and rounds,
+    without exporting the labels (for graphs whose index is too large to
+    copy out once more)."""
+    n, roff, radj, order = _prep(off, adj, order, tie_key)
+    L = lib()
+    h = L.oracle_build_pull_threads(n, roff, radj, depth_cap, max(1, int(threads)))
+    try:
+        rounds = int(L.oracle_index_rounds(h))
+        k = rounds + 1
+        raw, mer, kept, scan, act, act_adj, staged = (np.zeros(k, dtype=np.uint64)
+                                                      for _ in range(7))
+        L.oracle_index_round_stats(h, raw, mer, kept, scan)
+        L.oracle_index_model_stats(h, act, act_adj, staged)
+        return dict(n=n, entries=int(L.oracle_index_entries(h)), rounds=rounds, raw=raw,
+                    merged=mer, kept=kept, scanned=scan, active=act, active_adj=act_adj,
+                    staged=staged)
+    finally:
+        L.oracle_index_free(h)
 
 
 def build_graph(g, method: str = "pruned", depth_cap: int = 0, **kw) -> Labels:
@@ -703,3 +728,37 @@ def directed_labels(n: int, arcs, order=None) -> DirectedLabels:
                 if dv == full[v]:
                     lab[v][w] = (dv, min(sig[v], SAT))
     return DirectedLabels(order, out, inn)
+
+
+def directed_order(n: int, off, adj) -> np.ndarray:
+    """Rank -> vertex of a digraph given by out-arcs (CSR): total degree
+    (out + in) descending, ties by id (the paper fixes no directed order)."""
+    off, adj = _u64(off), _u32(adj)
+    deg = np.diff(off).astype(np.int64) + np.bincount(adj.astype(np.int64), minlength=n)[:n]
+    return np.lexsort((np.arange(n), -deg)).astype(np.uint32)
+
+
+def build_directed(n: int, off, adj, order=None) -> Labels:
+    """Directed labels from the definition (C): a Labels of 2n rows in rank
+    space, row r = L_out of rank r, row n + r = L_in of rank r; `order` is
+    rank -> vertex (default directed_order)."""
+    off, adj = _u64(off), _u32(adj)
+    if order is None:
+        order = directed_order(n, off, adj)
+    order = _u32(order)
+    rank = np.zeros(n, dtype=np.uint32)
+    rank[order] = np.arange(n, dtype=np.uint32)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(off).astype(np.int64))
+    a, b = rank[src].astype(np.int64), rank[adj].astype(np.int64)
+
+    def csr(x, y):
+        o = np.lexsort((y, x))
+        cnt = np.bincount(x, minlength=n).astype(np.uint64)
+        ro = np.zeros(n + 1, dtype=np.uint64)
+        np.cumsum(cnt, out=ro[1:])
+        return ro, y[o].astype(np.uint32)
+
+    roff, radj = csr(a, b)
+    ioff, iadj = csr(b, a)
+    h = lib().oracle_build_directed_definition(n, roff, radj, ioff, iadj)
+    return _collect(h, 2 * n, order, with_stats=False)

@@ -34,6 +34,7 @@
 #include "spc_oracle.h"
 
 #include <pthread.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
@@ -244,6 +245,33 @@ static void label_push(olabel *l, uint32_t hub, uint32_t dist, uint64_t cnt)
     l->len++;
 }
 
+/* Merge k new entries (hub-sorted, all of distance d, hubs not in the label)
+ * into a hub-sorted label, keeping it hub-sorted. */
+static void label_merge_sorted(olabel *l, const uint32_t *hub, const uint64_t *cnt, uint64_t k,
+                               uint32_t d)
+{
+    if (k == 0) return;
+    uint64_t old = l->len;
+    for (uint64_t i = 0; i < k; i++) label_push(l, 0, 0, 0); /* room for k more */
+    /* from the back: the larger of the two tails goes last */
+    uint64_t a = old, b = k, o = old + k;
+    while (b > 0) {
+        if (a > 0 && l->hub[a - 1] > hub[b - 1]) {
+            a--;
+            o--;
+            l->hub[o] = l->hub[a];
+            l->dist[o] = l->dist[a];
+            l->cnt[o] = l->cnt[a];
+        } else {
+            b--;
+            o--;
+            l->hub[o] = hub[b];
+            l->dist[o] = d;
+            l->cnt[o] = cnt[b];
+        }
+    }
+}
+
 static void stats_round(oracle_index *ix, uint32_t d, uint64_t raw, uint64_t merged,
                         uint64_t kept, uint64_t scanned)
 {
@@ -405,6 +433,76 @@ oracle_index *oracle_build_definition_weighted(uint32_t n, const uint64_t *off, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Directed labels (Section "2-Hop Labeling for Shortest Path Counting": an */
+/* out-label and an in-label per vertex), from the definition.  Rank-space   */
+/* digraph given by its out-arcs (off, adj) and in-arcs (ioff, iadj).  The   */
+/* index has 2n rows: row v < n is L_out(v), row n + v is L_in(v).  For a    */
+/* hub w and v ranked at or below w: (w, sd(v,w), c) is in L_out(v) when a   */
+/* shortest v-to-w path has every vertex but w ranked below w (c counts     */
+/* those paths); (w, sd(w,v), c) is in L_in(v) likewise for w-to-v paths.   */
+/* Per hub, the v-to-w paths are a BFS from w over the reversed arcs (the    */
+/* in-arcs), the w-to-v paths a BFS over the out-arcs; each once over the   */
+/* whole digraph (true distances) and once over {w} and the vertices ranked */
+/* below w (trough distances and counts).                                   */
+/* ------------------------------------------------------------------------ */
+static void bfs_count_arcs(uint32_t n, const uint64_t *off, const uint32_t *adj, uint32_t src,
+                           int restricted, uint32_t *dist, uint64_t *sigma, uint32_t *queue)
+{
+    for (uint32_t i = 0; i < n; i++) {
+        dist[i] = ORACLE_INF;
+        sigma[i] = 0;
+    }
+    uint64_t head = 0, tail = 0;
+    dist[src] = 0;
+    sigma[src] = 1;
+    queue[tail++] = src;
+    while (head < tail) {
+        uint32_t v = queue[head++];
+        for (uint64_t k = off[v]; k < off[v + 1]; k++) {
+            uint32_t x = adj[k];
+            if (restricted && x <= src) continue;
+            if (dist[x] == ORACLE_INF) {
+                dist[x] = dist[v] + 1;
+                queue[tail++] = x;
+            }
+            if (dist[x] == dist[v] + 1) sigma[x] = sat_add(sigma[x], sigma[v]);
+        }
+    }
+}
+
+oracle_index *oracle_build_directed_definition(uint32_t n, const uint64_t *off, const uint32_t *adj,
+                                               const uint64_t *ioff, const uint32_t *iadj)
+{
+    oracle_index *ix = index_new(2 * n);
+    uint32_t *df = xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    uint32_t *dr = xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    uint64_t *sf = xmalloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    uint64_t *sr = xmalloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    uint32_t *queue = xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    for (uint32_t w = 0; w < n; w++) { /* hubs in rank order: labels come out hub-sorted */
+        for (int side = 0; side < 2; side++) {
+            /* side 0: L_out (paths v -> w: BFS from w over in-arcs);
+             * side 1: L_in (paths w -> v: BFS from w over out-arcs) */
+            const uint64_t *o = side ? off : ioff;
+            const uint32_t *a = side ? adj : iadj;
+            bfs_count_arcs(n, o, a, w, 0, df, sf, queue);
+            bfs_count_arcs(n, o, a, w, 1, dr, sr, queue);
+            for (uint32_t v = w; v < n; v++)
+                if (dr[v] != ORACLE_INF && dr[v] == df[v])
+                    label_push(&ix->lab[(size_t)side * n + v], w, dr[v], sr[v]);
+        }
+    }
+    free(df);
+    free(dr);
+    free(sf);
+    free(sr);
+    free(queue);
+    ix->hubs_done = n;
+    ix->rounds = last_round(ix, 0);
+    return ix;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sequential pruned BFS, hubs in rank order.  While hub r is processed,     */
 /* the labels hold only hubs ranked above r, so a vertex v met at depth D is */
 /* skipped when a common hub of L(v) and L(r) already gives a distance < D.  */
@@ -436,7 +534,7 @@ oracle_index *oracle_build_pruned(uint32_t n, const uint64_t *off, const uint32_
     double t0 = now_s();
     uint32_t r;
     for (r = 0; r < limit; r++) {
-        if (time_limit_s > 0 && (r & 63) == 0 && now_s() - t0 > time_limit_s) break;
+        if (time_limit_s > 0 && now_s() - t0 > time_limit_s) break;
         olabel *lr = &ix->lab[r];
         for (uint64_t i = 0; i < lr->len; i++) tdist[lr->hub[i]] = lr->dist[i];
         uint64_t head = 0, tail = 0;
@@ -586,25 +684,22 @@ static void pull_vertex(const oracle_index *ix, const uint64_t *off, const uint3
     qsort(sc->touched, ntouch, sizeof(uint32_t), cmp_u32);
     for (uint32_t j = 0; j < ntouch; j++) {
         uint32_t w = sc->touched[j];
-        /* Query(w, u, entries of distance < d).  The counter `scanned` is the
-         * number of entries a scan of L(w) in hub order reads up to and
-         * including the first hub that proves a shorter distance (all of L(w)
-         * when none does); L(w) is stored here in insertion order, so it
-         * counts the entries whose hub is at most the smallest proving hub. */
+        /* Query(w, u, entries of distance < d): a scan of L(w) in hub order
+         * (labels are kept hub-sorted) that stops at the first hub proving a
+         * shorter distance.  The counter `scanned` is the number of entries
+         * it reads, that hub included (all of L(w) when none proves one). */
         const olabel *lw = &ix->lab[w];
         int pruned = 0;
-        uint32_t hmin = ORACLE_INF;
         for (uint64_t i = 0; i < lw->len; i++) {
             uint32_t du = sc->udist[lw->hub[i]];
             if (lw->dist[i] >= d) continue; /* entries of round >= d are not read */
             if (du != ORACLE_INF && du + lw->dist[i] < d) {
                 pruned = 1;
-                if (lw->hub[i] < hmin) hmin = lw->hub[i];
+                ct->scanned += i + 1;
+                break;
             }
         }
-        if (pruned) {
-            for (uint64_t i = 0; i < lw->len; i++) ct->scanned += lw->hub[i] <= hmin;
-        } else {
+        if (!pruned) {
             ct->scanned += lw->len;
             pull_out_push(out, w, sc->acc[w]);
             ct->kept++;
@@ -666,8 +761,9 @@ static void *pull_worker_run(void *arg)
                     uint64_t k = r->cur_off[u] + i;
                     r->cur_hub[k] = src->hub[r->ustart[u] + i];
                     r->cur_cnt[k] = src->cnt[r->ustart[u] + i];
-                    label_push(&r->ix->lab[u], r->cur_hub[k], r->d, r->cur_cnt[k]);
                 }
+                label_merge_sorted(&r->ix->lab[u], r->cur_hub + r->cur_off[u], r->cur_cnt + r->cur_off[u],
+                                   r->ulen[u], r->d);
             }
         }
     }
@@ -689,6 +785,9 @@ static void pull_phase(pull_round *r, uint32_t nthreads, int phase)
     for (uint32_t i = 0; i < nthreads; i++) pthread_join(th[i], NULL);
     free(th);
 }
+
+static int g_progress = 0; /* nonzero: one line per PULL round on stderr */
+void oracle_set_progress(int on) { g_progress = on; }
 
 oracle_index *oracle_build_pull_threads(uint32_t n, const uint64_t *off, const uint32_t *adj,
                                         uint32_t depth_cap, uint32_t nthreads)
@@ -762,6 +861,12 @@ oracle_index *oracle_build_pull_threads(uint32_t n, const uint64_t *off, const u
         pull_phase(&r, nthreads, 2);
         stats_round(ix, d, ct.raw, ct.merged, ct.kept, ct.scanned);
         stats_model(ix, d, ct.active, ct.active_adj, ct.staged);
+        if (g_progress) {
+            fprintf(stderr, "oracle pull: round %u raw %llu merged %llu kept %llu\n", d,
+                    (unsigned long long)ct.raw, (unsigned long long)ct.merged,
+                    (unsigned long long)ct.kept);
+            fflush(stderr);
+        }
         free(prev_off);
         free(prev_hub);
         free(prev_cnt);

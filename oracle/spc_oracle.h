@@ -57,6 +57,8 @@ oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t 
                                 uint32_t depth_cap);
 /* oracle_build_pull with the pullers of each round spread over nthreads
  * threads (0 or 1: the calling thread).  Same index and counters. */
+/* Nonzero: the PULL builders print one line per round on stderr. */
+void oracle_set_progress(int on);
 oracle_index *oracle_build_pull_threads(uint32_t n, const uint64_t *off, const uint32_t *adj,
                                         uint32_t depth_cap, uint32_t nthreads);
 /* The definition builder with vertex weights weight[rank]: an entry's count
@@ -64,6 +66,13 @@ oracle_index *oracle_build_pull_threads(uint32_t n, const uint64_t *off, const u
  * path's inner vertices (all weights 1: the plain index). */
 oracle_index *oracle_build_definition_weighted(uint32_t n, const uint64_t *off, const uint32_t *adj,
                                                const uint64_t *weight, uint32_t depth_cap);
+
+/* Directed labels from the definition (rank-space digraph: out-arcs off/adj,
+ * in-arcs ioff/iadj, no self loops or repeated arcs).  The index has 2n rows:
+ * row v < n is L_out(v) = {(w, sd(v,w), c)}, row n + v is L_in(v) =
+ * {(w, sd(w,v), c)}, for hubs w ranked at or above v with a trough path. */
+oracle_index *oracle_build_directed_definition(uint32_t n, const uint64_t *off, const uint32_t *adj,
+                                               const uint64_t *ioff, const uint32_t *iadj);
 
 uint64_t oracle_index_entries(const oracle_index *ix);
 /* Last round run by a round-by-distance build: the first empty round

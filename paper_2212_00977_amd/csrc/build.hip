@@ -138,9 +138,9 @@ __global__ void k_keys_to_adj(const uint64_t *keys, uint64_t nnz, int xbits, uin
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nnz) radj[i] = (uint32_t)(keys[i] & ((1ull << xbits) - 1));
 }
-// simple + symmetric check on sorted rank-space adjacency
+// simple (+ symmetric unless `directed`) check on sorted rank-space adjacency
 __global__ __launch_bounds__(kBlock) void k_check_adj(const uint64_t *roff, const uint32_t *radj,
-                                                      uint32_t N, uint32_t *err) {
+                                                      uint32_t N, uint32_t *err, int directed) {
     uint32_t r = blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (r >= N) return;
     uint32_t lane = threadIdx.x & 63;
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const uint64_t *roff, cons
         uint32_t x = radj[k];
         if (x == r) atomicOr(err, 8u);                       // self loop
         if (k > s && radj[k - 1] == x) atomicOr(err, 16u);   // duplicate
+        if (directed) continue;
         uint64_t xs = roff[x];
         uint32_t xl = (uint32_t)(roff[x + 1] - xs);
         uint32_t p = lower_bound_u32(radj + xs, xl, r);
@@ -160,17 +161,18 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const uint64_t *roff, cons
 // Round 0: L_0(v) = {(v, 0, 1)}.
 // ---------------------------------------------------------------------------
 template <int DB>
-__global__ void k_round0(uint32_t N, uint32_t *pool_hub, uint64_t *pool_cnt, uint64_t *rstart,
+__global__ void k_round0(uint32_t N, uint32_t nreal, uint32_t *pool_hub, uint64_t *pool_cnt, uint64_t *rstart,
                          uint32_t *rlen, uint64_t *lab_off, typename Ent<DB>::T *lab_hd) {
     uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v > N) return;
     lab_off[v] = v;
     if (v == N) return;
-    pool_hub[v] = v;
+    const uint32_t h = (nreal && v >= nreal) ? v - nreal : v;  // a row's own vertex
+    pool_hub[v] = h;
     pool_cnt[v] = 1;
     rstart[v] = v;
     rlen[v] = 1;
-    lab_hd[v] = e_make<DB>(v, 0);
+    lab_hd[v] = e_make<DB>(h, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -179,19 +181,23 @@ __global__ void k_round0(uint32_t N, uint32_t *pool_hub, uint64_t *pool_cnt, uin
 // neighbour v is hub-sorted, so this is a prefix length; when v outranks u
 // every hub of that segment does too.  One wave per u.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_expand_count(uint32_t N, const uint64_t *goff,
+__global__ __launch_bounds__(kBlock) void k_expand_count(uint32_t N, uint32_t nreal, const uint64_t *goff,
                                                          const uint32_t *gadj, const uint64_t *pstart,
                                                          const uint32_t *plen,
                                                          const uint32_t *pool_hub, uint64_t *raw) {
     uint32_t u = blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (u >= N) return;
     uint32_t lane = threadIdx.x & 63;
+    // rows of a directed build: hubs are real vertices (row - nreal for
+    // in-label rows)
+    const uint32_t ur = (nreal && u >= nreal) ? u - nreal : u;
     uint64_t s = 0;
     for (uint64_t k = goff[u] + lane; k < goff[u + 1]; k += 64) {
         uint32_t v = gadj[k];
         uint32_t ln = plen[v];
         if (ln == 0) continue;
-        s += (v < u) ? ln : lower_bound_u32(pool_hub + pstart[v], ln, u);
+        const uint32_t vr = (nreal && v >= nreal) ? v - nreal : v;
+        s += (vr < ur) ? ln : lower_bound_u32(pool_hub + pstart[v], ln, ur);
     }
     s = wave_sum(s);
     if (lane == 0) raw[u] = s;
@@ -255,14 +261,15 @@ __device__ __forceinline__ uint32_t land_count_le(uint64_t x, uint32_t lim) {
 }
 
 template <int DB>
-__global__ void k_land_init(uint32_t N, const uint32_t *gbase, typename Land<DB>::T *land) {
+__global__ void k_land_init(uint32_t N, uint32_t nreal, const uint32_t *gbase, typename Land<DB>::T *land) {
     using LT = typename Land<DB>::T;
     const uint64_t n = (uint64_t)N * kLand;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t v = (uint32_t)(i / kLand), l = (uint32_t)(i % kLand);
         uint32_t base = gbase ? gbase[v] : 0;
-        land[i] = (v - base == l) ? (LT)0 : (LT)~(LT)0;
+        const uint32_t h = (nreal && v >= nreal) ? v - nreal : v;
+        land[i] = (h - base == l) ? (LT)0 : (LT)~(LT)0;
     }
 }
 __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
@@ -323,6 +330,9 @@ constexpr uint32_t kTailSteps = SPC_TAIL_STEPS;
 
 struct RoundArgs {
     uint32_t d, u_lo, u_hi;
+    // directed builds: rows [0, nreal) are out-labels, rows [nreal, 2 nreal)
+    // in-labels of the same vertices (0: undirected, row = vertex)
+    uint32_t nreal;
     const uint64_t *goff;
     const uint32_t *gadj;
     const uint64_t *lab_off;         // L_{<=d-1}: staged for u
@@ -340,6 +350,8 @@ struct RoundArgs {
     const uint32_t *adj_w;           // per adjacency slot: the neighbour's weight (W only)
     uint32_t *cur, *nxt;             // per adjacency slot: segment positions at lo / hi
     const uint64_t *raw_off;  // exclusive prefix of raw over all vertices
+    // survivors of puller u go to the temp buffer at its pull offset
+    // raw_off[u] - raw_off[u_lo] (it has at most raw_u of them)
     uint32_t *tmp_hub;
     uint64_t *tmp_cnt;
     uint32_t *surv;
@@ -444,7 +456,13 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     const uint32_t grp = lane >> 4, gl = lane & 15;  // 16-lane groups
     const uint32_t u = a.u_hi - 1 - blockIdx.x;
     const uint64_t raw_u = a.raw_off[u + 1] - a.raw_off[u];
-    if (raw_u == 0) {
+    // a row's hubs are real vertices ranked at or above the row's own
+    // vertex ur; a candidate hub w is probed against w's in-label for an
+    // out-label row, w's out-label for an in-label row, w itself otherwise
+    auto real = [&](uint32_t p) -> uint32_t { return (a.nreal && p >= a.nreal) ? p - a.nreal : p; };
+    const uint32_t ur = real(u);
+    const uint32_t poff = (a.nreal && u < a.nreal) ? a.nreal : 0;
+    if (raw_u == 0) {  // uniform over the workgroup
         if (tid == 0) a.surv[u] = 0;
         return;
     }
@@ -536,26 +554,26 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     }
     float ratio = 2.0f;      // pulls per distinct candidate
     bool may_widen = true;   // false from an overflow until a chunk completes
-    uint32_t lo = 0, width = u;
+    uint32_t lo = 0, width = ur;
     if (raw_u > (uint64_t)(2 * kTarget)) {
         uint64_t parts = (raw_u + 2 * kTarget - 1) / (2 * kTarget);
-        width = (uint32_t)(u / parts) > 0 ? (uint32_t)(u / parts) : 1;
+        width = (uint32_t)(ur / parts) > 0 ? (uint32_t)(ur / parts) : 1;
     }
 
     // 2-5, chunk by chunk
-    while (lo < u) {
+    while (lo < ur) {
         // A. size the chunk.  With cursors in registers the exact pull count
         //    of [lo, hi) is cheap: the range is narrowed or widened once so
         //    that the expected distinct count fits.  Wider pullers take the
         //    width learned from the previous chunk.
-        uint32_t hi = (width >= u - lo) ? u : lo + width, tot = 0;
+        uint32_t hi = (width >= ur - lo) ? ur : lo + width, tot = 0;
         if (one_group) {
             for (int it = 0;; it++) {
-                hi = (width >= u - lo) ? u : lo + width;
+                hi = (width >= ur - lo) ? ur : lo + width;
                 uint32_t t = 0;
                 if (tid < deg) {
                     // hubs of v's segment are <= v
-                    my_e = (my_v >= lo && my_c < my_ln) ? gallop_u32(a.pool_hub + my_ps, my_c, my_ln, hi)
+                    my_e = (real(my_v) >= lo && my_c < my_ln) ? gallop_u32(a.pool_hub + my_ps, my_c, my_ln, hi)
                                                         : my_c;
                     t = my_e - my_c;
                 }
@@ -567,11 +585,11 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                     width = w2 ? w2 : 1;
                     continue;
                 }
-                if (may_widen && expect < 0.5f * kTarget && hi < u) {
+                if (may_widen && expect < 0.5f * kTarget && hi < ur) {
                     float f = expect > 1.0f ? (float)kTarget / expect : 8.0f;
                     f = f > 8.0f ? 8.0f : f;
                     uint64_t w2 = (uint64_t)((double)(hi - lo) * f);
-                    width = w2 >= (uint64_t)(u - lo) ? u - lo : (uint32_t)w2;
+                    width = w2 >= (uint64_t)(ur - lo) ? ur - lo : (uint32_t)w2;
                     continue;
                 }
                 break;
@@ -615,7 +633,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                     const uint32_t ln = a.plen[v];
                     ps = ln ? a.pstart[v] : 0;
                     c = lo ? a.cur[g0 + nb] : 0;
-                    e = (v >= lo && c < ln) ? gallop_u32(a.pool_hub + ps, c, ln, hi) : c;
+                    e = (real(v) >= lo && c < ln) ? gallop_u32(a.pool_hub + ps, c, ln, hi) : c;
                     a.nxt[g0 + nb] = e;
                 }
                 sb = ps + c;
@@ -725,7 +743,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                 if (i < M) {
                     wl = lhub[i] - base;
                     if (slice_useful && 16 * gl <= wl) {  // landmarks above w are not its hubs
-                        const LW *rw = lands + (uint64_t)lhub[i] * (kLand / 4) + 4 * gl;
+                        const LW *rw = lands + (uint64_t)(lhub[i] + poff) * (kLand / 4) + 4 * gl;
 #pragma unroll
                         for (int q = 0; q < 4; q++) hit |= land_hit(uw[q], rw[q], d);
                         loads = 1;
@@ -793,9 +811,9 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                     if (got < T) {
                         i = tlist[got];
                         const uint32_t w = lhub[i];
-                        const uint64_t q0 = a.prev_off[w];
-                        np = a.prev_off[w + 1] - q0 - 1;  // the last entry is (w, 0)
-                        p0 = a.lc_prev[w];
+                        const uint64_t q0 = a.prev_off[w + poff];
+                        np = a.prev_off[w + poff + 1] - q0 - 1;  // the last entry is (w, 0)
+                        p0 = a.lc_prev[w + poff];
                         pw = static_cast<const E *>(a.prev_hd) + q0;
                         nw = np - p0;
                         const uint64_t cu = lower_bound_hub<DB>(pu, npu, w);
@@ -1035,9 +1053,10 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     }
 }
 
-// Move a batch's survivors from the temp buffer to the round pool, record
-// the round's segment of every vertex of the batch, and write the round's
-// landmark entries into the landmark rows.  One wave per vertex.
+// Move a batch's survivors from the temp buffer (each puller's at its pull
+// offset) to the round pool, record the round's segment of every vertex of
+// the batch, and write the round's landmark entries into the landmark rows.
+// One wave per vertex.
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_compact(uint32_t u_lo, uint32_t u_hi, uint32_t d,
                                                     const uint64_t *raw_off, const uint64_t *soff,
@@ -1114,9 +1133,10 @@ __global__ __launch_bounds__(kBlock) void k_merge(uint32_t N, uint32_t d, const 
     }
 }
 
-__global__ void k_lc_init(uint32_t N, const uint32_t *gbase, uint32_t *lc) {
+__global__ void k_lc_init(uint32_t N, uint32_t nreal, const uint32_t *gbase, uint32_t *lc) {
     uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < N) lc[v] = (v - (gbase ? gbase[v] : 0)) < (uint32_t)kLand ? 1u : 0u;
+    const uint32_t h = (nreal && v >= nreal) ? v - nreal : v;
+    if (v < N) lc[v] = (h - (gbase ? gbase[v] : 0)) < (uint32_t)kLand ? 1u : 0u;
 }
 
 // Widen packed entries from 8-bit to 16-bit distances.
@@ -1240,6 +1260,8 @@ struct Build {
     uint32_t N = 0;
     uint64_t NNZ = 0;
     uint32_t k = 1;
+    // directed build: N = 2 nreal rows, out-labels then in-labels
+    uint32_t nreal = 0;
     std::vector<uint32_t> vbase, gn;
     bool simple = false;  // the input was validated simple and symmetric
     uint32_t prop = 0;    // SPC_PROPAGATE_*
@@ -1466,7 +1488,7 @@ __global__ void k_adj_weights(const uint32_t *adj, uint64_t nnz, const uint32_t 
 
 // simple + symmetric check of a CSR; sorts each row of adj in place
 spc_status validate_csr(Build &B, const uint64_t *off, uint32_t *adj, uint32_t N, uint64_t NNZ,
-                        uint32_t *err) {
+                        uint32_t *err, bool directed = false) {
     if (!NNZ) return SPC_OK;
     int xb = std::max(1, bit_width(N));
     uint64_t *keys = nullptr, *keys2 = nullptr;
@@ -1482,7 +1504,8 @@ spc_status validate_csr(Build &B, const uint64_t *off, uint32_t *adj, uint32_t N
                        adj);
     SPC_LAUNCHED();
     SPC_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), B.st));
-    hipLaunchKernelGGL(k_check_adj, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, off, adj, N, err);
+    hipLaunchKernelGGL(k_check_adj, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, off, adj, N, err,
+                       directed ? 1 : 0);
     SPC_LAUNCHED();
     uint64_t ev[1];
     SPC_TRY(B.read_u64((const uint64_t *)err, ev));
@@ -1696,8 +1719,17 @@ spc_status preprocess(Build &B, const spc_graph *gs, bool use_order, bool use_ti
     return SPC_OK;
 }
 
-// largest temp buffer (entries) one batch of pullers may use
-constexpr uint64_t kTempMax = 1ull << 27;
+// Pulled entries per batch (temp buffer entries): at least kRawBatchMax,
+// at most kTempMaxEntries (the small-table test build takes tiny ones, so
+// small graphs run many batches per round).
+#ifndef SPC_TEMP_LOG2
+#define SPC_TEMP_LOG2 27
+#endif
+#ifndef SPC_TEMP_MAX_LOG2
+#define SPC_TEMP_MAX_LOG2 30
+#endif
+constexpr uint64_t kRawBatchMax = 1ull << SPC_TEMP_LOG2;
+constexpr uint64_t kTempMaxEntries = 1ull << SPC_TEMP_MAX_LOG2;
 // pullers per round-kernel launch (one workgroup each: the launch's
 // work-item count stays below 2^32)
 constexpr uint32_t kBatchVerts = 1u << 22;
@@ -1828,7 +1860,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     const uint32_t *plen = B.rlen[d - 1];
     using LT = typename Land<DB>::T;
     B.arena.begin_window();
-    hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, B.goff,
+    hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N, B.nreal, B.goff,
                        B.gadj, pstart, plen, B.rhub[d - 1], B.raw);
     SPC_LAUNCHED();
     SPC_TRY(scan_u64(B.raw, B.raw_off, N, B.ws, B.st));
@@ -1837,26 +1869,6 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     *any_cand = total_raw > 0;
     *kept_out = 0;
     if (total_raw == 0) return SPC_OK;
-
-    // batches of pullers whose temp space fits
-    std::vector<uint32_t> bounds{0};
-    if (total_raw <= kTempMax && N <= kBatchVerts) {
-        bounds.push_back(N);
-    } else {
-        std::vector<uint64_t> ro((size_t)N + 1);
-        SPC_HIP(hipMemcpyAsync(ro.data(), B.raw_off, ((size_t)N + 1) * sizeof(uint64_t),
-                               hipMemcpyDeviceToHost, B.st));
-        SPC_HIP(hipStreamSynchronize(B.st));
-        uint32_t b0 = 0;
-        while (b0 < N) {
-            uint64_t lim = ro[b0] + kTempMax;
-            uint32_t b1 = (uint32_t)(std::upper_bound(ro.begin() + b0 + 1, ro.end(), lim) - ro.begin()) - 1;
-            if (b1 <= b0) b1 = b0 + 1;
-            if (b1 - b0 > kBatchVerts) b1 = b0 + kBatchVerts;
-            bounds.push_back(b1);
-            b0 = b1;
-        }
-    }
 
     uint64_t *rs = nullptr;
     uint32_t *rl = nullptr;
@@ -1875,6 +1887,47 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     // the graph is symmetric)
     const bool push = d >= 2 && B.simple &&
                       (B.prop == SPC_PROPAGATE_PUSH || (B.prop == SPC_PROPAGATE_AUTO && total_raw < B.NNZ));
+    // Batches of pullers whose pulled entries fit the temp buffer (a
+    // puller's survivors are a subset of its pulls, written at its pull
+    // offset).  The buffer takes up to a sixth of the memory the build has
+    // left (2^27 .. 2^30 entries): the more pullers a launch holds, the
+    // better the dispatcher balances their very uneven work.  PUSH rounds
+    // keep 2^27 (their scratch per pulled entry is larger).
+    uint64_t tmp_want = kRawBatchMax;
+    if (!push) {
+        const uint64_t cap_bytes = B.arena.budget() ? B.arena.budget() : B.dev_bytes;
+        const uint64_t left = cap_bytes > B.arena.used() ? cap_bytes - B.arena.used() : 0;
+        tmp_want = std::min<uint64_t>(std::max<uint64_t>(left / 6 / 12, kRawBatchMax), kTempMaxEntries);
+    }
+    tmp_want = std::min<uint64_t>(tmp_want, std::max<uint64_t>(total_raw, 1024));
+    if (tmp_want > B.tmp_cap) {
+        B.arena.release(B.tmp_hub);
+        B.arena.release(B.tmp_cnt);
+        B.tmp_cap = 0;
+        SPC_TRY(B.arena.alloc(&B.tmp_hub, tmp_want));
+        SPC_TRY(B.arena.alloc(&B.tmp_cnt, tmp_want));
+        B.tmp_cap = tmp_want;
+    }
+    std::vector<uint32_t> bounds{0};
+    if (total_raw <= B.tmp_cap && N <= kBatchVerts) {
+        bounds.push_back(N);
+    } else {
+        std::vector<uint64_t> ro((size_t)N + 1);
+        SPC_HIP(hipMemcpyAsync(ro.data(), B.raw_off, ((size_t)N + 1) * sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, B.st));
+        SPC_HIP(hipStreamSynchronize(B.st));
+        uint32_t b0 = 0;
+        while (b0 < N) {
+            uint64_t lim = ro[b0] + B.tmp_cap;
+            uint32_t b1 = (uint32_t)(std::upper_bound(ro.begin() + b0 + 1, ro.end(), lim) - ro.begin()) - 1;
+            if (b1 <= b0) b1 = b0 + 1;  // one puller pulling more than the buffer: a buffer of its own
+            if (b1 - b0 > kBatchVerts) b1 = b0 + kBatchVerts;
+            bounds.push_back(b1);
+            b0 = b1;
+        }
+    }
+    uint64_t raw_lo = 0;  // pull offset of the current batch's first puller
+
     if (push && !B.vgoff) {
         SPC_TRY(B.arena.alloc(&B.vgoff, (uint64_t)N + 1));
         SPC_TRY(B.arena.alloc(&B.vgadj, (uint64_t)N + 1));
@@ -1885,23 +1938,17 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         SPC_LAUNCHED();
     }
     for (size_t bi = 0; bi + 1 < bounds.size(); bi++) {
-        uint32_t b0 = bounds[bi], b1 = bounds[bi + 1];
-        uint64_t r2[2];
-        SPC_HIP(hipMemcpyAsync(B.h_pin, B.raw_off + b0, sizeof(uint64_t), hipMemcpyDeviceToHost, B.st));
-        SPC_HIP(hipMemcpyAsync(B.h_pin + 1, B.raw_off + b1, sizeof(uint64_t), hipMemcpyDeviceToHost,
-                               B.st));
-        SPC_HIP(hipStreamSynchronize(B.st));
-        r2[0] = B.h_pin[0];
-        r2[1] = B.h_pin[1];
-        uint64_t need = r2[1] - r2[0];
-        if (need > B.tmp_cap) {
+        const uint32_t b0 = bounds[bi], b1 = bounds[bi + 1];
+        uint64_t need;  // pulled entries of the batch
+        SPC_TRY(B.read_u64(B.raw_off + b1, &need));
+        need -= raw_lo;
+        if (need > B.tmp_cap) {  // a single puller pulling more than the buffer holds
             B.arena.release(B.tmp_hub);
             B.arena.release(B.tmp_cnt);
             B.tmp_cap = 0;
-            uint64_t cap = std::max<uint64_t>(need, 1024);
-            SPC_TRY(B.arena.alloc(&B.tmp_hub, cap));
-            SPC_TRY(B.arena.alloc(&B.tmp_cnt, cap));
-            B.tmp_cap = cap;
+            SPC_TRY(B.arena.alloc(&B.tmp_hub, need));
+            SPC_TRY(B.arena.alloc(&B.tmp_cnt, need));
+            B.tmp_cap = need;
         }
         // PUSH: scatter, sort by (puller, hub), merge equal hubs
         uint64_t *pkeys = nullptr, *pkeys2 = nullptr, *pcnt = nullptr, *phpos = nullptr, *pws = nullptr,
@@ -1948,6 +1995,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.d = d;
         ra.u_lo = b0;
         ra.u_hi = b1;
+        ra.nreal = B.nreal;
         ra.goff = B.goff;
         ra.gadj = B.gadj;
         ra.lab_off = B.lab_off;
@@ -2024,7 +2072,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         }
         SPC_TRY(scan_u32(B.surv + b0, B.soff, b1 - b0, B.ws, B.st));
         uint64_t sb;
-        SPC_TRY(B.read_u64(B.soff + (b1 - b0), &sb));
+        SPC_TRY(B.read_u64(B.soff + (b1 - b0), &sb));  // synchronises: both events are done
         float ms = 0;
         SPC_HIP(hipEventElapsedTime(&ms, B.ev_a, B.ev_b));
         if (!fast1) B.ms_round_kernel += ms;  // the fused round kernel only
@@ -2035,9 +2083,8 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
             // maps what is needed
             uint64_t want = B.rused[d] + sb;
             if (!B.vhub[d]) {
-                if (bi == 0 && bounds.size() > 2 && r2[1] > r2[0])
-                    want = std::max<uint64_t>(want,
-                                              (uint64_t)((double)sb * total_raw / (r2[1] - r2[0]) * 1.1));
+                if (bi == 0 && bounds.size() > 2 && need)
+                    want = std::max<uint64_t>(want, (uint64_t)((double)sb * total_raw / need * 1.1));
                 else if (bi > 0)
                     want = std::max<uint64_t>(want, B.rcap[d] + B.rcap[d] / 2);
             }
@@ -2050,6 +2097,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         SPC_LAUNCHED();
         B.rused[d] += sb;
         kept += sb;
+        raw_lo += need;
     }
     if (B.rcap[d] > B.rused[d] + B.rused[d] / 8 + (1u << 20)) SPC_TRY(B.shrink_round(d));
     uint64_t c[8];
@@ -2136,7 +2184,7 @@ spc_status rounds_loop(Build &B, uint32_t &d, uint32_t cap, bool auto_width, boo
             // truncated iff round cap+1 would still pull candidates
             const uint32_t N = B.N;
             hipLaunchKernelGGL(k_expand_count, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N,
-                               B.goff, B.gadj, B.rstart[d - 1], B.rlen[d - 1], B.rhub[d - 1], B.raw);
+                               B.nreal, B.goff, B.gadj, B.rstart[d - 1], B.rlen[d - 1], B.rhub[d - 1], B.raw);
             SPC_LAUNCHED();
             SPC_TRY(scan_u64(B.raw, B.raw_off, N, B.ws, B.st));
             uint64_t tr;
@@ -2247,6 +2295,232 @@ inline float elapsed(hipEvent_t a, hipEvent_t b) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Directed input (Section "2-Hop Labeling for Shortest Path Counting": an
+// out-label and an in-label per vertex).  The build labels 2n rows: row r is
+// the out-label of rank r, row n + r its in-label.  Row r pulls from the
+// out-labels of the heads of r's out-arcs (a path r -> x -> ... -> w), row
+// n + r from the in-labels of the tails of r's in-arcs (w -> ... -> y -> r),
+// so the rows' adjacency is the rank-space out-arcs for the first half and
+// the in-arcs, shifted by n, for the second.  A row's hubs are real vertices
+// ranked at or above its own, and a candidate of an out-label row is pruned
+// through the candidate's in-label (and vice versa): the round kernel's
+// `nreal`.
+// ---------------------------------------------------------------------------
+__global__ void k_in_degree(const uint32_t *col, uint64_t nnz, uint32_t *indeg) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&indeg[col[i]], 1u);
+}
+// total degree (out + in), and its maximum
+__global__ void k_total_degree(const uint64_t *off, const uint32_t *indeg, uint32_t n, uint32_t *deg,
+                               uint32_t *maxdeg) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const uint32_t dv = (uint32_t)(off[v + 1] - off[v]) + indeg[v];
+    deg[v] = dv;
+    atomicMax(maxdeg, dv);
+}
+// row lengths of the pseudo-graph: out-degree of rank r, then in-degree
+__global__ void k_dir_rowdeg(const uint32_t *order, const uint64_t *off, const uint32_t *indeg, uint32_t n,
+                             uint32_t *pdeg) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t v = order[r];
+    pdeg[r] = (uint32_t)(off[v + 1] - off[v]);
+    pdeg[n + r] = indeg[v];
+}
+// in-arc keys (rank of head << xb | rank of tail), one wave per tail
+__global__ __launch_bounds__(kBlock) void k_arc_keys(const uint64_t *off, const uint32_t *col,
+                                                     const uint32_t *rank_of, uint32_t n, int xb,
+                                                     uint64_t *keys) {
+    const uint32_t v = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (v >= n) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t rv = rank_of[v];
+    for (uint64_t k = off[v] + lane; k < off[v + 1]; k += 64)
+        keys[k] = ((uint64_t)rank_of[col[k]] << xb) | rv;
+}
+// sorted in-arc keys -> the in-label rows' neighbours (n + rank of tail)
+__global__ void k_dir_in_rows(const uint64_t *keys, uint64_t nnz, int xb, uint32_t n, uint32_t *gadj_in) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        gadj_in[i] = n + (uint32_t)(keys[i] & ((1ull << xb) - 1));
+}
+
+spc_status preprocess_directed(Build &B, const spc_graph &G, bool use_order, bool use_tie, bool validate) {
+    B.simple = false;  // no symmetric shortcuts (round 1 sort, PUSH)
+    const uint32_t n = B.nreal;
+    const uint64_t A = G.nnz;  // arcs
+    uint64_t *off = nullptr;
+    uint32_t *col = nullptr, *deg = nullptr, *indeg = nullptr, *err = nullptr, *ord = nullptr, *hits = nullptr;
+    uint64_t *tie = nullptr;
+    SPC_TRY(B.arena.alloc(&off, (uint64_t)n + 1));
+    SPC_TRY(B.arena.alloc(&col, std::max<uint64_t>(A, 1)));
+    SPC_TRY(B.arena.alloc(&deg, (uint64_t)n + 1));
+    SPC_TRY(B.arena.alloc(&indeg, (uint64_t)n + 1));
+    SPC_TRY(B.arena.alloc(&err, 2));
+    SPC_HIP(hipMemsetAsync(err, 0, 2 * sizeof(uint32_t), B.st));
+    SPC_HIP(hipMemsetAsync(indeg, 0, ((uint64_t)n + 1) * sizeof(uint32_t), B.st));
+    // inputs on the device (host inputs are staged)
+    const uint64_t *src_off = G.row_off;
+    const uint32_t *src_col = G.col, *src_ord = G.order;
+    const uint64_t *src_tie = G.tie_key;
+    uint64_t *st_off = nullptr, *st_tie = nullptr;
+    uint32_t *st_col = nullptr, *st_ord = nullptr;
+    if (!G.on_device) {
+        SPC_TRY(B.arena.alloc(&st_off, (uint64_t)n + 1));
+        SPC_TRY(B.arena.alloc(&st_col, std::max<uint64_t>(A, 1)));
+        SPC_HIP(hipMemcpyAsync(st_off, G.row_off, ((uint64_t)n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice,
+                               B.st));
+        if (A) SPC_HIP(hipMemcpyAsync(st_col, G.col, A * sizeof(uint32_t), hipMemcpyHostToDevice, B.st));
+        if (use_order) {
+            SPC_TRY(B.arena.alloc(&st_ord, (uint64_t)n + 1));
+            SPC_HIP(hipMemcpyAsync(st_ord, G.order, (uint64_t)n * sizeof(uint32_t), hipMemcpyHostToDevice, B.st));
+        }
+        if (use_tie) {
+            SPC_TRY(B.arena.alloc(&st_tie, (uint64_t)n + 1));
+            SPC_HIP(hipMemcpyAsync(st_tie, G.tie_key, (uint64_t)n * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                   B.st));
+        }
+        src_off = st_off;
+        src_col = st_col;
+        src_ord = st_ord;
+        src_tie = st_tie;
+    }
+    hipLaunchKernelGGL(k_union_off, dim3(grid_for((uint64_t)n + 1, kBlock)), dim3(kBlock), 0, B.st, src_off, off,
+                       n, A, (uint64_t)0, err);
+    SPC_LAUNCHED();
+    if (A) {
+        hipLaunchKernelGGL(k_union_col, dim3(grid_for(A, kBlock)), dim3(kBlock), 0, B.st, src_col, col, A, n, 0u,
+                           err);
+        SPC_LAUNCHED();
+    }
+    if (use_order) {
+        SPC_TRY(B.arena.alloc(&ord, (uint64_t)n + 1));
+        SPC_TRY(B.arena.alloc(&hits, (uint64_t)n + 1));
+        SPC_HIP(hipMemsetAsync(hits, 0, ((uint64_t)n + 1) * sizeof(uint32_t), B.st));
+        hipLaunchKernelGGL(k_union_order, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st, src_ord, ord, n, 0u,
+                           hits, err);
+        SPC_LAUNCHED();
+        hipLaunchKernelGGL(k_check_perm, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st, hits, n, err);
+        SPC_LAUNCHED();
+    }
+    if (use_tie) {
+        SPC_TRY(B.arena.alloc(&tie, (uint64_t)n + 1));
+        SPC_HIP(hipMemcpyAsync(tie, src_tie, (uint64_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, B.st));
+    }
+    uint64_t e2[1];
+    SPC_TRY(B.read_u64((const uint64_t *)err, e2));  // also ends the staging copies
+    if ((uint32_t)e2[0] != 0) return SPC_ERR_INVALID_ARG;
+    B.arena.release(st_off);
+    B.arena.release(st_col);
+    B.arena.release(st_ord);
+    B.arena.release(st_tie);
+    if (validate) {  // no self loops, no repeated arcs (sorts each row)
+        SPC_TRY(validate_csr(B, off, col, n, A, err, true));
+    }
+    // total degrees and the order
+    if (A) {
+        hipLaunchKernelGGL(k_in_degree, dim3(grid_stride(A)), dim3(kBlock), 0, B.st, col, A, indeg);
+        SPC_LAUNCHED();
+    }
+    uint32_t *maxdeg = err + 1;
+    SPC_HIP(hipMemsetAsync(maxdeg, 0, sizeof(uint32_t), B.st));
+    hipLaunchKernelGGL(k_total_degree, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st, off, indeg, n, deg,
+                       maxdeg);
+    SPC_LAUNCHED();
+    SPC_TRY(B.arena.alloc(&B.order, (uint64_t)n + 1));
+    SPC_TRY(B.arena.alloc(&B.rank_of, (uint64_t)n + 1));
+    if (use_order) {
+        SPC_HIP(hipMemcpyAsync(B.order, ord, (uint64_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, B.st));
+    } else {
+        uint64_t md[1];
+        SPC_TRY(B.read_u64((const uint64_t *)err, md));
+        const uint32_t maxd = (uint32_t)(md[0] >> 32);
+        uint64_t *keys = nullptr, *keys2 = nullptr;
+        uint32_t *vals2 = nullptr;
+        SPC_TRY(B.arena.alloc(&keys, (uint64_t)n + 1));
+        SPC_TRY(B.arena.alloc(&keys2, (uint64_t)n + 1));
+        SPC_TRY(B.arena.alloc(&vals2, (uint64_t)n + 1));
+        hipLaunchKernelGGL(k_iota_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st, (const uint64_t *)tie, n,
+                           keys, B.order);
+        SPC_LAUNCHED();
+        if (use_tie) SPC_TRY(radix_sort_pairs(keys, B.order, keys2, vals2, n, 64, B.ws, B.st));
+        const int degbits = std::max(1, bit_width(maxd));
+        hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st, B.order, deg, n, maxd,
+                           degbits, (const uint32_t *)nullptr, 1u, keys);
+        SPC_LAUNCHED();
+        SPC_TRY(radix_sort_pairs(keys, B.order, keys2, vals2, n, degbits, B.ws, B.st));
+        B.arena.release(keys);
+        B.arena.release(keys2);
+        B.arena.release(vals2);
+    }
+    B.arena.release(ord);
+    B.arena.release(hits);
+    B.arena.release(tie);
+    // the pseudo-graph in rank space
+    uint32_t *pdeg = nullptr, *rdeg = nullptr;
+    SPC_TRY(B.arena.alloc(&pdeg, 2 * (uint64_t)n + 1));
+    SPC_TRY(B.arena.alloc(&rdeg, (uint64_t)n + 1));
+    hipLaunchKernelGGL(k_rank_of, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st, B.order, n, deg, B.rank_of,
+                       rdeg);
+    SPC_LAUNCHED();
+    hipLaunchKernelGGL(k_dir_rowdeg, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, B.st, B.order, off, indeg, n,
+                       pdeg);
+    SPC_LAUNCHED();
+    SPC_TRY(B.arena.alloc(&B.goff, 2 * (uint64_t)n + 1));
+    SPC_TRY(B.arena.alloc(&B.gadj, std::max<uint64_t>(2 * A, 1)));
+    SPC_TRY(scan_u32(pdeg, B.goff, 2 * n, B.ws, B.st));
+    // out rows: the heads of each rank's out-arcs, in rank space
+    hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, kWaves)), dim3(kBlock), 0, B.st, B.order, B.rank_of, off, col,
+                       B.goff, B.gadj, n);
+    SPC_LAUNCHED();
+    // in rows: arcs sorted by (head rank, tail rank); row n + r gets r's tails
+    if (A) {
+        const int xb = std::max(1, bit_width(n));
+        uint64_t *keys = nullptr, *keys2 = nullptr, *rws = nullptr;
+        SPC_TRY(B.arena.alloc(&keys, A));
+        SPC_TRY(B.arena.alloc(&keys2, A));
+        SPC_TRY(B.arena.alloc(&rws, radix_ws_elems(A)));
+        hipLaunchKernelGGL(k_arc_keys, dim3(grid_for(n, kWaves)), dim3(kBlock), 0, B.st, off, col, B.rank_of, n, xb,
+                           keys);
+        SPC_LAUNCHED();
+        SPC_TRY(radix_sort_pairs(keys, nullptr, keys2, nullptr, A, 2 * xb, rws, B.st));
+        hipLaunchKernelGGL(k_dir_in_rows, dim3(grid_stride(A)), dim3(kBlock), 0, B.st, keys, A, xb, n, B.gadj + A);
+        SPC_LAUNCHED();
+        SPC_HIP(hipStreamSynchronize(B.st));
+        B.arena.release(keys);
+        B.arena.release(keys2);
+        B.arena.release(rws);
+    }
+    for (uint32_t *p : {pdeg, rdeg, col, deg, indeg, err}) B.arena.release(p);
+    B.arena.release(off);
+    return SPC_OK;
+}
+
+// Per graph (vbase, gn, obase, on) on the device, for queries that name
+// their graph one by one; owned by the index.
+spc_status attach_graph_table(Build &B, spc_index *ix) {
+    const size_t k = ix->gn.size();
+    std::vector<uint32_t> h(4 * std::max<size_t>(k, 1), 0);
+    for (size_t g = 0; g < k; g++) {
+        h[4 * g] = ix->vbase[g];
+        h[4 * g + 1] = ix->gn[g];
+        h[4 * g + 2] = ix->reduced ? ix->obase[g] : ix->vbase[g];
+        h[4 * g + 3] = ix->reduced ? ix->on[g] : ix->gn[g];
+    }
+    uint32_t *d = nullptr;
+    SPC_TRY(B.arena.alloc(&d, (uint64_t)h.size()));
+    SPC_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(uint32_t), hipMemcpyHostToDevice, B.st));
+    SPC_HIP(hipStreamSynchronize(B.st));
+    const uint64_t b = B.arena.detach(d);
+    ix->blocks.emplace_back(d, (size_t)b);
+    ix->index_bytes += b;
+    ix->g_tab = d;
+    return SPC_OK;
+}
+
 spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, hipStream_t st,
                       spc_index **out) {
     if (!gs || !o || !out || k == 0) return SPC_ERR_INVALID_ARG;
@@ -2255,12 +2529,18 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         return SPC_ERR_INVALID_ARG;
     if (o->propagation > SPC_PROPAGATE_AUTO || o->reserved != 0) return SPC_ERR_INVALID_ARG;
     if (o->dist_bits != 0 && o->dist_bits != 8 && o->dist_bits != 16) return SPC_ERR_INVALID_ARG;
+    // a directed graph is built alone and unreduced: 2n label rows
+    const bool directed = gs[0].directed != 0;
+    for (uint32_t g = 0; g < k; g++)
+        if ((gs[g].directed != 0) != directed) return SPC_ERR_INVALID_ARG;
+    if (directed && k > 1) return SPC_ERR_UNSUPPORTED;
+    if (directed && o->reduce != 0) return SPC_ERR_INVALID_ARG;
     uint64_t N64 = 0, NNZ = 0;
     uint32_t n_order = 0, n_tie = 0, n_dev = 0;
     for (uint32_t g = 0; g < k; g++) {
         const spc_graph &G = gs[g];
         if (!G.row_off || (G.nnz && !G.col)) return SPC_ERR_INVALID_ARG;
-        if (G.nnz & 1) return SPC_ERR_INVALID_ARG;  // symmetric: every edge twice
+        if (!directed && (G.nnz & 1)) return SPC_ERR_INVALID_ARG;  // symmetric: every edge twice
         N64 += G.n;
         NNZ += G.nnz;
         n_order += G.order != nullptr;
@@ -2271,7 +2551,8 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         return SPC_ERR_INVALID_ARG;
     // one wave per vertex in several kernels, one work-item per adjacency
     // slot in others: a launch's work-item count must stay below 2^32
-    if (N64 > kMaxVertices || NNZ > kMaxAdjacency) return SPC_ERR_UNSUPPORTED;
+    const uint64_t rows64 = directed ? 2 * N64 : N64, slots64 = directed ? 2 * NNZ : NNZ;
+    if (rows64 > kMaxVertices || slots64 > kMaxAdjacency) return SPC_ERR_UNSUPPORTED;
     int db = (o->dist_bits == 16) ? 16 : 8;
     if (db == 8 && N64 > Ent<8>::kMaxHub - 1) {
         if (o->dist_bits == 8) return SPC_ERR_UNSUPPORTED;
@@ -2290,9 +2571,10 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         const char *ev = std::getenv("SPC_VMM");
         B.vmm = vmm_supported() && !(ev && ev[0] == '0');
     }
-    B.N = (uint32_t)N64;
-    B.NNZ = NNZ;
-    B.prop = o->propagation;
+    B.N = (uint32_t)rows64;
+    B.NNZ = slots64;
+    B.nreal = directed ? (uint32_t)N64 : 0;
+    B.prop = directed ? (uint32_t)SPC_PROPAGATE_PULL : o->propagation;
     B.k = k;
     B.db = db;
     {
@@ -2341,6 +2623,10 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
             ix->blocks.emplace_back(blk, (size_t)b);
             ix->index_bytes += b;
         }
+        if (spc_status e = attach_graph_table(B, ix); e != SPC_OK) {
+            spc_free(ix);
+            return e;
+        }
         *out = ix;
         return SPC_OK;
     }
@@ -2348,7 +2634,10 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     SPC_TRY(B.arena.alloc(&B.ctr, 8));
 
     SPC_HIP(hipEventRecord(ev[0], st));
-    SPC_TRY(preprocess(B, gs, n_order == k, n_tie == k, o->validate != 0, o->reduce));
+    if (directed)
+        SPC_TRY(preprocess_directed(B, gs[0], n_order == k, n_tie == k, o->validate != 0));
+    else
+        SPC_TRY(preprocess(B, gs, n_order == k, n_tie == k, o->validate != 0, o->reduce));
     SPC_HIP(hipEventRecord(ev[1], st));
     // from here on the graph is the core when the 1-shell was cut off
     const uint32_t N = B.N;
@@ -2398,19 +2687,19 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
                 SPC_TRY(B.arena.alloc(&l8, nl));
                 B.land = l8;
                 hipLaunchKernelGGL(k_land_init<8>, dim3(grid_stride(nl)), dim3(kBlock), 0, st, N,
-                                   (const uint32_t *)B.gbase, l8);
+                                   B.nreal, (const uint32_t *)B.gbase, l8);
             } else {
                 uint16_t *l16 = nullptr;
                 SPC_TRY(B.arena.alloc(&l16, nl));
                 B.land = l16;
                 hipLaunchKernelGGL(k_land_init<16>, dim3(grid_stride(nl)), dim3(kBlock), 0, st, N,
-                                   (const uint32_t *)B.gbase, l16);
+                                   B.nreal, (const uint32_t *)B.gbase, l16);
             }
             SPC_LAUNCHED();
         }
         SPC_TRY(B.arena.alloc(&B.lc, (uint64_t)N + 1));
         SPC_TRY(B.arena.alloc(&B.lc2, (uint64_t)N + 1));
-        hipLaunchKernelGGL(k_lc_init, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, st, N,
+        hipLaunchKernelGGL(k_lc_init, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, st, N, B.nreal,
                            (const uint32_t *)B.gbase, B.lc);
         SPC_LAUNCHED();
         uint64_t lcap = std::max<uint64_t>((uint64_t)N + NNZ / 2, 1024);
@@ -2419,13 +2708,13 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
             SPC_TRY(B.arena.alloc(&h, lcap));
             B.lab_hd = h;
             hipLaunchKernelGGL(k_round0<8>, dim3(grid_for((uint64_t)N + 1, kBlock)), dim3(kBlock), 0,
-                               st, N, B.rhub[0], B.rcnt[0], rs, rl, B.lab_off, h);
+                               st, N, B.nreal, B.rhub[0], B.rcnt[0], rs, rl, B.lab_off, h);
         } else {
             uint64_t *h = nullptr;
             SPC_TRY(B.arena.alloc(&h, lcap));
             B.lab_hd = h;
             hipLaunchKernelGGL(k_round0<16>, dim3(grid_for((uint64_t)N + 1, kBlock)), dim3(kBlock), 0,
-                               st, N, B.rhub[0], B.rcnt[0], rs, rl, B.lab_off, h);
+                               st, N, B.nreal, B.rhub[0], B.rcnt[0], rs, rl, B.lab_off, h);
         }
         SPC_LAUNCHED();
         B.lab_cap = lcap;
@@ -2474,8 +2763,9 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
     spc_index *ix = new (std::nothrow) spc_index();
     if (!ix) return SPC_ERR_OUT_OF_MEMORY;
     ix->device = dev;
-    ix->n = N;
-    ix->m = NNZ_in / 2;
+    ix->n = directed ? B.nreal : N;
+    ix->m = directed ? NNZ_in : NNZ_in / 2;  // arcs of a directed graph
+    ix->nreal = B.nreal;
     ix->dist_bits = (uint32_t)B.db;
     ix->out_bits = out_bits;
     ix->rounds = last_round;
@@ -2526,6 +2816,10 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
             ix->blocks.emplace_back(blk, (size_t)b);
             ix->index_bytes += b;
         }
+    }
+    if (spc_status e = attach_graph_table(B, ix); e != SPC_OK) {
+        spc_free(ix);
+        return e;
     }
     *out = ix;
     return SPC_OK;

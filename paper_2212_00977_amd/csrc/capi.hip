@@ -56,6 +56,25 @@ spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_
                            static_cast<hipStream_t>(stream));
 }
 
+spc_status spc_query_batch_multi(const spc_index *ix, const uint32_t *graph_ids, const uint32_t *s,
+                                 const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                                 uint8_t *flags_out, void *stream) {
+    return spc::query_multi_impl(ix, graph_ids, s, t, nq, dist_out, count_out, flags_out,
+                                 static_cast<hipStream_t>(stream));
+}
+
+spc_status spc_tune_query_buckets(spc_index *ix, const uint32_t *graph_ids, const uint32_t *s,
+                                  const uint32_t *t, uint64_t nq, void *stream, uint32_t *small_out) {
+    return spc::tune_query_buckets_impl(ix, graph_ids, s, t, nq, static_cast<hipStream_t>(stream),
+                                        small_out);
+}
+
+spc_status spc_set_query_buckets(spc_index *ix, uint32_t small) {
+    if (!ix) return SPC_ERR_INVALID_ARG;
+    ix->query_small = small;
+    return SPC_OK;
+}
+
 void spc_free(spc_index *ix) {
     if (!ix) return;
     int cur = 0;
@@ -95,6 +114,7 @@ spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
     out->ms_round_kernel = ix->ms_round_kernel;
     out->alg_bytes_round_kernel = ix->alg_bytes_round_kernel;
     out->round_kernel_launches = ix->round_kernel_launches;
+    out->directed = ix->nreal ? 1u : 0u;
     out->query_config = ix->query_cfg;
     return SPC_OK;
 }
@@ -154,7 +174,8 @@ spc_status spc_round_profile(const spc_index *ix, uint32_t max_rounds, double *k
 spc_status spc_graph_entries(const spc_index *ix, uint32_t graph_id, uint32_t *n_out,
                              uint64_t *entries_out) {
     if (!ix || graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
-    uint32_t vb = ix->vbase[graph_id], n = ix->gn[graph_id];
+    // label rows: the graph's vertices, twice for a directed graph
+    uint32_t vb = ix->vbase[graph_id], n = ix->gn[graph_id] * (ix->nreal ? 2u : 1u);
     uint64_t e[2] = {0, 0};
     if (hipMemcpy(&e[0], ix->lab_off + vb, 8, hipMemcpyDeviceToHost) != hipSuccess) return SPC_ERR_DEVICE;
     if (hipMemcpy(&e[1], ix->lab_off + vb + n, 8, hipMemcpyDeviceToHost) != hipSuccess)

@@ -28,6 +28,9 @@ namespace spc {
 
 namespace {
 
+// queries bucketed per pass (perm entries of spc_query_batch_multi's scratch)
+constexpr uint64_t kMultiChunk = 1ull << 24;
+
 struct QueryArgs {
     const uint64_t *lab_off;
     const void *lab_hd;
@@ -47,38 +50,70 @@ struct QueryArgs {
     void *dist_out;
     uint64_t *count_out;
     uint8_t *flags_out;
+    // queries that name their graph (null: every query is on the graph
+    // view above): graph id per query, and per graph (vbase, gn, obase, on)
+    const uint32_t *gid;
+    const uint32_t *g_tab;
+    uint32_t ngraphs;
+    // bucketed launches: this launch answers queries perm[i] (back: perm[nq
+    // - 1 - i]) for i < *cnt; perm null: queries 0 .. nq-1
+    const uint32_t *perm;
+    const uint32_t *cnt;
+    bool back;
+    // directed index: t's row is its in-label, t_row past its out-label
+    uint32_t t_row;
 };
 
-// kQStage: L(s) entries staged per wave; kQTiles: L(t) tiles of 64
-// requested together.  The pair is a launch configuration (see kQueryCfg).
-// DB: label distance bits; OB: output distance bits; RED: the index was
-// built with a reduction (the plain instances carry none of its code).
-template <int DB, int OB, bool RED, uint32_t kQStage, int kQTiles>
+// kQStage: L(s) entries staged per query; kQTiles: L(t) tiles of G entries
+// requested together; G: lanes per query (64: one query per wave, fewer:
+// several queries per wave for short labels).  The triple is a launch
+// configuration (see kQueryCfg).  DB: label distance bits; OB: output
+// distance bits; RED: the index was built with a reduction (the plain
+// instances carry none of its code).
+template <int DB, int OB, bool RED, uint32_t kQStage, int kQTiles, int G>
 __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     using E = typename Ent<DB>::T;
     using DT = typename std::conditional<OB == 8, uint8_t, uint16_t>::type;
-    __shared__ E stage[kWaves][kQStage];
-    const uint64_t q = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (q >= a.nq) return;
-    const uint32_t lane = threadIdx.x & 63;
-    E *st = stage[threadIdx.x >> 6];
+    static_assert(G == 64 || G == 32 || G == 16, "lanes per query");
+    constexpr bool kWave = G == 64;  // one query per wave: uniform values in scalar registers
+    __shared__ E stage[kBlock / G][kQStage];
+    const uint64_t q = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+    const uint64_t nq = a.cnt ? (uint64_t)*a.cnt : a.nq;
+    if (q >= nq) return;
+    const uint32_t lane = threadIdx.x & (G - 1);
+    // this query's lanes within the wave
+    const uint64_t gmask = kWave ? ~0ull : (((1ull << G) - 1) << ((threadIdx.x & 63) & ~(uint32_t)(G - 1)));
+    E *st = stage[threadIdx.x / G];
     const E *hd = static_cast<const E *>(a.lab_hd);
-    // one query per wave: its ids, ranks and label ranges are wave-uniform
-    // and kept in scalar registers
-    const uint32_t s = __builtin_amdgcn_readfirstlane(a.s[q]), t = __builtin_amdgcn_readfirstlane(a.t[q]);
+    auto uni = [](uint32_t x) -> uint32_t { return kWave ? __builtin_amdgcn_readfirstlane(x) : x; };
+    const uint64_t qi = a.perm ? a.perm[a.back ? a.nq - 1 - q : q] : q;
+    uint32_t vbase = a.vbase, gn = a.gn, obase = a.obase, on = a.on;
+    bool bad = false;
+    if (a.gid) {
+        const uint32_t g = uni(a.gid[qi]);
+        if (g < a.ngraphs) {
+            vbase = uni(a.g_tab[4 * g]);
+            gn = uni(a.g_tab[4 * g + 1]);
+            obase = uni(a.g_tab[4 * g + 2]);
+            on = uni(a.g_tab[4 * g + 3]);
+        } else {
+            bad = true;
+        }
+    }
+    const uint32_t s = uni(a.s[qi]), t = uni(a.t[qi]);
     const DT kInf = (DT)~(DT)0;
-    const uint32_t lim = RED ? a.on : a.gn;
-    if (s >= lim || t >= lim) {
+    const uint32_t lim = RED ? on : gn;
+    if (bad || s >= lim || t >= lim) {
         if (lane == 0) {
-            static_cast<DT *>(a.dist_out)[q] = kInf;
-            a.count_out[q] = 0;
-            if (a.flags_out) a.flags_out[q] = SPC_FLAG_INVALID;
+            static_cast<DT *>(a.dist_out)[qi] = kInf;
+            a.count_out[qi] = 0;
+            if (a.flags_out) a.flags_out[qi] = SPC_FLAG_INVALID;
         }
         return;
     }
     uint32_t rs, rt, extra = 0;
     if constexpr (RED) {
-        const uint32_t gs = a.obase + s, gt = a.obase + t;
+        const uint32_t gs = obase + s, gt = obase + t;
         const uint32_t cs = a.red_root[gs], ct = a.red_root[gt];
         if (cs == ct && a.red_same) {
             // one class: the same vertex (0, 1); adjacent twins (1, 1);
@@ -100,9 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
                         cc = k;
                     }
                 }
-                static_cast<DT *>(a.dist_out)[q] = dd;
-                a.count_out[q] = cc;
-                if (a.flags_out) a.flags_out[q] = fl;
+                static_cast<DT *>(a.dist_out)[qi] = dd;
+                a.count_out[qi] = cc;
+                if (a.flags_out) a.flags_out[qi] = fl;
             }
             return;
         }
@@ -118,18 +153,18 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
                     x = a.red_parent[x];
                     y = a.red_parent[y];
                 }
-                static_cast<DT *>(a.dist_out)[q] = (DT)(tot - 2 * dx);
-                a.count_out[q] = 1;
-                if (a.flags_out) a.flags_out[q] = 0;
+                static_cast<DT *>(a.dist_out)[qi] = (DT)(tot - 2 * dx);
+                a.count_out[qi] = 1;
+                if (a.flags_out) a.flags_out[qi] = 0;
             }
             return;
         }
-        extra = __builtin_amdgcn_readfirstlane(a.red_depth[gs] + a.red_depth[gt]);
-        rs = __builtin_amdgcn_readfirstlane(a.rank_of[cs]);
-        rt = __builtin_amdgcn_readfirstlane(a.rank_of[ct]);
+        extra = uni(a.red_depth[gs] + a.red_depth[gt]);
+        rs = uni(a.rank_of[cs]);
+        rt = uni(a.rank_of[ct]);
     } else {
-        rs = __builtin_amdgcn_readfirstlane(a.rank_of[a.vbase + s]);
-        rt = __builtin_amdgcn_readfirstlane(a.rank_of[a.vbase + t]);
+        rs = uni(a.rank_of[vbase + s]);
+        rt = uni(a.rank_of[vbase + t]) + a.t_row;
     }
     const uint64_t as = a.lab_off[rs], na = a.lab_off[rs + 1] - as;
     const uint64_t bs = a.lab_off[rt], nb = a.lab_off[rt + 1] - bs;
@@ -145,21 +180,21 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
         const uint32_t cnt = (uint32_t)((na - ia) < kQStage ? (na - ia) : kQStage);
         E nxt = (E)~(E)0;
 #pragma unroll
-        for (uint32_t j = 0; j < kQStage / 64; j++) {
-            const uint32_t k = j * 64 + lane;
+        for (uint32_t j = 0; j < kQStage / G; j++) {
+            const uint32_t k = j * G + lane;
             if (k < cnt) st[k] = hd[as + ia + k];
         }
         if (lane == 0 && ia + cnt < na) nxt = hd[as + ia + cnt];
         wave_lds_sync();
         // staged hubs are [first, hub_hi): up to the next stage's first hub
-        const uint32_t hub_hi = (ia + cnt < na) ? e_hub<DB>((E)__shfl(nxt, 0, 64))
+        const uint32_t hub_hi = (ia + cnt < na) ? e_hub<DB>((E)__shfl(nxt, 0, G))
                                                 : e_hub<DB>(st[cnt - 1]) + 1;
         bool more = true;
         while (more && ib < nb) {
             E eb[kQTiles];
 #pragma unroll
             for (int j = 0; j < kQTiles; j++) {
-                const uint64_t i = ib + (uint64_t)j * 64 + lane;
+                const uint64_t i = ib + (uint64_t)j * G + lane;
                 eb[j] = i < nb ? hd[bs + i] : (E)~(E)0;
             }
             uint32_t pos[kQTiles];
@@ -167,9 +202,9 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
             uint32_t n_in = 0;
 #pragma unroll
             for (int j = 0; j < kQTiles; j++) {
-                const uint64_t i = ib + (uint64_t)j * 64 + lane;
+                const uint64_t i = ib + (uint64_t)j * G + lane;
                 in[j] = i < nb && e_hub<DB>(eb[j]) < hub_hi;
-                n_in += (uint32_t)__popcll(__ballot(in[j]));
+                n_in += (uint32_t)__popcll(__ballot(in[j]) & gmask);
                 pos[j] = 0;
             }
             // lower bound of each streamed hub among the staged hubs; the
@@ -200,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
                     ct[j] = 0;
                     if (dd[j] == gmin) {
                         cs[j] = a.lab_cnt[as + ia + pos[j]];
-                        ct[j] = a.lab_cnt[bs + ib + (uint64_t)j * 64 + lane];
+                        ct[j] = a.lab_cnt[bs + ib + (uint64_t)j * G + lane];
                         // a hub other than s and t lies inside the path
                         if (RED && a.hub_w) {
                             const uint32_t h = e_hub<DB>(eb[j]);
@@ -218,18 +253,19 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
             }
             // L(t) is sorted: the in-range entries are a prefix
             ib += n_in;
-            more = n_in == (uint32_t)(kQTiles * 64);
+            more = n_in == (uint32_t)(kQTiles * G);
         }
         ia += cnt;
         wave_lds_sync();  // the stage is rewritten next
     }
-    // wave reduction: least distance, then the saturating sum at it
+    // reduction over the query's lanes: least distance, then the saturating
+    // sum at it
     uint32_t mn = best;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
+    for (int o = G / 2; o > 0; o >>= 1) mn = min(mn, (uint32_t)__shfl_xor(mn, o, G));
     uint64_t part = (best == mn) ? sum : 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) part = sat_add(part, __shfl_xor(part, o, 64));
+    for (int o = G / 2; o > 0; o >>= 1) part = sat_add(part, __shfl_xor(part, o, G));
     if (lane == 0) {
         uint8_t fl = 0;
         DT dout;
@@ -245,10 +281,55 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
             if (part == kSat) fl |= SPC_FLAG_SATURATED;
             if (a.cap && mn > a.cap) fl |= SPC_FLAG_HORIZON;
         }
-        static_cast<DT *>(a.dist_out)[q] = dout;
-        a.count_out[q] = cout;
-        if (a.flags_out) a.flags_out[q] = fl;
+        static_cast<DT *>(a.dist_out)[qi] = dout;
+        a.count_out[qi] = cout;
+        if (a.flags_out) a.flags_out[qi] = fl;
     }
+}
+
+// Bucketing of a query batch by its work, |L(s)| + |L(t)|: queries at most
+// `small` go to the front of perm (answered G < 64 lanes each), the others
+// to the back (a wave each).  cnt[0] counts the front, cnt[1] the back;
+// both start at zero.  The order within a bucket is arbitrary (answers are
+// written by query index).
+__global__ void k_qbucket(QueryArgs a, uint32_t small, uint32_t *perm, uint32_t *cnt) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.nq) return;
+    uint32_t vbase = a.vbase, gn = a.gn, obase = a.obase, on = a.on;
+    bool big = false;
+    if (a.gid) {
+        const uint32_t g = a.gid[q];
+        if (g < a.ngraphs) {
+            vbase = a.g_tab[4 * g];
+            gn = a.g_tab[4 * g + 1];
+            obase = a.g_tab[4 * g + 2];
+            on = a.g_tab[4 * g + 3];
+        } else {
+            gn = on = 0;  // invalid: answered at once by either kernel
+        }
+    }
+    const uint32_t s = a.s[q], t = a.t[q];
+    const uint32_t lim = a.red_root ? on : gn;
+    if (s < lim && t < lim) {
+        uint32_t rs, rt;
+        if (a.red_root) {
+            rs = a.rank_of[a.red_root[obase + s]];
+            rt = a.rank_of[a.red_root[obase + t]];
+        } else {
+            rs = a.rank_of[vbase + s];
+            rt = a.rank_of[vbase + t] + a.t_row;
+        }
+        const uint64_t w = (a.lab_off[rs + 1] - a.lab_off[rs]) + (a.lab_off[rt + 1] - a.lab_off[rt]);
+        big = w > small;
+    }
+    if (big)
+        perm[a.nq - 1 - atomicAdd(&cnt[1], 1u)] = (uint32_t)q;
+    else
+        perm[atomicAdd(&cnt[0], 1u)] = (uint32_t)q;
+}
+
+__global__ void k_qzero(uint32_t *cnt, uint32_t n) {
+    if (threadIdx.x < n) cnt[threadIdx.x] = 0;
 }
 
 // Export kernels: labels of one graph, rank space of that graph.
@@ -299,36 +380,68 @@ constexpr uint32_t kQueryCfgs = sizeof(kQueryCfg) / sizeof(kQueryCfg[0]);
 template <int DB, int OB, bool RED>
 void launch_cfg(uint32_t cfg, dim3 g, hipStream_t st, const QueryArgs &c) {
     switch (cfg) {
-        case 1: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 2: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 4>), g, dim3(kBlock), 0, st, c); break;
-        case 3: hipLaunchKernelGGL((k_query<DB, OB, RED, 256, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 4: hipLaunchKernelGGL((k_query<DB, OB, RED, 256, 2>), g, dim3(kBlock), 0, st, c); break;
-        case 5: hipLaunchKernelGGL((k_query<DB, OB, RED, 1024, 1>), g, dim3(kBlock), 0, st, c); break;
-        case 6: hipLaunchKernelGGL((k_query<DB, OB, RED, 1024, 2>), g, dim3(kBlock), 0, st, c); break;
-        case 7: hipLaunchKernelGGL((k_query<DB, OB, RED, 2048, 1>), g, dim3(kBlock), 0, st, c); break;
-        default: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 2>), g, dim3(kBlock), 0, st, c); break;
+        case 1: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 1, 64>), g, dim3(kBlock), 0, st, c); break;
+        case 2: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 4, 64>), g, dim3(kBlock), 0, st, c); break;
+        case 3: hipLaunchKernelGGL((k_query<DB, OB, RED, 256, 1, 64>), g, dim3(kBlock), 0, st, c); break;
+        case 4: hipLaunchKernelGGL((k_query<DB, OB, RED, 256, 2, 64>), g, dim3(kBlock), 0, st, c); break;
+        case 5: hipLaunchKernelGGL((k_query<DB, OB, RED, 1024, 1, 64>), g, dim3(kBlock), 0, st, c); break;
+        case 6: hipLaunchKernelGGL((k_query<DB, OB, RED, 1024, 2, 64>), g, dim3(kBlock), 0, st, c); break;
+        case 7: hipLaunchKernelGGL((k_query<DB, OB, RED, 2048, 1, 64>), g, dim3(kBlock), 0, st, c); break;
+        default: hipLaunchKernelGGL((k_query<DB, OB, RED, 512, 2, 64>), g, dim3(kBlock), 0, st, c); break;
     }
 }
+// short labels: 16 lanes per query (16 queries per workgroup), L(s) staged
+// 128 entries at a time, L(t) streamed two 16-entry tiles per round
+constexpr int kSmallG = 16;
+template <int DB, int OB, bool RED>
+void launch_small(dim3 g, hipStream_t st, const QueryArgs &c) {
+    hipLaunchKernelGGL((k_query<DB, OB, RED, 128, 2, kSmallG>), g, dim3(kBlock), 0, st, c);
+}
 template <int DB, int OB>
-void launch_red(uint32_t cfg, dim3 g, hipStream_t st, const QueryArgs &c) {
-    if (c.red_root)
+void launch_red(uint32_t cfg, bool small, dim3 g, hipStream_t st, const QueryArgs &c) {
+    if (small) {
+        if (c.red_root)
+            launch_small<DB, OB, true>(g, st, c);
+        else
+            launch_small<DB, OB, false>(g, st, c);
+    } else if (c.red_root) {
         launch_cfg<DB, OB, true>(cfg, g, st, c);
-    else
+    } else {
         launch_cfg<DB, OB, false>(cfg, g, st, c);
+    }
 }
 
-// 16-bit labels always come with 16-bit outputs
+// 16-bit labels always come with 16-bit outputs.  Work-items of a launch:
+// nq * (lanes per query), kept below 2^32 by the callers' chunks.
 spc_status launch_query(uint32_t dist_bits, uint32_t out_bits, uint32_t cfg, const QueryArgs &c,
-                        hipStream_t st) {
-    const dim3 g((uint32_t)((c.nq + kWaves - 1) / kWaves));
+                        hipStream_t st, bool small = false) {
+    const uint64_t per_block = small ? kBlock / kSmallG : kWaves;
+    const dim3 g((uint32_t)((c.nq + per_block - 1) / per_block));
     if (dist_bits == 16)
-        launch_red<16, 16>(cfg, g, st, c);
+        launch_red<16, 16>(cfg, small, g, st, c);
     else if (out_bits == 16)
-        launch_red<8, 16>(cfg, g, st, c);
+        launch_red<8, 16>(cfg, small, g, st, c);
     else
-        launch_red<8, 8>(cfg, g, st, c);
+        launch_red<8, 8>(cfg, small, g, st, c);
     SPC_LAUNCHED();
     return SPC_OK;
+}
+
+// The index's arrays in the arguments of a query launch.
+QueryArgs index_args(const spc_index *ix) {
+    QueryArgs a = {};
+    a.lab_off = ix->lab_off;
+    a.lab_hd = ix->lab_hd;
+    a.lab_cnt = ix->lab_cnt;
+    a.rank_of = ix->rank_of;
+    a.cap = ix->truncated ? ix->round_cap : 0;
+    a.red_root = ix->reduced ? ix->red_root : nullptr;
+    a.red_depth = ix->red_depth;
+    a.red_parent = ix->red_parent;
+    a.hub_w = ix->hub_w;
+    a.red_same = ix->red_same;
+    a.t_row = ix->nreal;
+    return a;
 }
 
 }  // namespace
@@ -352,6 +465,96 @@ spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
                       hipStream_t st) {
     if (!ix) return SPC_ERR_INVALID_ARG;
     return query_run(ix, graph_id, s, t, nq, dist_out, count_out, flags_out, ix->query_cfg, st);
+}
+
+spc_status query_multi_impl(const spc_index *ix, const uint32_t *gid, const uint32_t *s,
+                            const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                            uint8_t *flags_out, hipStream_t st) {
+    if (!ix) return SPC_ERR_INVALID_ARG;
+    if (nq == 0) return SPC_OK;
+    if (!s || !t || !dist_out || !count_out) return SPC_ERR_INVALID_ARG;
+    if (ix->query_small == 0)
+        return query_multi_run(ix, gid, s, t, nq, dist_out, count_out, flags_out, nullptr, nullptr, 0,
+                               ix->query_cfg, st);
+    // scratch in stream order: freed after the launches that read it
+    const uint64_t np = std::min<uint64_t>(nq, kMultiChunk);
+    void *buf = nullptr;
+    if (hipMallocAsync(&buf, (np + 64) * sizeof(uint32_t), st) != hipSuccess) return SPC_ERR_OUT_OF_MEMORY;
+    uint32_t *perm = static_cast<uint32_t *>(buf);
+    spc_status r = query_multi_run(ix, gid, s, t, nq, dist_out, count_out, flags_out, perm, perm + np,
+                                   ix->query_small, ix->query_cfg, st);
+    if (hipFreeAsync(buf, st) != hipSuccess && r == SPC_OK) r = SPC_ERR_DEVICE;
+    return r;
+}
+
+// Bucket thresholds the tuner times (0: no bucketing).
+constexpr uint32_t kSmallChoices[] = {0, 64, 128, 256, 512, 1024, 2048};
+
+spc_status tune_query_buckets_impl(spc_index *ix, const uint32_t *gid, const uint32_t *s,
+                                   const uint32_t *t, uint64_t nq, hipStream_t st, uint32_t *small_out) {
+    if (!ix || !s || !t || nq == 0 || ix->gn.empty()) return SPC_ERR_INVALID_ARG;
+    const size_t dsz = ix->out_bits == 8 ? 1 : 2;
+    const uint64_t per = (nq * (dsz + 8 + 1) + 255) & ~uint64_t(255);
+    const uint64_t np = std::min<uint64_t>(nq, kMultiChunk);
+    Arena tmp(0, st);
+    uint8_t *buf = nullptr;
+    unsigned int *diff = nullptr;
+    uint32_t *perm = nullptr;
+    SPC_TRY(tmp.alloc(&buf, 2 * per + 16));
+    SPC_TRY(tmp.alloc(&diff, 1));
+    SPC_TRY(tmp.alloc(&perm, np + 64));
+    auto outs = [&](int side, void **d, uint64_t **c, uint8_t **f) {
+        uint8_t *b = buf + side * per;
+        *c = reinterpret_cast<uint64_t *>(b);
+        *d = b + nq * 8;
+        *f = b + nq * (8 + dsz);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SPC_HIP(hipEventCreate(&e0));
+    SPC_HIP(hipEventCreate(&e1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    float best_ms = 0;
+    uint32_t best = ix->query_small;
+    bool first = true;
+    for (uint32_t small : kSmallChoices) {
+        void *d;
+        uint64_t *c;
+        uint8_t *f;
+        outs(first ? 0 : 1, &d, &c, &f);
+        float ms = 0;
+        for (int rep = 0; rep < 2; rep++) {  // the first run warms caches
+            SPC_HIP(hipEventRecord(e0, st));
+            SPC_TRY(query_multi_run(ix, gid, s, t, nq, d, c, f, perm, perm + np, small, ix->query_cfg, st));
+            SPC_HIP(hipEventRecord(e1, st));
+            SPC_HIP(hipEventSynchronize(e1));
+            SPC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (!first) {  // every threshold must give the same answers
+            SPC_HIP(hipMemsetAsync(diff, 0, sizeof(unsigned int), st));
+            const uint64_t used = nq * (dsz + 8 + 1);
+            hipLaunchKernelGGL(k_same, dim3(grid1(used) < 4096 ? grid1(used) : 4096), dim3(kBlock), 0, st,
+                               buf, buf + per, used, diff);
+            SPC_LAUNCHED();
+            unsigned int h = 0;
+            SPC_HIP(hipMemcpyAsync(&h, diff, sizeof(h), hipMemcpyDeviceToHost, st));
+            SPC_HIP(hipStreamSynchronize(st));
+            if (h) return SPC_ERR_DEVICE;
+        }
+        if (first || ms < best_ms) {
+            best_ms = ms;
+            best = small;
+        }
+        first = false;
+    }
+    ix->query_small = best;
+    if (small_out) *small_out = best;
+    return SPC_OK;
 }
 
 uint32_t query_cfg_count() { return kQueryCfgs; }
@@ -435,24 +638,14 @@ spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, 
     if (graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
     if (nq == 0) return SPC_OK;
     if (!s || !t || !dist_out || !count_out) return SPC_ERR_INVALID_ARG;
-    QueryArgs a;
-    a.lab_off = ix->lab_off;
-    a.lab_hd = ix->lab_hd;
-    a.lab_cnt = ix->lab_cnt;
-    a.rank_of = ix->rank_of;
+    QueryArgs a = index_args(ix);
     a.s = s;
     a.t = t;
     a.nq = nq;
     a.vbase = ix->vbase[graph_id];
     a.gn = ix->gn[graph_id];
-    a.cap = ix->truncated ? ix->round_cap : 0;
-    a.red_root = ix->reduced ? ix->red_root : nullptr;
-    a.red_depth = ix->red_depth;
-    a.red_parent = ix->red_parent;
     a.obase = ix->reduced ? ix->obase[graph_id] : 0;
     a.on = ix->reduced ? ix->on[graph_id] : 0;
-    a.hub_w = ix->hub_w;
-    a.red_same = ix->red_same;
     a.dist_out = dist_out;
     a.count_out = count_out;
     a.flags_out = flags_out;
@@ -476,11 +669,71 @@ spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, 
 
 }  // namespace
 
+// Queries that name their graph (gid null: graph 0), bucketed by the work
+// |L(s)| + |L(t)|: up to `small` entries 16 lanes per query, the rest a wave
+// each with the index's configuration (small = 0: no bucketing).  perm
+// holds min(nq, kMultiChunk) entries and cnt two; both are scratch written
+// before they are read, on `st`, so calls sharing them must not overlap.
+spc_status query_multi_run(const spc_index *ix, const uint32_t *gid, const uint32_t *s,
+                           const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                           uint8_t *flags_out, uint32_t *perm, uint32_t *cnt, uint32_t small,
+                           uint32_t cfg, hipStream_t st) {
+    if (!ix) return SPC_ERR_INVALID_ARG;
+    if (nq == 0) return SPC_OK;
+    if (!s || !t || !dist_out || !count_out) return SPC_ERR_INVALID_ARG;
+    if (cfg >= kQueryCfgs) return SPC_ERR_INVALID_ARG;
+    QueryArgs a = index_args(ix);
+    a.gid = gid;
+    a.g_tab = ix->g_tab;
+    a.ngraphs = (uint32_t)ix->gn.size();
+    if (!gid) {  // every query on graph 0
+        if (ix->gn.empty()) return SPC_ERR_INVALID_ARG;
+        a.vbase = ix->vbase[0];
+        a.gn = ix->gn[0];
+        a.obase = ix->reduced ? ix->obase[0] : 0;
+        a.on = ix->reduced ? ix->on[0] : 0;
+    }
+    const size_t dsz = ix->out_bits == 8 ? 1 : 2;
+    for (uint64_t q0 = 0; q0 < nq; q0 += kMultiChunk) {
+        const uint64_t nc = std::min<uint64_t>(kMultiChunk, nq - q0);
+        QueryArgs c = a;
+        c.s = s + q0;
+        c.t = t + q0;
+        c.gid = gid ? gid + q0 : nullptr;
+        c.nq = nc;
+        c.dist_out = static_cast<char *>(dist_out) + q0 * dsz;
+        c.count_out = count_out + q0;
+        c.flags_out = flags_out ? flags_out + q0 : nullptr;
+        if (small == 0) {
+            SPC_TRY(launch_query(ix->dist_bits, ix->out_bits, cfg, c, st));
+            continue;
+        }
+        hipLaunchKernelGGL(k_qzero, dim3(1), dim3(64), 0, st, cnt, 2u);
+        SPC_LAUNCHED();
+        hipLaunchKernelGGL(k_qbucket, dim3(grid1(nc)), dim3(kBlock), 0, st, c, small, perm, cnt);
+        SPC_LAUNCHED();
+        QueryArgs cs = c, cl = c;
+        cs.perm = perm;
+        cs.cnt = cnt;
+        cs.back = false;
+        cl.perm = perm;
+        cl.cnt = cnt + 1;
+        cl.back = true;
+        SPC_TRY(launch_query(ix->dist_bits, ix->out_bits, cfg, cs, st, true));
+        SPC_TRY(launch_query(ix->dist_bits, ix->out_bits, cfg, cl, st, false));
+    }
+    return SPC_OK;
+}
+
+
 spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, uint32_t *hub,
                        uint16_t *dist, uint64_t *count, uint32_t *order, int32_t on_device,
                        hipStream_t st) {
     if (!ix || graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
-    const uint32_t vb = ix->vbase[graph_id], n = ix->gn[graph_id];
+    // label rows (twice the vertices of a directed graph); the order has
+    // one entry per vertex
+    const uint32_t vb = ix->vbase[graph_id], nv = ix->gn[graph_id];
+    const uint32_t n = ix->nreal ? 2 * nv : nv;
     uint64_t e0 = 0, e1 = 0;
     SPC_HIP(hipMemcpy(&e0, ix->lab_off + vb, sizeof(uint64_t), hipMemcpyDeviceToHost));
     SPC_HIP(hipMemcpy(&e1, ix->lab_off + vb + n, sizeof(uint64_t), hipMemcpyDeviceToHost));
@@ -496,7 +749,7 @@ spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, ui
         if (hub) SPC_TRY(tmp.alloc(&d_hub, ne));
         if (dist) SPC_TRY(tmp.alloc(&d_dist, ne));
         if (count) SPC_TRY(tmp.alloc(&d_cnt, ne));
-        if (order) SPC_TRY(tmp.alloc(&d_ord, (uint64_t)n));
+        if (order) SPC_TRY(tmp.alloc(&d_ord, (uint64_t)nv));
     }
     if (off) {
         hipLaunchKernelGGL(k_export_off, dim3(grid1((uint64_t)n + 1)), dim3(kBlock), 0, st,
@@ -520,8 +773,8 @@ spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, ui
                                vb, h, dd, cc);
         SPC_LAUNCHED();
     }
-    if (order && n) {
-        hipLaunchKernelGGL(k_export_order, dim3(grid1(n)), dim3(kBlock), 0, st, ix->order, vb, n,
+    if (order && nv) {
+        hipLaunchKernelGGL(k_export_order, dim3(grid1(nv)), dim3(kBlock), 0, st, ix->order, vb, nv,
                            ix->reduced ? ix->core_vid : nullptr, ix->reduced ? ix->obase[graph_id] : 0,
                            d_ord);
         SPC_LAUNCHED();
@@ -531,7 +784,7 @@ spc_status export_impl(const spc_index *ix, uint32_t graph_id, uint64_t *off, ui
         if (hub && ne) SPC_HIP(hipMemcpyAsync(hub, d_hub, ne * 4, hipMemcpyDeviceToHost, st));
         if (dist && ne) SPC_HIP(hipMemcpyAsync(dist, d_dist, ne * 2, hipMemcpyDeviceToHost, st));
         if (count && ne) SPC_HIP(hipMemcpyAsync(count, d_cnt, ne * 8, hipMemcpyDeviceToHost, st));
-        if (order && n) SPC_HIP(hipMemcpyAsync(order, d_ord, (uint64_t)n * 4, hipMemcpyDeviceToHost, st));
+        if (order && nv) SPC_HIP(hipMemcpyAsync(order, d_ord, (uint64_t)nv * 4, hipMemcpyDeviceToHost, st));
     }
     SPC_HIP(hipStreamSynchronize(st));
     return SPC_OK;

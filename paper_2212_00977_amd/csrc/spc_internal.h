@@ -279,6 +279,7 @@ class Arena {
         return b;
     }
     uint64_t used() const { return used_; }
+    uint64_t budget() const { return budget_; }
     uint64_t peak() const { return peak_; }
 
   private:
@@ -363,6 +364,13 @@ struct spc_index {
     uint64_t alg_bytes_round_kernel = 0;
     uint64_t round_kernel_launches = 0;
     uint32_t query_cfg = 0;  // query launch configuration (query.hip)
+    // queries with |L(s)| + |L(t)| at most this are answered 16 lanes per
+    // query by spc_query_batch_multi (0: no bucketing)
+    uint32_t query_small = 256;
+    uint32_t *g_tab = nullptr;  // per graph (vbase, gn, obase, on), device
+    // directed: label rows [0, nreal) are out-labels, [nreal, 2 nreal)
+    // in-labels (0: undirected)
+    uint32_t nreal = 0;
     uint32_t out_bits = 8;   // width of query dist outputs
     // SPC_REDUCE_ONE_SHELL: input vertex ranges [obase[i], obase[i] + on[i])
     // of the graphs, and per input vertex (union ids) the core id of its
@@ -394,6 +402,15 @@ spc_status twin_reduce(Arena &ar, hipStream_t st, uint64_t *ws, uint32_t N, uint
 spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                       uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
                       hipStream_t st);
+spc_status query_multi_run(const spc_index *ix, const uint32_t *gid, const uint32_t *s,
+                           const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                           uint8_t *flags_out, uint32_t *perm, uint32_t *cnt, uint32_t small,
+                           uint32_t cfg, hipStream_t st);
+spc_status tune_query_buckets_impl(spc_index *ix, const uint32_t *gid, const uint32_t *s,
+                                   const uint32_t *t, uint64_t nq, hipStream_t st, uint32_t *small_out);
+spc_status query_multi_impl(const spc_index *ix, const uint32_t *gid, const uint32_t *s,
+                            const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                            uint8_t *flags_out, hipStream_t st);
 // order.hip
 spc_status hybrid_order_impl(const spc_graph *g, uint32_t delta, uint32_t *order, uint32_t *core_out);
 spc_status tune_queries_impl(spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,

@@ -31,10 +31,12 @@ class Graph:
     order: Optional[np.ndarray] = None     # explicit rank -> vertex order (uint32[n]) or None
     tie_key: Optional[np.ndarray] = None   # uint64[n] random tie keys or None
     meta: dict = field(default_factory=dict)
+    directed: bool = False  # off/adj hold each arc once, in its tail's row
 
     @property
     def m(self) -> int:
-        return int(self.adj.shape[0]) // 2
+        """Undirected edges, or arcs of a directed graph."""
+        return int(self.adj.shape[0]) if self.directed else int(self.adj.shape[0]) // 2
 
     def degrees(self) -> np.ndarray:
         return np.diff(self.off).astype(np.int64)
@@ -165,7 +167,42 @@ def chung_lu(n: int, seed: int, exponent: float = 2.1, wmin: float = 2.0,
 
 def rmat(scale: int, edge_factor: int, seed, a=0.57, b=0.19, c=0.19) -> Graph:
     """R-MAT: edge_factor * 2^scale sampled edges, no noise; symmetrised,
-    deduplicated, loops dropped; all 2^scale vertices kept.
+    deduplicated, loops dropped; all 2^scale vertices kept."""
+    n = 1 << scale
+    src, dst = _rmat_pairs(scale, edge_factor, seed, a, b, c)
+    return from_edges(n, np.stack([src, dst], axis=1),
+                      name=f"rmat_s{scale}_ef{edge_factor}", scale=scale)
+
+
+def rmat_digraph(scale: int, edge_factor: int, seed, a=0.57, b=0.19, c=0.19) -> Graph:
+    """The R-MAT draws of rmat() kept as arcs (source -> target):
+    deduplicated, loops dropped, all 2^scale vertices kept."""
+    n = 1 << scale
+    src, dst = _rmat_pairs(scale, edge_factor, seed, a, b, c)
+    return digraph_from_arcs(n, np.stack([src, dst], axis=1), name=f"rmat_dir_s{scale}_ef{edge_factor}")
+
+
+def digraph_from_arcs(n: int, arcs, name: str = "") -> Graph:
+    """Directed graph: each distinct non-loop arc (a, b) once, in row a,
+    rows sorted by head."""
+    e = np.asarray(arcs, dtype=np.int64).reshape(-1, 2)
+    e = e[e[:, 0] != e[:, 1]]
+    key = np.unique(e[:, 0] * np.int64(n) + e[:, 1]) if e.size else np.zeros(0, dtype=np.int64)
+    src, dst = (key // n, key % n) if key.size else (key, key)
+    off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(np.bincount(src, minlength=n).astype(np.uint64), out=off[1:])
+    return Graph(n, off, dst.astype(np.uint32), name=name, directed=True)
+
+
+def random_digraph(n: int, m: int, seed: int) -> Graph:
+    """m arcs drawn uniformly (with repeats, then deduplicated, loops dropped)."""
+    rng = np.random.default_rng(seed)
+    arcs = rng.integers(0, n, size=(m, 2)) if n else np.zeros((0, 2), dtype=np.int64)
+    return digraph_from_arcs(n, arcs, name=f"digraph_n{n}_m{m}_s{seed}")
+
+
+def _rmat_pairs(scale: int, edge_factor: int, seed, a=0.57, b=0.19, c=0.19):
+    """The R-MAT draws: (source, target) of edge_factor * 2^scale samples.
 
     Edge i takes, at recursion level L, the uniform number at position
     L * k + i of the stream of ``default_rng(seed)`` (k sampled edges): the
@@ -207,8 +244,7 @@ def rmat(scale: int, edge_factor: int, seed, a=0.57, b=0.19, c=0.19) -> Graph:
         chunk = -(-k // (4 * workers))
         with ThreadPoolExecutor(workers) as ex:
             list(ex.map(lambda i0: fill(i0, min(k, i0 + chunk), rng_at), range(0, k, chunk)))
-    return from_edges(n, np.stack([src, dst], axis=1),
-                      name=f"rmat_s{scale}_ef{edge_factor}", scale=scale)
+    return src, dst
 
 
 def grid_lcc(k: int, delete_frac: float, seed: int) -> Graph:

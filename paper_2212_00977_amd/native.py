@@ -24,14 +24,17 @@ EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_f
            "spc_index_stats", "spc_round_stats", "spc_round_profile", "spc_graph_entries", "spc_export_labels",
            "spc_status_string", "spc_release_cached_memory", "spc_query_config_count",
            "spc_query_config_info", "spc_tune_queries", "spc_set_query_config", "spc_hybrid_order",
-           "spc_export_reduction"]
+           "spc_export_reduction", "spc_query_batch_multi", "spc_tune_query_buckets",
+           "spc_set_query_buckets"]
 
 
 # A test build with tiny on-chip tables (8-bit hash of 128 slots for the
-# puller's label, 256 distinct candidates per chunk): small graphs then take
-# the paths that only large labels take in the default build (unstaged
-# label parts, chunk overflow and narrowing, many chunks per puller).
-SMALL_TABLES = ["-DSPC_LBITS=7", "-DSPC_CBITS=9"]
+# puller's label, 256 distinct candidates per chunk) and 2^14 pulled
+# entries per batch: small graphs then take the paths that only large labels
+# and large rounds take in the default build (unstaged label parts, chunk
+# overflow and narrowing, many chunks per puller, many batches per round,
+# pullers with a buffer of their own).
+SMALL_TABLES = ["-DSPC_LBITS=7", "-DSPC_CBITS=9", "-DSPC_TEMP_LOG2=14", "-DSPC_TEMP_MAX_LOG2=14"]
 SMALL_TABLES_PATH = os.path.join(LIBDIR, "libspc_smalltab.so")
 
 
@@ -62,13 +65,14 @@ class SpcStats(C.Structure):
                 ("ms_round_kernel", C.c_double), ("alg_bytes_round_kernel", C.c_uint64),
                 ("round_kernel_launches", C.c_uint64), ("query_config", C.c_uint32),
                 ("label_bits", C.c_uint32), ("fringe_vertices", C.c_uint64),
-                ("fringe_depth", C.c_uint32), ("twin_vertices", C.c_uint32)]
+                ("fringe_depth", C.c_uint32), ("twin_vertices", C.c_uint32),
+                ("directed", C.c_uint32)]
 
 
 class SpcGraph(C.Structure):
     _fields_ = [("n", C.c_uint32), ("nnz", C.c_uint64), ("row_off", C.c_void_p),
                 ("col", C.c_void_p), ("order", C.c_void_p), ("tie_key", C.c_void_p),
-                ("on_device", C.c_int32)]
+                ("on_device", C.c_int32), ("directed", C.c_int32)]
 
 
 class SpcBuildOpts(C.Structure):
@@ -122,6 +126,12 @@ def load(path: str | None = None):
     L.spc_hybrid_order.restype = C.c_int
     L.spc_export_reduction.argtypes = [vp, u32, vp, vp, vp, i32, vp]
     L.spc_export_reduction.restype = C.c_int
+    L.spc_query_batch_multi.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
+    L.spc_query_batch_multi.restype = C.c_int
+    L.spc_tune_query_buckets.argtypes = [vp, vp, vp, vp, u64, vp, C.POINTER(u32)]
+    L.spc_tune_query_buckets.restype = C.c_int
+    L.spc_set_query_buckets.argtypes = [vp, u32]
+    L.spc_set_query_buckets.restype = C.c_int
     L.spc_set_query_config.argtypes = [vp, u32]
     L.spc_set_query_config.restype = C.c_int
     L.spc_status_string.argtypes = [C.c_int]

@@ -61,7 +61,7 @@ def _np_view(dtype_t):
             torch.uint8: np.uint8}[dtype_t]
 
 
-def _graph_struct(off, adj, order, tie_key, device, keep):
+def _graph_struct(off, adj, order, tie_key, device, keep, directed=False):
     torch = _torch()
     off_t = _dev(off, np.uint64, torch.int64, device)
     n = off_t.shape[0] - 1
@@ -83,6 +83,7 @@ def _graph_struct(off, adj, order, tie_key, device, keep):
         keep.append(tk)
         g.tie_key = tk.data_ptr()
     g.on_device = 1
+    g.directed = 1 if directed else 0
     return g
 
 
@@ -168,31 +169,90 @@ class Index:
                "spc_graph_entries")
         return n.value, e.value
 
+    def _outputs(self, nq, out, what):
+        """Caller's output tensors, checked, or new ones (current stream)."""
+        torch = _torch()
+        bits = self.dist_bits
+        if out is None:
+            n = max(nq, 1)
+            return (torch.empty(n, dtype=torch.uint8 if bits == 8 else torch.int16, device=self.device),
+                    torch.empty(n, dtype=torch.int64, device=self.device),
+                    torch.empty(n, dtype=torch.uint8, device=self.device))
+        dist, cnt, flags = out
+        if dist.element_size() * 8 != bits:
+            raise ValueError(f"{what}: dist output holds {dist.element_size() * 8}-bit values, "
+                             f"the index answers with {bits}-bit distances")
+        if cnt.element_size() != 8 or (flags is not None and flags.element_size() != 1):
+            raise ValueError(f"{what}: count must be 8-byte and flags 1-byte elements")
+        for nm, x in (("dist", dist), ("count", cnt), ("flags", flags)):
+            if x is None:
+                continue
+            if x.numel() < nq or not x.is_contiguous() or x.device.type != "cuda":
+                raise ValueError(f"{what}: {nm} output must be a contiguous device tensor "
+                                 f"of at least {nq} elements")
+        return dist, cnt, flags
+
     def query(self, s, t, graph_id: int = 0, stream=None, out=None):
         """SPC(s, t) for vertex ids of graph `graph_id`.  Returns device
         tensors (dist uint8 / int16-as-uint16, count int64-as-uint64,
-        flags uint8), written asynchronously on `stream`."""
+        flags uint8), written asynchronously on `stream`.  Inputs and new
+        outputs are placed on `stream`, so they stay valid for the launch."""
         torch = _torch()
-        s_t = _dev(s, np.uint32, torch.int32, self.device)
-        t_t = _dev(t, np.uint32, torch.int32, self.device)
-        nq = int(s_t.shape[0])
-        if int(t_t.shape[0]) != nq:
-            raise ValueError("s and t differ in length")
-        bits = self.dist_bits
-        if out is None:
-            dist = torch.empty(max(nq, 1), dtype=torch.uint8 if bits == 8 else torch.int16,
-                               device=self.device)
-            cnt = torch.empty(max(nq, 1), dtype=torch.int64, device=self.device)
-            flags = torch.empty(max(nq, 1), dtype=torch.uint8, device=self.device)
-        else:
-            dist, cnt, flags = out
+        strm = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(strm):
+            s_t = _dev(s, np.uint32, torch.int32, self.device)
+            t_t = _dev(t, np.uint32, torch.int32, self.device)
+            nq = int(s_t.shape[0])
+            if int(t_t.shape[0]) != nq:
+                raise ValueError("s and t differ in length")
+            dist, cnt, flags = self._outputs(nq, out, "Index.query")
         rc = native.load().spc_query_batch(self.handle, graph_id, s_t.data_ptr(), t_t.data_ptr(),
                                            nq, dist.data_ptr(), cnt.data_ptr(),
                                            flags.data_ptr() if flags is not None else None,
-                                           _stream_handle(stream))
+                                           _stream_handle(strm))
         _check(rc, "spc_query_batch")
         self._keep = (s_t, t_t)  # inputs stay alive until the next call
         return dist[:nq], cnt[:nq], (flags[:nq] if flags is not None else None)
+
+    def query_multi(self, graph_ids, s, t, stream=None, out=None):
+        """SPC(s[i], t[i]) on graph graph_ids[i] for every i, in one call
+        (spc_query_batch_multi: bucketed by label length); graph_ids None =
+        every query on graph 0.  Same outputs as query()."""
+        torch = _torch()
+        strm = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(strm):
+            s_t = _dev(s, np.uint32, torch.int32, self.device)
+            t_t = _dev(t, np.uint32, torch.int32, self.device)
+            g_t = None if graph_ids is None else _dev(graph_ids, np.uint32, torch.int32, self.device)
+            nq = int(s_t.shape[0])
+            if int(t_t.shape[0]) != nq or (g_t is not None and int(g_t.shape[0]) != nq):
+                raise ValueError("graph_ids, s and t differ in length")
+            dist, cnt, flags = self._outputs(nq, out, "Index.query_multi")
+        rc = native.load().spc_query_batch_multi(self.handle, None if g_t is None else g_t.data_ptr(),
+                                                 s_t.data_ptr(), t_t.data_ptr(), nq, dist.data_ptr(),
+                                                 cnt.data_ptr(),
+                                                 flags.data_ptr() if flags is not None else None,
+                                                 _stream_handle(strm))
+        _check(rc, "spc_query_batch_multi")
+        self._keep = (s_t, t_t, g_t)
+        return dist[:nq], cnt[:nq], (flags[:nq] if flags is not None else None)
+
+    def tune_query_buckets(self, graph_ids, s, t, stream=None) -> int:
+        """Autotune the bucket threshold of query_multi on sample queries;
+        returns the threshold kept (0 = no bucketing)."""
+        torch = _torch()
+        s_t = _dev(s, np.uint32, torch.int32, self.device)
+        t_t = _dev(t, np.uint32, torch.int32, self.device)
+        g_t = None if graph_ids is None else _dev(graph_ids, np.uint32, torch.int32, self.device)
+        out = C.c_uint32()
+        _check(native.load().spc_tune_query_buckets(self.handle, None if g_t is None else g_t.data_ptr(),
+                                                    s_t.data_ptr(), t_t.data_ptr(), int(s_t.shape[0]),
+                                                    _stream_handle(stream), C.byref(out)),
+               "spc_tune_query_buckets")
+        return out.value
+
+    def set_query_buckets(self, small: int):
+        _check(native.load().spc_set_query_buckets(self.handle, int(small)), "spc_set_query_buckets")
 
     def tune_queries(self, s, t, graph_id: int = 0, stream=None) -> int:
         """Autotune the query launch configuration on the sample pairs (s, t):
@@ -235,7 +295,8 @@ class Index:
                                              hub.ctypes.data, dist.ctypes.data, cnt.ctypes.data,
                                              order.ctypes.data, 0, _stream_handle(None))
         _check(rc, "spc_export_labels")
-        return dict(off=off, hub=hub[:e], dist=dist[:e], count=cnt[:e], order=order[:n])
+        nv = n // 2 if self.stats()["directed"] else n  # a directed index has 2n label rows
+        return dict(off=off, hub=hub[:e], dist=dist[:e], count=cnt[:e], order=order[:nv])
 
     def export_reduction(self, graph_id: int = 0):
         """The 1-shell of one graph (host numpy, input vertex ids): root
@@ -282,13 +343,14 @@ class Index:
 
 
 def build_index(off, adj, order=None, tie_key=None, opts: BuildOptions | None = None,
-                device=None, stream=None) -> Index:
+                device=None, stream=None, directed: bool = False) -> Index:
     """Build the SPC label index of one graph (symmetric CSR off/adj, numpy or
-    torch).  Inputs are placed in device memory first."""
+    torch; with directed=True, each arc once in its tail's row).  Inputs are
+    placed in device memory first."""
     torch = _torch()
     device = device or torch.device("cuda", torch.cuda.current_device())
     keep = []
-    g = _graph_struct(off, adj, order, tie_key, device, keep)
+    g = _graph_struct(off, adj, order, tie_key, device, keep, directed=directed)
     o = (opts or BuildOptions()).struct()
     h = C.c_void_p()
     rc = native.load().spc_build_index(C.byref(g), C.byref(o), _stream_handle(stream), C.byref(h))

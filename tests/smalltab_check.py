@@ -6,6 +6,7 @@ first mismatch.  Small graphs here take the paths that only large labels
 take in the default build: unstaged label parts searched in HBM or in the
 chunk's LDS window, chunk overflow and narrowing, many chunks per puller."""
 import sys
+import time
 
 import numpy as np
 
@@ -25,7 +26,11 @@ def main():
                                 name="path300")]
     for g in graphs:
         print(f"[case] small tables: {g.name} n={g.n} m={g.m}", flush=True)
+        t0 = time.perf_counter()
         ix = spc.build_graph(g)
+        st = ix.stats()
+        print(f"[case]   build {1e3 * (time.perf_counter() - t0):.0f} ms, "
+              f"{st['round_kernel_launches']} round-kernel launches", flush=True)
         ref = oracle.build_graph(g, method="pull")
         assert_labels_equal(ix.export(), ref, g.name)
         rs = ix.round_stats()

@@ -20,5 +20,6 @@ def test_help_lists_workloads_and_options():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True,
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 0
-    for w in ("chunglu", "rmat_batch", "rmat_served", "grid", "--propagation", "--one-shell", "--equivalence"):
+    for w in ("rmat21", "chunglu", "rmat_batch", "rmat_served", "grid", "--propagation", "--one-shell",
+              "--equivalence", "--no-side"):
         assert w in r.stdout, w

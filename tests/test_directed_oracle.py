@@ -81,3 +81,48 @@ def test_symmetric_digraph_is_the_undirected_index():
                     zip(ref.hub[ref.off[r]:ref.off[r + 1]], ref.dist[ref.off[r]:ref.off[r + 1]],
                         ref.count[ref.off[r]:ref.off[r + 1]])}
             assert lab.out[v] == want and lab.inn[v] == want, v
+
+
+def _arcs_csr(n, arcs):
+    arcs = sorted(set((int(a), int(b)) for a, b in arcs if a != b))
+    off = np.zeros(n + 1, dtype=np.uint64)
+    for a, _ in arcs:
+        off[a + 1] += 1
+    off = np.cumsum(off).astype(np.uint64)
+    adj = np.array([b for _, b in arcs], dtype=np.uint32)
+    return off, adj
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_c_directed_definition_equals_python(seed):
+    """The C builder (rows: L_out then L_in, rank space) holds exactly the
+    Python definition's entries."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(5, 45))
+    m = int(rng.integers(n, 5 * n))
+    arcs = [(int(a), int(b)) for a, b in rng.integers(0, n, (m, 2)) if a != b]
+    off, adj = _arcs_csr(n, arcs)
+    order = oracle.directed_order(n, off, adj)
+    py = oracle.directed_labels(n, arcs, order=order)
+    C = oracle.build_directed(n, off, adj, order=order)
+    for r in range(n):
+        v = int(order[r])
+        for side, lab in ((0, py.out), (1, py.inn)):
+            row = side * n + r
+            got = {int(order[C.hub[i]]): (int(C.dist[i]), int(C.count[i]))
+                   for i in range(int(C.off[row]), int(C.off[row + 1]))}
+            assert got == lab[v], (seed, side, v)
+
+
+def test_c_directed_symmetric_is_undirected_index():
+    g = inputs.erdos_renyi(120, 360, seed=5)
+    off, adj = g.off, g.adj   # both directions of every edge
+    order = oracle.degree_order(g.off)
+    U = oracle.build_graph(g, method="definition")
+    D = oracle.build_directed(g.n, off, adj, order=order)
+    n = g.n
+    for side in (0, 1):
+        a, b = int(D.off[side * n]), int(D.off[side * n + n])
+        assert np.array_equal(D.off[side * n: side * n + n + 1] - D.off[side * n], U.off)
+        assert np.array_equal(D.hub[a:b], U.hub) and np.array_equal(D.dist[a:b], U.dist)
+        assert np.array_equal(D.count[a:b], U.count)
