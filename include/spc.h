@@ -230,6 +230,24 @@ spc_status spc_query_batch_multi(const spc_index *ix, const uint32_t *graph_ids,
                                  const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
                                  uint8_t *flags_out, void *stream);
 
+/* spc_query_batch_multi for callers that cannot allocate device memory
+ * while they run: work captured into a HIP graph, tight serving loops, and
+ * runtimes that forbid allocation inside a request.  Same arguments and
+ * answers; no hipMalloc, no stream-ordered allocation, no allocating library
+ * call: the bucketing scratch (4 bytes per query and two counters) is a
+ * fixed device array of the library, 16 MiB + 256 B on every GPU the library
+ * runs on, held until the process ends.  Limit: nq <= 2^22 queries per call
+ * (SPC_ERR_UNSUPPORTED beyond, before any launch).  Every call on one GPU
+ * uses that GPU's single array, whose counters a kernel clears at the start
+ * of each call: calls that overlap on one GPU (several streams, several host
+ * threads) race and must be serialised by the caller, e.g. on one stream.
+ * The first call on a device looks the array's address up with the index's
+ * device current (SPC_ERR_DEVICE if the runtime refuses). */
+spc_status spc_query_batch_multi_noalloc(const spc_index *ix, const uint32_t *graph_ids,
+                                         const uint32_t *s, const uint32_t *t, uint64_t nq,
+                                         void *dist_out, uint64_t *count_out, uint8_t *flags_out,
+                                         void *stream);
+
 /* Bucketing of spc_query_batch_multi: queries with |L(s)| + |L(t)| at most
  * `small` take the 16-lanes-per-query path; 0 turns bucketing off (every
  * query a wave).  A new index starts at 256.  The tuner times the

@@ -63,6 +63,14 @@ spc_status spc_query_batch_multi(const spc_index *ix, const uint32_t *graph_ids,
                                  static_cast<hipStream_t>(stream));
 }
 
+spc_status spc_query_batch_multi_noalloc(const spc_index *ix, const uint32_t *graph_ids,
+                                         const uint32_t *s, const uint32_t *t, uint64_t nq,
+                                         void *dist_out, uint64_t *count_out, uint8_t *flags_out,
+                                         void *stream) {
+    return spc::query_multi_noalloc_impl(ix, graph_ids, s, t, nq, dist_out, count_out, flags_out,
+                                         static_cast<hipStream_t>(stream));
+}
+
 spc_status spc_tune_query_buckets(spc_index *ix, const uint32_t *graph_ids, const uint32_t *s,
                                   const uint32_t *t, uint64_t nq, void *stream, uint32_t *small_out) {
     return spc::tune_query_buckets_impl(ix, graph_ids, s, t, nq, static_cast<hipStream_t>(stream),

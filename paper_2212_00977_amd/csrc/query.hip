@@ -19,10 +19,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include <type_traits>
 
 #include "spc_internal.h"
+
+// Scratch of spc_query_batch_multi_noalloc: the bucket permutation of at
+// most kNoAllocQueries queries, then the two bucket counters.  One copy per
+// GPU, resident while the library is loaded.  Host code reaches it only
+// through the address hipGetSymbolAddress returns for the device.
+constexpr uint64_t kNoAllocQueries = 1ull << 22;
+static __device__ __align__(256) uint32_t scratch[kNoAllocQueries + 64];
 
 namespace spc {
 
@@ -812,6 +820,46 @@ spc_status export_reduction_impl(const spc_index *ix, uint32_t graph_id, uint32_
     }
     SPC_HIP(hipStreamSynchronize(st));
     return SPC_OK;
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch[kMaxDevices];  // device address of `scratch`, per device
+
+// The device address of `scratch` on device `dev`, looked up once per
+// device with that device current.
+spc_status scratch_on(int dev, uint32_t **out) {
+    if (dev < 0 || dev >= kMaxDevices) return SPC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int cur = 0;
+        SPC_HIP(hipGetDevice(&cur));
+        if (cur != dev) SPC_HIP(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) SPC_HIP(hipSetDevice(cur));
+        if (e != hipSuccess || !p) return SPC_ERR_DEVICE;
+        g_scratch[dev] = static_cast<uint32_t *>(p);
+    }
+    *out = g_scratch[dev];
+    return SPC_OK;
+}
+}  // namespace
+
+spc_status query_multi_noalloc_impl(const spc_index *ix, const uint32_t *gid, const uint32_t *s,
+                                    const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                                    uint8_t *flags_out, hipStream_t st) {
+    if (!ix) return SPC_ERR_INVALID_ARG;
+    if (nq == 0) return SPC_OK;
+    if (!s || !t || !dist_out || !count_out) return SPC_ERR_INVALID_ARG;
+    if (nq > kNoAllocQueries) return SPC_ERR_UNSUPPORTED;
+    uint32_t *p = nullptr;
+    SPC_TRY(scratch_on(ix->device, &p));
+    // perm = p[0 .. nq), counters at p[kNoAllocQueries]: cleared by a kernel
+    // at the start of the call (query_multi_run)
+    return query_multi_run(ix, gid, s, t, nq, dist_out, count_out, flags_out, p, p + kNoAllocQueries,
+                           ix->query_small, ix->query_cfg, st);
 }
 
 }  // namespace spc

@@ -408,6 +408,9 @@ spc_status query_multi_run(const spc_index *ix, const uint32_t *gid, const uint3
                            uint32_t cfg, hipStream_t st);
 spc_status tune_query_buckets_impl(spc_index *ix, const uint32_t *gid, const uint32_t *s,
                                    const uint32_t *t, uint64_t nq, hipStream_t st, uint32_t *small_out);
+spc_status query_multi_noalloc_impl(const spc_index *ix, const uint32_t *gid, const uint32_t *s,
+                                    const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
+                                    uint8_t *flags_out, hipStream_t st);
 spc_status query_multi_impl(const spc_index *ix, const uint32_t *gid, const uint32_t *s,
                             const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
                             uint8_t *flags_out, hipStream_t st);

@@ -25,7 +25,7 @@ EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_f
            "spc_status_string", "spc_release_cached_memory", "spc_query_config_count",
            "spc_query_config_info", "spc_tune_queries", "spc_set_query_config", "spc_hybrid_order",
            "spc_export_reduction", "spc_query_batch_multi", "spc_tune_query_buckets",
-           "spc_set_query_buckets"]
+           "spc_set_query_buckets", "spc_query_batch_multi_noalloc"]
 
 
 # A test build with tiny on-chip tables (8-bit hash of 128 slots for the
@@ -128,6 +128,8 @@ def load(path: str | None = None):
     L.spc_export_reduction.restype = C.c_int
     L.spc_query_batch_multi.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
     L.spc_query_batch_multi.restype = C.c_int
+    L.spc_query_batch_multi_noalloc.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
+    L.spc_query_batch_multi_noalloc.restype = C.c_int
     L.spc_tune_query_buckets.argtypes = [vp, vp, vp, vp, u64, vp, C.POINTER(u32)]
     L.spc_tune_query_buckets.restype = C.c_int
     L.spc_set_query_buckets.argtypes = [vp, u32]
