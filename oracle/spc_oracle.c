@@ -740,6 +740,8 @@ struct pull_round { /* shared by the workers of one round */
     int phase;         /* 1: pull; 2: gather + insert */
 };
 
+static int g_progress;
+
 static void *pull_worker_run(void *arg)
 {
     pull_worker *me = arg;
@@ -747,6 +749,10 @@ static void *pull_worker_run(void *arg)
     for (;;) {
         uint32_t b = __atomic_fetch_add(&r->next, PULL_BLOCK, __ATOMIC_RELAXED);
         if (b >= r->n) break;
+        if (g_progress && r->phase == 1 && (b & ((1u << 16) - 1)) == 0) {
+            fprintf(stderr, "oracle pull: round %u, puller %u of %u\n", r->d, b, r->n);
+            fflush(stderr);
+        }
         uint32_t e = (r->n - b < PULL_BLOCK) ? r->n : b + PULL_BLOCK;
         for (uint32_t u = b; u < e; u++) {
             if (r->phase == 1) {
@@ -786,7 +792,7 @@ static void pull_phase(pull_round *r, uint32_t nthreads, int phase)
     free(th);
 }
 
-static int g_progress = 0; /* nonzero: one line per PULL round on stderr */
+/* nonzero: progress lines on stderr (per round, and every 2^16 pullers) */
 void oracle_set_progress(int on) { g_progress = on; }
 
 oracle_index *oracle_build_pull_threads(uint32_t n, const uint64_t *off, const uint32_t *adj,

@@ -57,7 +57,8 @@ oracle_index *oracle_build_pull(uint32_t n, const uint64_t *off, const uint32_t 
                                 uint32_t depth_cap);
 /* oracle_build_pull with the pullers of each round spread over nthreads
  * threads (0 or 1: the calling thread).  Same index and counters. */
-/* Nonzero: the PULL builders print one line per round on stderr. */
+/* Nonzero: the PULL builders print progress lines on stderr (one per round,
+ * and one every 2^16 pullers within a round). */
 void oracle_set_progress(int on);
 oracle_index *oracle_build_pull_threads(uint32_t n, const uint64_t *off, const uint32_t *adj,
                                         uint32_t depth_cap, uint32_t nthreads);
