@@ -282,27 +282,29 @@ __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
 // The fused round kernel.  One workgroup per puller u (largest rank ids
 // first: they have the most candidates).
 //   1. stage u's landmark row (registers + LDS) and the rest of L_{<d}(u)
-//      (hub -> dist, hubs past the landmarks) in an LDS hash table; if that
-//      part is longer than the table allows, its tail (largest hubs) is
-//      searched in HBM by binary search instead;
+//      (hub -> dist, hubs past the landmarks) in an LDS hash table; a part
+//      longer than the table allows is staged chunk by chunk instead (the
+//      entries with hubs in the chunk's range, which is capped to fit);
 //   2. walk the hub range [0, u) in chunks: pull every neighbour's round d-1
 //      entries with hub in the chunk, drop hubs u already holds (Label
 //      Elimination: they hold a smaller distance) and merge equal hubs in an
 //      LDS hash by summing counts (Label Merging, saturating).  A chunk whose
 //      distinct hubs overflow the table is retried with half the width;
-//   3. sort the chunk's merged candidates by hub (bitonic, LDS);
-//   4. prune each candidate w with the 2-hop query over entries of distance
-//      < d (Eq. PSPCdu), one wave per candidate: first through the landmark
-//      rows of u and w; if no landmark proves a shorter path and w is not a
-//      landmark itself, through w's other entries of rounds 1..d-2 (only an
-//      entry with d_w <= d-2 can prove anything, since h != u forces
-//      d_u >= 1), read round by round from the round pool and looked up in
-//      u's table.  A hub with d_u(h) + d_w(h) < d prunes; equality keeps;
-//   5. append the survivors, in hub order, to u's slot of the temp buffer.
+//   3. prune each merged candidate w with the 2-hop query over entries of
+//      distance < d (Eq. PSPCdu), 16 lanes per candidate: first through the
+//      landmark rows of u and w; if no landmark proves a shorter path and w
+//      is not a landmark itself, through the two labels' other entries of
+//      distance <= d-2 (only those can prove anything, since a common hub
+//      h != u, w forces d_u, d_w >= 1) with hubs ranked above w, from the
+//      previous round's merged labels.  A hub with d_u(h) + d_w(h) < d
+//      prunes; equality keeps;
+//   4. sort the survivors by hub (bitonic, LDS);
+//   5. append them to u's slot of the temp buffer.
 // ---------------------------------------------------------------------------
 // LDS budget of the round kernel (about 40 KB with the defaults: four
-// workgroups per CU).  u's L_{<=d-2} part is read from HBM by the probes
-// that stream u's side (staging it too measured slower).
+// workgroups per CU).  u's L_{<=d-2} part is staged for the probes in the
+// candidate table's count array, which is idle between a chunk's merge and
+// its sort, so it costs no occupancy.
 #ifndef SPC_LBITS
 #define SPC_LBITS 12
 #endif
@@ -327,6 +329,23 @@ static_assert((1 << (SPC_CBITS - 1)) >= SPC_ROUND_BLOCK, "candidate limit below 
 // merge trips over u's unstaged label per tile of w's entries before the
 // remaining hubs are binary-searched
 constexpr uint32_t kTailSteps = SPC_TAIL_STEPS;
+#ifndef SPC_PROBE_GROUP
+#define SPC_PROBE_GROUP 4
+#endif
+#ifndef SPC_PULL_UNROLL
+#define SPC_PULL_UNROLL 4
+#endif
+#ifndef SPC_LAND_UNROLL
+#define SPC_LAND_UNROLL 2
+#endif
+// pulled entries per thread whose loads are in flight together
+constexpr int kPullUnroll = SPC_PULL_UNROLL;
+// candidates per 16-lane group whose landmark slices are in flight together
+constexpr int kLandUnroll = SPC_LAND_UNROLL;
+// lanes per candidate in the probes past the landmarks (a power of two <= 64)
+constexpr uint32_t kProbeGroup = SPC_PROBE_GROUP;
+static_assert(kProbeGroup >= 2 && kProbeGroup <= 64 && (kProbeGroup & (kProbeGroup - 1)) == 0,
+              "probe group: a power of two from 2 to 64");
 
 struct RoundArgs {
     uint32_t d, u_lo, u_hi;
@@ -440,11 +459,8 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     __shared__ uint32_t lhub[kULimit];
     __shared__ unsigned long long lcnt[kULimit];
     __shared__ uint8_t lkeep[kULimit];   // 0 pruned, 1 kept, 2 needs the tail check
-    // candidates that need the tail check (probe phase); during the pull the
-    // same bytes hold the chunk's slice of u's unstaged label
-    __shared__ __align__(8) uint16_t tlist[kULimit];
-    constexpr uint32_t kWin = kULimit * sizeof(uint16_t) / sizeof(E);
-    E *win = reinterpret_cast<E *>(tlist);
+    // candidates that need the tail check (probe phase)
+    __shared__ uint16_t tlist[kULimit];
     __shared__ uint64_t nb_start[RB];
     __shared__ uint32_t nb_off[RB];
     __shared__ uint32_t red32[RW];
@@ -480,7 +496,17 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     const uint64_t nL = a.lab_off[u + 1] - l0;
     const uint64_t s0 = a.lc_cur[u];
     const uint64_t nsp = nL - s0;
-    const uint32_t nst = nsp < (uint64_t)kLStage ? (uint32_t)nsp : (uint32_t)kLStage;
+    const E *lab = hd + l0 + s0;  // u's label past the landmarks, hub-sorted
+    // a label that fits the table is staged once; a longer one chunk by
+    // chunk, the chunk's hub range capped so that its slice fits
+    const bool big = nsp > (uint64_t)kLStage;
+    auto stage = [&](const E *src, uint32_t cnt) {
+        for (uint32_t i = tid; i < cnt; i += RB) {
+            E e = src[i];
+            uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
+            while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
+        }
+    };
     for (int i = tid; i < kLCap; i += RB) ltab[i] = kEmptyE;
     if (tid == 0) {
         s_tail = 0;
@@ -488,11 +514,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         s_rowb = 0;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < nst; i += RB) {
-        E e = hd[l0 + s0 + i];
-        uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
-        while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
-    }
+    if (!big) stage(lab, (uint32_t)nsp);
     // u's entries of distance <= d-2 past the landmarks, hub-sorted (from
     // the previous round's merged label), for probes that stream u's side
     const E *pu = nullptr;
@@ -503,25 +525,27 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         pu = static_cast<const E *>(a.prev_hd) + q0 + qs;
         npu = a.prev_off[u + 1] - q0 - qs;
     }
-    LabelLookup<DB> look;
-    look.tab = ltab;
-    look.tail = hd + l0 + s0 + nst;
-    look.ntail = nsp - nst;
-    look.x = (nst < nsp) ? e_hub<DB>(hd[l0 + s0 + nst]) : 0xFFFFFFFFu;
+    // the table, which holds the current chunk's hubs of u's label
+    LabelLookup<DB> tabl;
+    tabl.tab = ltab;
+    tabl.tail = lab + nsp;
+    tabl.ntail = 0;
+    tabl.x = 0xFFFFFFFFu;
+    // u's whole label past the landmarks for the probes: the table when
+    // staged once, else HBM
+    LabelLookup<DB> look = tabl;
+    if (big) {
+        look.tail = lab;
+        look.ntail = nsp;
+        look.x = 0;
+    }
     __syncthreads();
     const LT *lrow_t = reinterpret_cast<const LT *>(lrow);
     // is hub w of the current chunk already held by u (at a distance < d)?
-    // Hubs past the staged part are searched in the chunk's slice of the
-    // rest of u's label: [wbase, wbase + wlen) of look.tail, copied to the
-    // LDS window when it fits
-    uint64_t tcur = 0, tend = 0, wbase = 0, wlen = 0;
-    bool inwin = false;
+    uint64_t tcur = 0, tend = 0;  // u's slice of the chunk in lab (big labels)
     auto held = [&](uint32_t w) -> bool {
         if (w < land_end) return lrow_t[w - base] != kInfL;
-        if (w < look.x) return look(w) != kNone;
-        const E *t = inwin ? win : look.tail + wbase;
-        const uint64_t p = lower_bound_hub<DB>(t, wlen, w);
-        return p < wlen && e_hub<DB>(t[p]) == w;
+        return tabl(w) != kNone;
     };
     // this lane's 16 landmarks of u, and whether any of them is within d-2
     // (a landmark farther from u cannot prove d_u + d_w < d since d_w >= 1)
@@ -565,11 +589,18 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         // A. size the chunk.  With cursors in registers the exact pull count
         //    of [lo, hi) is cheap: the range is narrowed or widened once so
         //    that the expected distinct count fits.  Wider pullers take the
-        //    width learned from the previous chunk.
-        uint32_t hi = (width >= ur - lo) ? ur : lo + width, tot = 0;
+        //    width learned from the previous chunk.  A label staged chunk by
+        //    chunk caps the range at the hub of its entry kLStage past the
+        //    cursor (which is above lo).
+        uint32_t hend = ur;
+        if (big && tcur + kLStage < nsp) {
+            const uint32_t hc = e_hub<DB>(lab[tcur + kLStage]);
+            hend = hc < ur ? hc : ur;
+        }
+        uint32_t hi = (width >= hend - lo) ? hend : lo + width, tot = 0;
         if (one_group) {
             for (int it = 0;; it++) {
-                hi = (width >= ur - lo) ? ur : lo + width;
+                hi = (width >= hend - lo) ? hend : lo + width;
                 uint32_t t = 0;
                 if (tid < deg) {
                     // hubs of v's segment are <= v
@@ -585,11 +616,11 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                     width = w2 ? w2 : 1;
                     continue;
                 }
-                if (may_widen && expect < 0.5f * kTarget && hi < ur) {
+                if (may_widen && expect < 0.5f * kTarget && hi < hend) {
                     float f = expect > 1.0f ? (float)kTarget / expect : 8.0f;
                     f = f > 8.0f ? 8.0f : f;
                     uint64_t w2 = (uint64_t)((double)(hi - lo) * f);
-                    width = w2 >= (uint64_t)(ur - lo) ? ur - lo : (uint32_t)w2;
+                    width = w2 >= (uint64_t)(hend - lo) ? hend - lo : (uint32_t)w2;
                     continue;
                 }
                 break;
@@ -602,19 +633,25 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
             cval[i] = 0;
             cwrap[i] = 0;
         }
-        // u's unstaged entries with hubs in [lo, hi): from the tail cursor
-        // (first entry with hub >= lo) to the first with hub >= hi
-        wbase = tcur;
-        wlen = 0;
-        inwin = false;
-        tend = tcur;
-        if (look.ntail > tcur && hi > look.x) {
-            tend = tcur + gallop_hub<DB>(look.tail + tcur, look.ntail - tcur, hi);
-            wlen = tend - tcur;
-            if (wlen <= kWin) {
-                for (uint32_t i = tid; i < (uint32_t)wlen; i += RB) win[i] = look.tail[tcur + i];
-                inwin = true;
+        // a long label: stage its entries with hubs in [lo, hi), from the
+        // cursor (first entry with hub >= lo), RB per trip
+        if (big) {
+            for (int i = tid; i < kLCap; i += RB) ltab[i] = kEmptyE;
+            __syncthreads();
+            uint64_t b = tcur;
+            while (true) {
+                const uint64_t j = b + tid;
+                const E e = j < nsp ? lab[j] : (E)0;
+                const bool in = j < nsp && e_hub<DB>(e) < hi;  // a prefix of the trip
+                if (in) {
+                    uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
+                    while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
+                }
+                const uint32_t cnt = (uint32_t)__syncthreads_count(in);
+                b += cnt;
+                if (cnt < (uint32_t)RB) break;
             }
+            tend = b;
         }
         if (tid == 0) {
             s_nuniq = 0;
@@ -646,47 +683,64 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
             nb_off[tid] = ex;
             __syncthreads();
             uint32_t jl = 0;  // owner of k: last j with nb_off[j] <= k (monotone in k)
-            for (uint32_t k = tid; k < gt; k += RB) {
+            // kPullUnroll pulled entries per thread and trip: their loads are
+            // issued together, then each is eliminated or merged
+            for (uint32_t k0 = tid; k0 < gt; k0 += kPullUnroll * RB) {
                 if (*(volatile uint32_t *)&s_ovf) break;
-                if (jl + 1 < (uint32_t)RB && nb_off[jl + 1] <= k) {
-                    uint32_t lo2 = jl + 1, hi2 = RB - 1;
-                    while (lo2 < hi2) {
-                        uint32_t mid = (lo2 + hi2 + 1) >> 1;
-                        if (nb_off[mid] <= k)
-                            lo2 = mid;
-                        else
-                            hi2 = mid - 1;
+                uint32_t wq[kPullUnroll];
+                uint64_t cq[kPullUnroll];
+#pragma unroll
+                for (int r = 0; r < kPullUnroll; r++) {
+                    const uint32_t k = k0 + r * RB;
+                    wq[r] = kEmpty32;  // no hub: past the chunk's pulls
+                    cq[r] = 0;
+                    if (k < gt) {
+                        if (jl + 1 < (uint32_t)RB && nb_off[jl + 1] <= k) {
+                            uint32_t lo2 = jl + 1, hi2 = RB - 1;
+                            while (lo2 < hi2) {
+                                uint32_t mid = (lo2 + hi2 + 1) >> 1;
+                                if (nb_off[mid] <= k)
+                                    lo2 = mid;
+                                else
+                                    hi2 = mid - 1;
+                            }
+                            jl = lo2;
+                        }
+                        const uint64_t idx = nb_start[jl] + (k - nb_off[jl]);
+                        wq[r] = a.pool_hub[idx];
+                        cq[r] = a.pool_cnt[idx];
+                        if constexpr (W) cq[r] = sat_mul(cq[r], (uint64_t)a.adj_w[g0 + nb0 + jl]);
                     }
-                    jl = lo2;
                 }
-                uint64_t idx = nb_start[jl] + (k - nb_off[jl]);
-                uint32_t w = a.pool_hub[idx];
-                uint64_t c = a.pool_cnt[idx];
-                if constexpr (W) c = sat_mul(c, (uint64_t)a.adj_w[g0 + nb0 + jl]);
-                if (held(w)) continue;  // Label Elimination
-                uint32_t s = hash_slot(w, kCBits);
-                bool ok = true;
-                for (uint32_t probes = 0;; probes++) {
-                    uint32_t kk = ckey[s];
-                    if (kk == w) break;
-                    if (kk == kEmpty32) {
-                        uint32_t old = atomicCAS(&ckey[s], kEmpty32, w);
-                        if (old == kEmpty32) {
-                            if (atomicAdd(&s_nuniq, 1u) + 1 > (uint32_t)kULimit) s_ovf = 1;
+#pragma unroll
+                for (int r = 0; r < kPullUnroll; r++) {
+                    const uint32_t w = wq[r];
+                    const uint64_t c = cq[r];
+                    if (w == kEmpty32 || held(w)) continue;  // Label Elimination
+                    uint32_t s = hash_slot(w, kCBits);
+                    bool ok = true;
+                    for (uint32_t probes = 0;; probes++) {
+                        uint32_t kk = ckey[s];
+                        if (kk == w) break;
+                        if (kk == kEmpty32) {
+                            uint32_t old = atomicCAS(&ckey[s], kEmpty32, w);
+                            if (old == kEmpty32) {
+                                if (atomicAdd(&s_nuniq, 1u) + 1 > (uint32_t)kULimit) s_ovf = 1;
+                                break;
+                            }
+                            if (old == w) break;
+                        }
+                        s = (s + 1) & (kCCap - 1);
+                        if (probes + 1 >= (uint32_t)kCCap) {
+                            s_ovf = 1;
+                            ok = false;
                             break;
                         }
-                        if (old == w) break;
                     }
-                    s = (s + 1) & (kCCap - 1);
-                    if (probes + 1 >= (uint32_t)kCCap) {
-                        s_ovf = 1;
-                        ok = false;
-                        break;
+                    if (ok) {  // Label Merging: saturating sum, wrap recorded
+                        unsigned long long old = atomicAdd(&cval[s], (unsigned long long)c);
+                        if (old + c < old) cwrap[s] = 1;
                     }
-                }
-                if (ok) {  // Label Merging: saturating sum, wrap recorded
-                    unsigned long long old = atomicAdd(&cval[s], (unsigned long long)c);
-                    if (old + c < old) cwrap[s] = 1;
                 }
             }
             __syncthreads();
@@ -736,31 +790,52 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         //      reading w's slice only if u has a landmark within d-2 there.
         uint64_t my_tail = 0, my_hdr = 0, my_rowb = 0;
         if (d >= 3) {
-            for (uint32_t i0 = wv * 4; i0 < M; i0 += RB / 16) {
-                const uint32_t i = i0 + grp;
-                bool hit = false;
-                uint32_t wl = 0, loads = 0;
-                if (i < M) {
-                    wl = lhub[i] - base;
-                    if (slice_useful && 16 * gl <= wl) {  // landmarks above w are not its hubs
+            // kLandUnroll candidates per group and trip, their row slices
+            // loaded together
+            for (uint32_t i0 = wv * 4; i0 < M; i0 += kLandUnroll * (RB / 16)) {
+                LW rv[kLandUnroll][4];
+                uint32_t wl[kLandUnroll];
+                bool rd[kLandUnroll];
+#pragma unroll
+                for (int r = 0; r < kLandUnroll; r++) {
+                    const uint32_t i = i0 + r * (RB / 16) + grp;
+                    wl[r] = i < M ? lhub[i] - base : 0;
+                    rd[r] = i < M && slice_useful && 16 * gl <= wl[r];  // landmarks above w are not its hubs
+                    if (rd[r]) {
                         const LW *rw = lands + (uint64_t)(lhub[i] + poff) * (kLand / 4) + 4 * gl;
 #pragma unroll
-                        for (int q = 0; q < 4; q++) hit |= land_hit(uw[q], rw[q], d);
-                        loads = 1;
+                        for (int q = 0; q < 4; q++) rv[r][q] = rw[q];
                     }
                 }
-                const uint64_t m = __ballot(hit);
-                const bool ghit = ((m >> (16 * grp)) & 0xFFFFull) != 0;
 #pragma unroll
-                for (int o = 8; o > 0; o >>= 1) loads += __shfl_xor(loads, o, 16);
-                if (i < M && gl == 0) {
-                    lkeep[i] = ghit ? 0 : (wl >= (uint32_t)kLand ? 2 : 1);
-                    my_rowb += (uint64_t)loads * 16 * sizeof(LT);
+                for (int r = 0; r < kLandUnroll; r++) {
+                    const uint32_t i = i0 + r * (RB / 16) + grp;
+                    bool hit = false;
+                    if (rd[r]) {
+#pragma unroll
+                        for (int q = 0; q < 4; q++) hit |= land_hit(uw[q], rv[r][q], d);
+                    }
+                    const bool ghit = ((__ballot(hit) >> (16 * grp)) & 0xFFFFull) != 0;
+                    uint32_t loads = rd[r] ? 1 : 0;
+#pragma unroll
+                    for (int o = 8; o > 0; o >>= 1) loads += __shfl_xor(loads, o, 16);
+                    if (i < M && gl == 0) {
+                        lkeep[i] = ghit ? 0 : (wl[r] >= (uint32_t)kLand ? 2 : 1);
+                        my_rowb += (uint64_t)loads * 16 * sizeof(LT);
+                    }
                 }
             }
         } else {
             for (uint32_t i = tid; i < M; i += RB) lkeep[i] = 1;
         }
+        // u's entries of distance <= d-2 past the landmarks go to the
+        // candidate table's count array (idle until the next chunk) when they
+        // fit, for the probes below
+        E *pl = reinterpret_cast<E *>(cval);
+        constexpr uint64_t kPuCap = (uint64_t)kCCap * sizeof(unsigned long long) / sizeof(E);
+        const bool pstaged = d >= 3 && npu <= kPuCap;
+        if (pstaged)
+            for (uint32_t j = tid; j < (uint32_t)npu; j += RB) pl[j] = pu[j];
         __syncthreads();
         //  4b. the other hubs of the surviving non-landmark candidates: their
         //      entries of distance <= d-2 past the landmarks on both sides
@@ -776,6 +851,11 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
             for (int q = 0; q < PER; q++) {
                 uint32_t i = PER * tid + q;
                 f[q] = (i < M && lkeep[i] == 2) ? 1 : 0;
+                // a common hub ranks above w: none of u's hubs below w, no probe
+                if (f[q] && pstaged && (npu == 0 || e_hub<DB>(pl[0]) >= lhub[i])) {
+                    lkeep[i] = 1;
+                    f[q] = 0;
+                }
                 nf += f[q];
             }
             if (tid == 0) s_next = 0;
@@ -789,7 +869,118 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         // groups take them from a shared counter: a group that finishes one
         // takes the next, one 16-entry step per trip, and no group waits for
         // a slow one of another wave.
-        if (T > 0) {
+        if (T > 0 && pstaged) {
+            // u's side is pl[0, cu), its hubs below w, in LDS.  Groups of PG
+            // lanes take one candidate each and either
+            //  B. binary-search u's cu hubs in w's entries, PG at a time, or
+            //  A. stream w's entries, 4 PG per trip (each PG-lane load
+            //     contiguous), looking each hub up in u's table, until a hit
+            //     or a hub past u's last one below w,
+            // whichever reads fewer entries; the last levels of a binary
+            // search stay within one cache line.  The next candidate's label
+            // offsets are loaded one trip ahead, with the current entries.
+            constexpr uint32_t PG = kProbeGroup;
+            constexpr uint64_t kPGMask = PG == 64 ? ~0ull : ((1ull << PG) - 1);
+            const uint32_t pgi = lane / PG, pgl = lane % PG;
+            bool have = false, nhave = false, useu = false;
+            uint32_t i = 0, ni = 0, it = 0, nit = 0, cu = 0, hmax = 0, nlc = 0;
+            uint64_t nq0 = 0, nq1 = 0, np = 0, p0 = 0, nw = 0, read = 0, wt = 1;
+            const E *pw = nullptr;
+            auto grab = [&]() {  // called by whole groups
+                uint32_t got = 0;
+                if (pgl == 0) got = atomicAdd(&s_next, 1u);
+                got = (uint32_t)__shfl((int)got, (int)(pgi * PG), 64);
+                nhave = got < T;
+                if (nhave) {
+                    ni = tlist[got];
+                    const uint32_t wr = lhub[ni] + poff;
+                    nq0 = a.prev_off[wr];
+                    nq1 = a.prev_off[wr + 1];
+                    nlc = a.lc_prev[wr];
+                }
+            };
+            // u's distance to hub h <= hmax of w's label (kNone: not held
+            // within d-2 past the landmarks)
+            auto du_of = [&](uint32_t h) -> uint32_t {
+                if (h < look.x) return look(h);
+                const uint32_t p = (uint32_t)lower_bound_hub<DB>(pl, cu, h);
+                return (p < cu && e_hub<DB>(pl[p]) == h) ? e_dist<DB>(pl[p]) : kNone;
+            };
+            grab();
+            while (true) {
+                if (!have && nhave) {  // uniform within the group
+                    i = ni;
+                    const uint32_t w = lhub[i];
+                    pw = static_cast<const E *>(a.prev_hd) + nq0;
+                    np = nq1 - nq0 - 1;  // the last entry is (w, 0)
+                    p0 = nlc;
+                    nw = np - p0;
+                    grab();
+                    cu = (uint32_t)lower_bound_hub<DB>(pl, npu, w);  // >= 1
+                    hmax = e_hub<DB>(pl[cu - 1]);
+                    uint32_t steps = 1;
+                    while ((1ull << steps) <= nw) steps++;
+                    useu = (uint64_t)cu * steps < nw;
+                    nit = useu ? (cu + PG - 1) / PG : (uint32_t)((nw + 4 * PG - 1) / (4 * PG));
+                    wt = useu ? steps : 1;
+                    it = 0;
+                    read = 0;
+                    have = nit > 0;
+                    if (!have && pgl == 0) {  // w holds nothing past its landmarks: kept
+                        lkeep[i] = 1;
+                        my_hdr++;
+                    }
+                }
+                if (__ballot(have || nhave) == 0) break;
+                bool h2 = false, past = false;
+                if (have) {
+                    if (useu) {
+                        const uint32_t j = it * PG + pgl;
+                        if (j < cu) {
+                            const E e = pl[j];
+                            const uint32_t h = e_hub<DB>(e);
+                            const uint64_t q = p0 + lower_bound_hub<DB>(pw + p0, nw, h);
+                            h2 = q < np && e_hub<DB>(pw[q]) == h && e_dist<DB>(e) + e_dist<DB>(pw[q]) < d;
+                        }
+                    } else {
+                        const uint64_t j0 = (uint64_t)it * (4 * PG) + pgl;
+                        E ev[4];
+                        bool ok[4];
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            ok[k] = j0 + PG * k < nw;
+                            ev[k] = ok[k] ? pw[p0 + j0 + PG * k] : (E)0;
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            if (!ok[k]) continue;
+                            const uint32_t h = e_hub<DB>(ev[k]);
+                            if (h > hmax) {
+                                past = true;  // and every later entry of w
+                                continue;
+                            }
+                            const uint32_t du = du_of(h);
+                            h2 |= du != kNone && du + e_dist<DB>(ev[k]) < d;
+                        }
+                    }
+                }
+                const bool ghit = ((__ballot(h2) >> (PG * pgi)) & kPGMask) != 0;
+                const bool gpast = ((__ballot(past) >> (PG * pgi)) & kPGMask) != 0;
+                if (have) {
+                    const uint64_t tile = useu ? PG : 4 * PG, lenx = useu ? cu : nw;
+                    const uint64_t done = (uint64_t)it * tile;
+                    read += (lenx - done < tile ? lenx - done : tile) * wt;
+                    if (ghit || gpast || ++it >= nit) {
+                        if (pgl == 0) {
+                            lkeep[i] = ghit ? 0 : 1;
+                            my_tail += read;
+                            my_hdr++;
+                        }
+                        have = false;
+                    }
+                }
+            }
+        } else if (T > 0) {
             bool have = false, retired = false;
             uint32_t i = 0, it = 0, nit = 0;
             uint64_t np = 0, p0 = 0, nw = 0, len = 0, read = 0, wt = 1;
@@ -968,7 +1159,13 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                 }
             }
         }
-        if (gl == 0) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            my_tail += __shfl_xor(my_tail, o, 64);
+            my_hdr += __shfl_xor(my_hdr, o, 64);
+            my_rowb += __shfl_xor(my_rowb, o, 64);
+        }
+        if (lane == 0) {
             atomicAdd(&s_tail, (unsigned long long)my_tail);
             atomicAdd(&s_hdr, (unsigned long long)my_hdr);
             atomicAdd(&s_rowb, (unsigned long long)my_rowb);
