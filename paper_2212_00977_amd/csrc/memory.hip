@@ -1,5 +1,6 @@
-// Per-device cache of device memory blocks, and growable arrays on the
-// virtual memory API.
+// Per-device cache of device memory: a pool of physical pieces behind large
+// blocks and growable arrays (virtual memory API), and hipMalloc blocks kept
+// by size for the small ones.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,33 +14,176 @@ namespace spc {
 
 namespace {
 
+using Handle = hipMemGenericAllocationHandle_t;
+
 struct DeviceCache {
-    std::multimap<size_t, void *> free_blocks;  // size -> block
-    size_t bytes = 0;                           // total held
+    std::multimap<size_t, void *> free_blocks;  // size -> hipMalloc block
+    size_t bytes = 0;                           // held in free_blocks
+    std::vector<Handle> pieces;                 // free pieces of kPoolPiece bytes
 };
 
-std::mutex g_mu;
-std::vector<DeviceCache> g_cache;
-
-DeviceCache &cache_for_current() {
+// a large block: an address range with pooled pieces mapped behind it
+struct Mapped {
+    size_t bytes = 0;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::vector<Handle> pieces;
+};
+
+std::mutex g_mu;  // guards g_cache and g_mapped
+std::vector<DeviceCache> g_cache;
+std::map<void *, Mapped> g_mapped;
+
+int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        dev = 0;
+    }
+    return dev;
+}
+
+DeviceCache &cache_of(int dev) {
     if ((size_t)dev >= g_cache.size()) g_cache.resize((size_t)dev + 1);
     return g_cache[(size_t)dev];
 }
 
-void flush_locked(DeviceCache &c) {
+void release_blocks_locked(DeviceCache &c) {
     for (auto &kv : c.free_blocks) (void)hipFree(kv.second);
     c.free_blocks.clear();
     c.bytes = 0;
 }
 
-}  // namespace
+void release_pieces_locked(DeviceCache &c) {
+    for (Handle h : c.pieces) (void)hipMemRelease(h);
+    c.pieces.clear();
+}
 
-void *cache_alloc(size_t bytes, size_t *got) {
+hipMemAllocationProp device_prop(int dev) {
+    hipMemAllocationProp p{};
+    p.type = hipMemAllocationTypePinned;
+    p.location.type = hipMemLocationTypeDevice;
+    p.location.id = dev;
+    return p;
+}
+
+hipMemAccessDesc device_access(int dev) {
+    hipMemAccessDesc acc{};
+    acc.location = device_prop(dev).location;
+    acc.flags = hipMemAccessFlagsProtReadWrite;
+    return acc;
+}
+
+// a block of n pooled pieces mapped at one address range; nullptr on failure
+void *mapped_alloc(int dev, size_t n) {
+    const size_t bytes = n * kPoolPiece;
+    void *va = nullptr;
+    if (hipMemAddressReserve(&va, bytes, 0, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::vector<Handle> hs;
+    if (!pool_take(dev, n, &hs)) {
+        (void)hipMemAddressFree(va, bytes);
+        return nullptr;
+    }
+    size_t done = 0;
+    bool ok = true;
+    for (; done < n; done++)
+        if (hipMemMap(static_cast<char *>(va) + done * kPoolPiece, kPoolPiece, 0, hs[done], 0) !=
+            hipSuccess) {
+            ok = false;
+            break;
+        }
+    const hipMemAccessDesc acc = device_access(dev);
+    if (ok && hipMemSetAccess(va, bytes, &acc, 1) != hipSuccess) ok = false;
+    if (!ok) {
+        (void)hipGetLastError();
+        for (size_t i = 0; i < done; i++) (void)hipMemUnmap(static_cast<char *>(va) + i * kPoolPiece, kPoolPiece);
+        (void)hipMemAddressFree(va, bytes);
+        pool_give(dev, hs.data(), hs.size());
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    Mapped &m = g_mapped[va];
+    m.bytes = bytes;
+    m.dev = dev;
+    m.pieces = std::move(hs);
+    return va;
+}
+
+// unmaps a large block and pools its pieces; false if p is not one
+bool mapped_free(void *p) {
+    Mapped m;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        DeviceCache &c = cache_for_current();
+        auto it = g_mapped.find(p);
+        if (it == g_mapped.end()) return false;
+        m = std::move(it->second);
+        g_mapped.erase(it);
+    }
+    for (size_t i = 0; i < m.pieces.size(); i++)
+        (void)hipMemUnmap(static_cast<char *>(p) + i * kPoolPiece, kPoolPiece);
+    (void)hipMemAddressFree(p, m.bytes);
+    pool_give(m.dev, m.pieces.data(), m.pieces.size());
+    return true;
+}
+
+}  // namespace
+
+bool pool_take(int dev, size_t n, std::vector<Handle> *out) {
+    out->clear();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DeviceCache &c = cache_of(dev);
+        while (out->size() < n && !c.pieces.empty()) {
+            out->push_back(c.pieces.back());
+            c.pieces.pop_back();
+        }
+    }
+    const hipMemAllocationProp prop = device_prop(dev);
+    bool flushed = false;
+    while (out->size() < n) {
+        Handle h{};
+        if (hipMemCreate(&h, kPoolPiece, &prop, 0) == hipSuccess) {
+            out->push_back(h);
+            continue;
+        }
+        (void)hipGetLastError();
+        if (flushed) break;
+        // the cached hipMalloc blocks may hold what is missing
+        std::lock_guard<std::mutex> lk(g_mu);
+        release_blocks_locked(cache_of(dev));
+        flushed = true;
+    }
+    if (out->size() < n) {
+        pool_give(dev, out->data(), out->size());
+        out->clear();
+        return false;
+    }
+    return true;
+}
+
+void pool_give(int dev, const Handle *h, size_t n) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCache &c = cache_of(dev);
+    c.pieces.insert(c.pieces.end(), h, h + n);
+}
+
+void *cache_alloc(size_t bytes, size_t *got) {
+    const int dev = current_device();
+    if (bytes >= kPoolMin && vmm_supported()) {
+        const size_t n = (bytes + kPoolPiece - 1) / kPoolPiece;
+        if (void *p = mapped_alloc(dev, n)) {
+            *got = n * kPoolPiece;
+            return p;
+        }
+        // out of memory with the pool emptied: hipMalloc will not do better
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (cache_of(dev).pieces.empty()) return nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        DeviceCache &c = cache_of(dev);
         auto it = c.free_blocks.lower_bound(bytes);
         if (it != c.free_blocks.end() && it->first <= bytes + bytes / 8) {
             void *p = it->second;
@@ -54,7 +198,8 @@ void *cache_alloc(size_t bytes, size_t *got) {
         (void)hipGetLastError();
         {
             std::lock_guard<std::mutex> lk(g_mu);
-            flush_locked(cache_for_current());
+            release_blocks_locked(cache_of(dev));
+            release_pieces_locked(cache_of(dev));
         }
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
@@ -67,26 +212,39 @@ void *cache_alloc(size_t bytes, size_t *got) {
 
 void cache_free(void *p, size_t bytes) {
     if (!p) return;
+    if (mapped_free(p)) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    DeviceCache &c = cache_for_current();
+    DeviceCache &c = cache_of(current_device());
     c.free_blocks.emplace(bytes, p);
     c.bytes += bytes;
 }
 
+void cache_release(void *p) {
+    if (!p || mapped_free(p)) return;
+    (void)hipFree(p);
+}
+
 void cache_trim(size_t max_bytes) {
     std::lock_guard<std::mutex> lk(g_mu);
-    DeviceCache &c = cache_for_current();
-    while (c.bytes > max_bytes && !c.free_blocks.empty()) {
+    DeviceCache &c = cache_of(current_device());
+    while (c.bytes + c.pieces.size() * kPoolPiece > max_bytes && !c.free_blocks.empty()) {
         auto it = std::prev(c.free_blocks.end());  // largest first
         (void)hipFree(it->second);
         c.bytes -= it->first;
         c.free_blocks.erase(it);
     }
+    while (c.bytes + c.pieces.size() * kPoolPiece > max_bytes && !c.pieces.empty()) {
+        (void)hipMemRelease(c.pieces.back());
+        c.pieces.pop_back();
+    }
 }
 
 void cache_flush() {
     std::lock_guard<std::mutex> lk(g_mu);
-    for (auto &c : g_cache) flush_locked(c);
+    for (auto &c : g_cache) {
+        release_blocks_locked(c);
+        release_pieces_locked(c);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -110,18 +268,12 @@ bool vmm_supported() {
 }
 
 namespace {
-hipMemAllocationProp device_prop(int dev) {
-    hipMemAllocationProp p{};
-    p.type = hipMemAllocationTypePinned;
-    p.location.type = hipMemLocationTypeDevice;
-    p.location.id = dev;
-    return p;
-}
 constexpr size_t kPieceMin = size_t(2) << 20;  // mapping piece bounds
 constexpr size_t kPieceMax = size_t(2) << 30;
 // pieces start and end on 2 MiB boundaries (the large-page size), whatever
 // smaller granularity the runtime reports
 constexpr size_t kPieceAlign = size_t(2) << 20;
+static_assert(kPoolPiece % kPieceAlign == 0, "pooled pieces are whole large pages");
 }  // namespace
 
 spc_status VArray::reserve(size_t max_bytes) {
@@ -147,6 +299,22 @@ spc_status VArray::reserve(size_t max_bytes) {
     return SPC_OK;
 }
 
+// maps pieces hs[0, n) of `bytes` each behind the mapped prefix and grants
+// access; on failure nothing stays mapped and the caller keeps the handles
+spc_status VArray::map_pieces(const Handle *hs, size_t n, size_t bytes) {
+    size_t i = 0;
+    for (; i < n; i++)
+        if (hipMemMap(static_cast<char *>(base_) + mapped_ + i * bytes, bytes, 0, hs[i], 0) != hipSuccess)
+            break;
+    // access is granted over the whole mapped prefix: the runtime rejects
+    // some ranges that start past the reservation's base
+    const hipMemAccessDesc acc = device_access(device_);
+    if (i == n && hipMemSetAccess(base_, mapped_ + n * bytes, &acc, 1) == hipSuccess) return SPC_OK;
+    (void)hipGetLastError();
+    for (size_t j = 0; j < i; j++) (void)hipMemUnmap(static_cast<char *>(base_) + mapped_ + j * bytes, bytes);
+    return SPC_ERR_DEVICE;
+}
+
 spc_status VArray::ensure(size_t bytes, size_t *added) {
     *added = 0;
     if (bytes <= mapped_) return SPC_OK;
@@ -154,11 +322,25 @@ spc_status VArray::ensure(size_t bytes, size_t *added) {
     hipMemAllocationProp prop = device_prop(device_);
     while (mapped_ < bytes) {
         // pieces grow with the array (at most an eighth of it, within
-        // bounds), so an array takes few pieces and little slack
+        // bounds), so an array takes few pieces and little slack; from the
+        // pool's piece size on, pooled pieces are mapped
         size_t piece = std::max(bytes - mapped_, std::min(std::max(kPieceMin, mapped_ / 8), kPieceMax));
+        if (piece >= kPoolPiece && reserved_ - mapped_ >= kPoolPiece) {
+            const size_t n = std::min((piece + kPoolPiece - 1) / kPoolPiece, (reserved_ - mapped_) / kPoolPiece);
+            std::vector<Handle> hs;
+            if (!pool_take(device_, n, &hs)) return SPC_ERR_OUT_OF_MEMORY;
+            if (map_pieces(hs.data(), n, kPoolPiece) != SPC_OK) {
+                pool_give(device_, hs.data(), n);
+                return SPC_ERR_DEVICE;
+            }
+            for (size_t i = 0; i < n; i++) pieces_.push_back({hs[i], kPoolPiece, true});
+            mapped_ += n * kPoolPiece;
+            *added += n * kPoolPiece;
+            continue;
+        }
         piece = (piece + gran_ - 1) / gran_ * gran_;
         piece = std::min(piece, reserved_ - mapped_);
-        hipMemGenericAllocationHandle_t h{};
+        Handle h{};
         if (hipMemCreate(&h, piece, &prop, 0) != hipSuccess) {
             (void)hipGetLastError();
             cache_flush();
@@ -167,24 +349,11 @@ spc_status VArray::ensure(size_t bytes, size_t *added) {
                 return SPC_ERR_OUT_OF_MEMORY;
             }
         }
-        char *at = static_cast<char *>(base_) + mapped_;
-        if (hipMemMap(at, piece, 0, h, 0) != hipSuccess) {
-            (void)hipGetLastError();
+        if (map_pieces(&h, 1, piece) != SPC_OK) {
             (void)hipMemRelease(h);
             return SPC_ERR_DEVICE;
         }
-        // access is granted over the whole mapped prefix: the runtime
-        // rejects some ranges that start past the reservation's base
-        hipMemAccessDesc acc{};
-        acc.location = prop.location;
-        acc.flags = hipMemAccessFlagsProtReadWrite;
-        if (hipMemSetAccess(base_, mapped_ + piece, &acc, 1) != hipSuccess) {
-            (void)hipGetLastError();
-            (void)hipMemUnmap(at, piece);
-            (void)hipMemRelease(h);
-            return SPC_ERR_DEVICE;
-        }
-        pieces_.emplace_back(h, piece);
+        pieces_.push_back({h, piece, false});
         mapped_ += piece;
         *added += piece;
     }
@@ -194,11 +363,16 @@ spc_status VArray::ensure(size_t bytes, size_t *added) {
 void VArray::reset() {
     if (!base_) return;
     size_t off = 0;
+    std::vector<Handle> back;
     for (auto &pc : pieces_) {
-        (void)hipMemUnmap(static_cast<char *>(base_) + off, pc.second);
-        (void)hipMemRelease(pc.first);
-        off += pc.second;
+        (void)hipMemUnmap(static_cast<char *>(base_) + off, pc.bytes);
+        if (pc.pooled)
+            back.push_back(pc.h);
+        else
+            (void)hipMemRelease(pc.h);
+        off += pc.bytes;
     }
+    if (!back.empty()) pool_give(device_, back.data(), back.size());
     pieces_.clear();
     (void)hipMemAddressFree(base_, reserved_);
     base_ = nullptr;

@@ -152,19 +152,36 @@ __device__ __forceinline__ uint64_t lower_bound_hub(const typename Ent<DB>::T *a
 }
 
 // ---------------------------------------------------------------------------
-// Device block cache (memory.hip): freed blocks are kept per device and
-// reused by later allocations of a similar size, so repeated builds and
-// frees do not pay for large hipMalloc / hipFree calls.
+// Device memory cache (memory.hip).  Physical memory that the runtime takes
+// back and hands out again is cleared by the driver first, about 3 s per
+// 100 GB, so freed memory is kept per device and reused:
+//  * blocks of at least kPoolMin bytes are address ranges with pieces of
+//    kPoolPiece bytes of physical memory mapped behind them (virtual memory
+//    API); a freed block's pieces go to the device's piece pool and back
+//    into any later block, whatever its size;
+//  * smaller blocks come from hipMalloc and are kept by size, and reused by
+//    later allocations of a similar size.
 // ---------------------------------------------------------------------------
-// Returns a block of at least `bytes` bytes (size rounded to 256 B), from the
-// cache when a block of at most 1.5 times that size is there, else hipMalloc
-// (after flushing the cache if hipMalloc fails).  nullptr on failure.
+constexpr size_t kPoolPiece = size_t(512) << 20;
+constexpr size_t kPoolMin = size_t(4) << 30;
+// Returns a block of at least `bytes` bytes (size rounded to 256 B; *got =
+// what it holds): pooled pieces for large blocks, else a cached block of at
+// most 1.125 times that size, else hipMalloc (after flushing the cache if
+// that fails).  nullptr on failure.
 void *cache_alloc(size_t bytes, size_t *got);
 void cache_free(void *p, size_t bytes);
+// give a block straight back: a large block's pieces to the pool, a small
+// block to the runtime
+void cache_release(void *p);
+// give every cached block and pooled piece of every device back
 void cache_flush();
-// free the largest cached blocks of the current device until at most
-// max_bytes stay cached
+// give the largest cached blocks, then pooled pieces, of the current device
+// back until at most max_bytes stay cached
 void cache_trim(size_t max_bytes);
+// n pieces of kPoolPiece bytes for device dev (pooled ones first, then new
+// ones); false, with nothing taken, when the device is out of memory
+bool pool_take(int dev, size_t n, std::vector<hipMemGenericAllocationHandle_t> *out);
+void pool_give(int dev, const hipMemGenericAllocationHandle_t *h, size_t n);
 
 // Growable device array on the virtual memory API: an address range is
 // reserved once and physical memory is mapped behind it piece by piece, so
@@ -186,10 +203,16 @@ class VArray {
     size_t mapped() const { return mapped_; }
 
   private:
+    struct Piece {
+        hipMemGenericAllocationHandle_t h;
+        size_t bytes;
+        bool pooled;  // from the piece pool (goes back there)
+    };
+    spc_status map_pieces(const hipMemGenericAllocationHandle_t *hs, size_t n, size_t bytes);
     void *base_ = nullptr;
     size_t reserved_ = 0, mapped_ = 0, gran_ = 0;
     int device_ = 0;
-    std::vector<std::pair<hipMemGenericAllocationHandle_t, size_t>> pieces_;  // handle, bytes
+    std::vector<Piece> pieces_;
 };
 // whether the current device supports the virtual memory API
 bool vmm_supported();
@@ -259,7 +282,7 @@ class Arena {
         if (it != sizes_.end()) {
             (void)hipStreamSynchronize(st_);
             used_ -= it->second;
-            (void)hipFree(it->first);
+            cache_release(it->first);
             sizes_.erase(it);
         }
         p = nullptr;
