@@ -289,11 +289,15 @@ spc_status spc_round_stats(const spc_index *ix, uint32_t max_rounds, uint64_t *r
 /* Per-round cost profile of the build, same indexing as spc_round_stats:
  * time inside the fused round kernel (ms), label entries of the pullers
  * staged on chip, landmark-row bytes read by prune probes, round segment
- * headers read by prune probes, and the device bytes the build held at the
- * round's high-water mark.  Host arrays; any may be NULL. */
+ * headers read by prune probes, the device bytes the build held at the
+ * round's high-water mark, and the bytes of membership-filter words the
+ * prune probes looked up (0 in a round built without the filter: the filter
+ * of the older labels' (vertex, hub) pairs is an implementation device that
+ * skips most label searches; it changes no result).  Host arrays; any may
+ * be NULL. */
 spc_status spc_round_profile(const spc_index *ix, uint32_t max_rounds, double *kernel_ms,
                              uint64_t *staged, uint64_t *row_bytes, uint64_t *headers,
-                             uint64_t *mem_peak);
+                             uint64_t *mem_peak, uint64_t *filter_bytes);
 
 /* Number of labelled vertices (the core under SPC_REDUCE_ONE_SHELL, else
  * every vertex) and label entries of graph `graph_id` (host out). */

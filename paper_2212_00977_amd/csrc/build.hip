@@ -317,6 +317,7 @@ constexpr int kLStage = kLCap / 2;   // staged entries (load <= 1/2)
 constexpr int kCBits = SPC_CBITS;  // >= 9: a candidate slot per thread at least
 constexpr int kCCap = 1 << kCBits;   // candidate hash slots
 constexpr int kULimit = kCCap / 2;   // distinct candidates per chunk
+static_assert(kULimit <= 65536 && kCCap * 2 <= 65536, "filtered probes pack (candidate, entry) in 16 + 16 bits");
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 #ifndef SPC_ROUND_BLOCK
 #define SPC_ROUND_BLOCK 256
@@ -340,6 +341,14 @@ constexpr uint32_t kTailSteps = SPC_TAIL_STEPS;
 #endif
 // pulled entries per thread whose loads are in flight together
 constexpr int kPullUnroll = SPC_PULL_UNROLL;
+// filter lookups per thread in flight together
+constexpr int kProbeUnroll = 4;
+#ifndef SPC_FILT_LIST
+#define SPC_FILT_LIST 512
+#endif
+// filter hits listed for the searches after the lookups (more are searched
+// at once)
+constexpr uint32_t kFiltList = SPC_FILT_LIST;
 // candidates per 16-lane group whose landmark slices are in flight together
 constexpr int kLandUnroll = SPC_LAND_UNROLL;
 // lanes per candidate in the probes past the landmarks (a power of two <= 64)
@@ -374,11 +383,35 @@ struct RoundArgs {
     uint32_t *tmp_hub;
     uint64_t *tmp_cnt;
     uint32_t *surv;
-    unsigned long long *ctr;  // raw, merged, kept, tail, staged, row bytes, headers
+    unsigned long long *ctr;  // raw, merged, kept, tail, staged, row bytes, headers, filter bytes
+    // membership filter of L_{<=d-2}'s (row, hub) pairs past the landmarks
+    // (null: none this round); filt_mask = words - 1
+    const unsigned long long *filt = nullptr;
+    uint64_t filt_mask = 0;
 };
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t h, int bits) {
     return (h * 0x9E3779B1u) >> (32 - bits);
+}
+
+// Membership filter over the (row, hub) pairs of the older labels past the
+// landmarks: a Bloom filter with one 64-bit word per key, in which a key
+// sets (and a lookup tests) up to 4 bits.  A clear bit proves the pair
+// absent; a hit is confirmed in the label itself.  Keys are mixed with the
+// 64-bit finalizer of MurmurHash3; the low bits pick the word, the top 24
+// bits the 4 bit positions.
+__device__ __forceinline__ uint64_t filt_mix(uint32_t row, uint32_t hub) {
+    uint64_t x = ((uint64_t)row << 32) | hub;
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+__device__ __forceinline__ unsigned long long filt_bits(uint64_t x) {
+    return (1ull << ((x >> 40) & 63)) | (1ull << ((x >> 46) & 63)) | (1ull << ((x >> 52) & 63)) |
+           (1ull << (x >> 58));
 }
 
 // first position p in [0, n) with hub(a[p]) >= key (packed entries sorted by
@@ -464,8 +497,8 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     __shared__ uint64_t nb_start[RB];
     __shared__ uint32_t nb_off[RB];
     __shared__ uint32_t red32[RW];
-    __shared__ uint32_t s_nuniq, s_ovf, s_next;
-    __shared__ unsigned long long s_tail, s_hdr, s_rowb;
+    __shared__ uint32_t s_nuniq, s_ovf, s_next, s_nver;
+    __shared__ unsigned long long s_tail, s_hdr, s_rowb, s_filt;
 
     const E *hd = static_cast<const E *>(a.lab_hd);
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -512,6 +545,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         s_tail = 0;
         s_hdr = 0;
         s_rowb = 0;
+        s_filt = 0;
     }
     __syncthreads();
     if (!big) stage(lab, (uint32_t)nsp);
@@ -788,7 +822,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         //  4a. landmark pass, 16 lanes per candidate (4 candidates per wave):
         //      lane gl compares landmarks [16 gl, 16 gl + 16) of the two rows,
         //      reading w's slice only if u has a landmark within d-2 there.
-        uint64_t my_tail = 0, my_hdr = 0, my_rowb = 0;
+        uint64_t my_tail = 0, my_hdr = 0, my_rowb = 0, my_filt = 0;
         if (d >= 3) {
             // kLandUnroll candidates per group and trip, their row slices
             // loaded together
@@ -869,7 +903,104 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         // groups take them from a shared counter: a group that finishes one
         // takes the next, one 16-entry step per trip, and no group waits for
         // a slow one of another wave.
-        if (T > 0 && pstaged) {
+        if (T > 0 && pstaged && a.filt) {
+            // Filtered probes.  Every pair (candidate w, hub h of pl[0, cu_w))
+            // is looked up in the membership filter first: a miss proves h
+            // absent from L_{<=d-2}(w) past the landmarks.  The pairs that
+            // hit (the proving ones and the filter's rare false positives)
+            // are listed, then binary-searched in w's label, one per thread.
+            // Pairs are numbered candidate by candidate: pre[t] is the first
+            // pair of tlist[t] (the candidate table's key array is idle here).
+            uint32_t *pre = ckey;
+            uint32_t *vlist = reinterpret_cast<uint32_t *>(nb_start);  // (t << 16) | j
+            constexpr uint32_t kVCap = kFiltList < RB * 2 ? kFiltList : RB * 2;  // nb_start's bytes
+            uint32_t P = 0;
+            {
+                uint32_t cq[PER], sum = 0;
+#pragma unroll
+                for (int q = 0; q < PER; q++) {
+                    const uint32_t t = PER * tid + q;
+                    cq[q] = t < T ? (uint32_t)lower_bound_hub<DB>(pl, npu, lhub[tlist[t]]) : 0;  // >= 1
+                    sum += cq[q];
+                }
+                uint32_t ex = block_excl_scan<uint32_t, RW>(sum, red32, P);
+#pragma unroll
+                for (int q = 0; q < PER; q++) {
+                    const uint32_t t = PER * tid + q;
+                    if (t < T) {
+                        pre[t] = ex;
+                        ex += cq[q];
+                        lkeep[tlist[t]] = 1;  // until a search proves a shorter path
+                    }
+                }
+                if (tid == 0) {
+                    pre[T] = P;
+                    s_nver = 0;
+                }
+                __syncthreads();
+            }
+            // binary search of u's entry pl[j] in w = lhub[tlist[t]]'s label
+            auto search = [&](uint32_t t, uint32_t j) {
+                const uint32_t i = tlist[t];
+                const uint32_t wr = lhub[i] + poff;
+                const uint64_t q0 = a.prev_off[wr];
+                const uint64_t np = a.prev_off[wr + 1] - q0 - 1;  // the last entry is (w, 0)
+                const uint64_t p0 = a.lc_prev[wr];
+                const E *pw = static_cast<const E *>(a.prev_hd) + q0;
+                const E e = pl[j];
+                const uint32_t h = e_hub<DB>(e);
+                const uint64_t nw = np - p0;
+                const uint64_t q = p0 + lower_bound_hub<DB>(pw + p0, nw, h);
+                if (q < np && e_hub<DB>(pw[q]) == h && e_dist<DB>(e) + e_dist<DB>(pw[q]) < d) lkeep[i] = 0;
+                uint32_t steps = 1;
+                while ((1ull << steps) <= nw) steps++;
+                my_tail += steps;
+                my_hdr++;
+            };
+            uint32_t own = 0;  // owner of pair p: last t with pre[t] <= p (monotone in p)
+            for (uint32_t pb = tid; pb < P; pb += kProbeUnroll * RB) {
+                uint32_t tq[kProbeUnroll], jq[kProbeUnroll];
+                unsigned long long mq[kProbeUnroll], wq[kProbeUnroll];
+#pragma unroll
+                for (int r = 0; r < kProbeUnroll; r++) {
+                    const uint32_t p = pb + r * RB;
+                    mq[r] = 0;  // no pair
+                    wq[r] = 0;
+                    tq[r] = jq[r] = 0;
+                    if (p < P) {
+                        if (pre[own + 1] <= p) {
+                            uint32_t lo2 = own + 1, hi2 = T - 1;
+                            while (lo2 < hi2) {
+                                const uint32_t mid = (lo2 + hi2 + 1) >> 1;
+                                if (pre[mid] <= p)
+                                    lo2 = mid;
+                                else
+                                    hi2 = mid - 1;
+                            }
+                            own = lo2;
+                        }
+                        tq[r] = own;
+                        jq[r] = p - pre[own];
+                        const uint64_t x = filt_mix(lhub[tlist[own]] + poff, e_hub<DB>(pl[jq[r]]));
+                        mq[r] = filt_bits(x);
+                        wq[r] = a.filt[x & a.filt_mask];
+                        my_filt += sizeof(unsigned long long);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kProbeUnroll; r++) {
+                    if (mq[r] == 0 || (wq[r] & mq[r]) != mq[r]) continue;  // no pair, or absent
+                    const uint32_t slot = atomicAdd(&s_nver, 1u);
+                    if (slot < kVCap)
+                        vlist[slot] = (tq[r] << 16) | jq[r];
+                    else
+                        search(tq[r], jq[r]);  // the list is full
+                }
+            }
+            __syncthreads();
+            const uint32_t nver = s_nver < kVCap ? s_nver : kVCap;
+            for (uint32_t v = tid; v < nver; v += RB) search(vlist[v] >> 16, vlist[v] & 0xFFFFu);
+        } else if (T > 0 && pstaged) {
             // u's side is pl[0, cu), its hubs below w, in LDS.  Groups of PG
             // lanes take one candidate each and either
             //  B. binary-search u's cu hubs in w's entries, PG at a time, or
@@ -1164,11 +1295,13 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
             my_tail += __shfl_xor(my_tail, o, 64);
             my_hdr += __shfl_xor(my_hdr, o, 64);
             my_rowb += __shfl_xor(my_rowb, o, 64);
+            my_filt += __shfl_xor(my_filt, o, 64);
         }
         if (lane == 0) {
             atomicAdd(&s_tail, (unsigned long long)my_tail);
             atomicAdd(&s_hdr, (unsigned long long)my_hdr);
             atomicAdd(&s_rowb, (unsigned long long)my_rowb);
+            atomicAdd(&s_filt, (unsigned long long)my_filt);
         }
         __syncthreads();
 
@@ -1247,6 +1380,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         atomicAdd(&a.ctr[4], (unsigned long long)nsp);
         atomicAdd(&a.ctr[5], s_rowb);
         atomicAdd(&a.ctr[6], s_hdr);
+        atomicAdd(&a.ctr[7], s_filt);
     }
 }
 
@@ -1337,6 +1471,30 @@ __global__ void k_lc_init(uint32_t N, uint32_t nreal, const uint32_t *gbase, uin
 }
 
 // Widen packed entries from 8-bit to 16-bit distances.
+// The round's membership filter: cleared, then every row's older label
+// entries past its landmarks, but its own entry (r, 0), inserted (one wave
+// per row).
+__global__ void k_filt_clear(unsigned long long *f, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        f[i] = 0;
+}
+template <int DB>
+__global__ __launch_bounds__(kBlock) void k_filt_insert(uint32_t N, const uint64_t *off, const void *hd,
+                                                        const uint32_t *lc, unsigned long long *f, uint64_t mask) {
+    using E = typename Ent<DB>::T;
+    const uint32_t r = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (r >= N) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t b = off[r] + lc[r], e = off[r + 1];
+    if (e <= b + 1) return;
+    const E *lab = static_cast<const E *>(hd);
+    for (uint64_t i = b + lane; i < e - 1; i += 64) {
+        const uint64_t x = filt_mix(r, e_hub<DB>(lab[i]));
+        atomicOr(&f[x & mask], filt_bits(x));
+    }
+}
+
 __global__ void k_widen(const uint32_t *src, uint64_t *dst, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
@@ -1487,6 +1645,7 @@ struct Build {
     std::vector<uint64_t *> rstart;
     std::vector<uint32_t *> rlen;
     bool vmm = false;              // round arrays grow in place (virtual memory API)
+    bool filter = true;            // membership filters for the prune probes
     uint64_t dev_bytes = 0;        // device memory size (bounds reservations)
     std::vector<std::unique_ptr<VArray>> vhub, vcnt;
     uint64_t **rs_tab = nullptr;  // device copies of the per-round pointers
@@ -2105,6 +2264,27 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         SPC_TRY(B.arena.alloc(&B.tmp_cnt, tmp_want));
         B.tmp_cap = tmp_want;
     }
+    // Membership filter of L_{<=d-2}'s (row, hub) pairs for the prune probes
+    // (16 bits per entry, 1/8 of the memory left at most), where inserting
+    // the older labels costs less than a quarter of the round's pulls
+    unsigned long long *filt = nullptr;
+    uint64_t filt_words = 0;
+    if (B.filter && d >= 3 && !push && !fast1 && B.entries_prev > 0 && B.entries_prev * 4 <= total_raw) {
+        uint64_t words = 1024;
+        while (words < B.entries_prev / 4) words <<= 1;
+        const uint64_t cap_bytes = B.arena.budget() ? B.arena.budget() : B.dev_bytes;
+        const uint64_t left = cap_bytes > B.arena.used() ? cap_bytes - B.arena.used() : 0;
+        if (words * 8 <= left / 8 && B.arena.alloc(&filt, words) == SPC_OK) {
+            filt_words = words;
+            hipLaunchKernelGGL(k_filt_clear, dim3(grid_stride(words)), dim3(kBlock), 0, B.st, filt, words);
+            SPC_LAUNCHED();
+            hipLaunchKernelGGL(k_filt_insert<DB>, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N,
+                               B.lab_off2, B.lab_hd2, B.lc2, filt, words - 1);
+            SPC_LAUNCHED();
+        } else {
+            filt = nullptr;
+        }
+    }
     std::vector<uint32_t> bounds{0};
     if (total_raw <= B.tmp_cap && N <= kBatchVerts) {
         bounds.push_back(N);
@@ -2225,6 +2405,8 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.cur = B.cur;
         ra.nxt = B.nxt;
         ra.ctr = B.ctr;
+        ra.filt = filt;
+        ra.filt_mask = filt_words ? filt_words - 1 : 0;
         SPC_HIP(hipEventRecord(B.ev_a, B.st));
         // from round 17 on the graph has a long diameter: there, neighbours'
         // labels are nearly the same set, which the tail merge exploits
@@ -2296,6 +2478,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         kept += sb;
         raw_lo += need;
     }
+    B.arena.release(filt);
     if (B.rcap[d] > B.rused[d] + B.rused[d] / 8 + (1u << 20)) SPC_TRY(B.shrink_round(d));
     uint64_t c[8];
     SPC_TRY(B.read_u64((const uint64_t *)B.ctr, c, 8));
@@ -2307,6 +2490,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     rc.staged = c[4];
     rc.row_bytes = c[5];
     rc.headers = c[6];
+    rc.filter_bytes = c[7];
     rc.kernel_ms = round_ms;
     rc.mem_peak = B.arena.window_peak();
     B.stats.push_back(rc);
@@ -2314,9 +2498,9 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     // count), u's staged label entries past the landmarks, the candidates'
     // landmark rows (hubs <= w), the other probe entries read up to the first
     // one proving a shorter path and their label offsets, and the survivors
-    // written (hub + count)
+    // written (hub + count), and the filter words looked up
     uint64_t es = sizeof(E);
-    B.alg_bytes += c[0] * 12 + c[4] * es + c[5] + c[3] * es + c[6] * 16 + c[2] * 12;
+    B.alg_bytes += c[0] * 12 + c[4] * es + c[5] + c[3] * es + c[6] * 16 + c[2] * 12 + c[7];
     *kept_out = kept;
     if (kept == 0) return SPC_OK;
 
@@ -2767,6 +2951,9 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         // SPC_VMM=0 in the environment turns in-place growth off
         const char *ev = std::getenv("SPC_VMM");
         B.vmm = vmm_supported() && !(ev && ev[0] == '0');
+        // SPC_FILTER=0 turns the prune probes' membership filter off
+        const char *ef = std::getenv("SPC_FILTER");
+        B.filter = !(ef && ef[0] == '0');
     }
     B.N = (uint32_t)rows64;
     B.NNZ = slots64;

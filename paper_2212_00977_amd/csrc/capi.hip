@@ -165,7 +165,7 @@ spc_status spc_round_stats(const spc_index *ix, uint32_t max_rounds, uint64_t *r
 
 spc_status spc_round_profile(const spc_index *ix, uint32_t max_rounds, double *kernel_ms,
                              uint64_t *staged, uint64_t *row_bytes, uint64_t *headers,
-                             uint64_t *mem_peak) {
+                             uint64_t *mem_peak, uint64_t *filter_bytes) {
     if (!ix) return SPC_ERR_INVALID_ARG;
     for (uint32_t r = 0; r < max_rounds; r++) {
         spc::RoundCounters c;
@@ -175,6 +175,7 @@ spc_status spc_round_profile(const spc_index *ix, uint32_t max_rounds, double *k
         if (row_bytes) row_bytes[r] = c.row_bytes;
         if (headers) headers[r] = c.headers;
         if (mem_peak) mem_peak[r] = c.mem_peak;
+        if (filter_bytes) filter_bytes[r] = c.filter_bytes;
     }
     return SPC_OK;
 }

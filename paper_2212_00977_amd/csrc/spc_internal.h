@@ -357,6 +357,7 @@ struct ShellResult {
 struct RoundCounters {
     uint64_t raw = 0, merged = 0, kept = 0, scanned = 0;
     uint64_t staged = 0, row_bytes = 0, headers = 0;
+    uint64_t filter_bytes = 0;  // membership-filter words looked up by the prune probes
     uint64_t mem_peak = 0;  // device bytes held by the build at the round's high-water mark
     double kernel_ms = 0;   // fused round kernel time of this round
 };

@@ -33,8 +33,10 @@ EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_f
 # entries per batch: small graphs then take the paths that only large labels
 # and large rounds take in the default build (unstaged label parts, chunk
 # overflow and narrowing, many chunks per puller, many batches per round,
-# pullers with a buffer of their own).
-SMALL_TABLES = ["-DSPC_LBITS=7", "-DSPC_CBITS=9", "-DSPC_TEMP_LOG2=14", "-DSPC_TEMP_MAX_LOG2=14"]
+# pullers with a buffer of their own) and a 16-pair list of filter hits (so
+# the probes that search at once run too).
+SMALL_TABLES = ["-DSPC_LBITS=7", "-DSPC_CBITS=9", "-DSPC_TEMP_LOG2=14", "-DSPC_TEMP_MAX_LOG2=14",
+                "-DSPC_FILT_LIST=16"]
 SMALL_TABLES_PATH = os.path.join(LIBDIR, "libspc_smalltab.so")
 
 
@@ -110,7 +112,7 @@ def load(path: str | None = None):
     L.spc_index_stats.restype = C.c_int
     L.spc_round_stats.argtypes = [vp, u32, vp, vp, vp, vp]
     L.spc_round_stats.restype = C.c_int
-    L.spc_round_profile.argtypes = [vp, u32, vp, vp, vp, vp, vp]
+    L.spc_round_profile.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp]
     L.spc_round_profile.restype = C.c_int
     L.spc_graph_entries.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(u64)]
     L.spc_graph_entries.restype = C.c_int

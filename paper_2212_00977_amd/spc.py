@@ -153,12 +153,13 @@ class Index:
         R = self.stats()["rounds"] + 1
         ms = np.zeros(R, dtype=np.float64)
         arrs = {k: np.zeros(R, dtype=np.uint64) for k in ("staged", "row_bytes", "headers",
-                                                           "mem_peak")}
+                                                           "mem_peak", "filter_bytes")}
         _check(native.load().spc_round_profile(self.handle, R, ms.ctypes.data,
                                                arrs["staged"].ctypes.data,
                                                arrs["row_bytes"].ctypes.data,
                                                arrs["headers"].ctypes.data,
-                                               arrs["mem_peak"].ctypes.data), "spc_round_profile")
+                                               arrs["mem_peak"].ctypes.data,
+                                               arrs["filter_bytes"].ctypes.data), "spc_round_profile")
         arrs["kernel_ms"] = ms
         return arrs
 

@@ -52,7 +52,7 @@ def test_null_arguments_rejected_on_host(lib):
     st = native.SpcStats()
     assert lib.spc_index_stats(None, C.byref(st)) == 1
     assert lib.spc_round_stats(None, 1, None, None, None, None) == 1
-    assert lib.spc_round_profile(None, 1, None, None, None, None, None) == 1
+    assert lib.spc_round_profile(None, 1, None, None, None, None, None, None) == 1
     assert lib.spc_export_labels(None, 0, None, None, None, None, None, 0, None) == 1
     assert lib.spc_tune_queries(None, 0, None, None, 1, None, None) == 1
     assert lib.spc_set_query_config(None, 0) == 1
