@@ -292,9 +292,9 @@ spc_status spc_round_stats(const spc_index *ix, uint32_t max_rounds, uint64_t *r
  * headers read by prune probes, the device bytes the build held at the
  * round's high-water mark, and the bytes of membership-filter words the
  * prune probes looked up (0 in a round built without the filter: the filter
- * of the older labels' (vertex, hub) pairs is an implementation device that
- * skips most label searches; it changes no result).  Host arrays; any may
- * be NULL. */
+ * of the older labels' (vertex, hub, distance) triples is an implementation
+ * device that skips most label searches; it changes no result).  Host
+ * arrays; any may be NULL. */
 spc_status spc_round_profile(const spc_index *ix, uint32_t max_rounds, double *kernel_ms,
                              uint64_t *staged, uint64_t *row_bytes, uint64_t *headers,
                              uint64_t *mem_peak, uint64_t *filter_bytes);

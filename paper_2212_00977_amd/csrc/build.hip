@@ -341,8 +341,9 @@ constexpr uint32_t kTailSteps = SPC_TAIL_STEPS;
 #endif
 // pulled entries per thread whose loads are in flight together
 constexpr int kPullUnroll = SPC_PULL_UNROLL;
-// filter lookups per thread in flight together
+// filter lookups per thread in flight together: pairs, and distances per pair
 constexpr int kProbeUnroll = 4;
+constexpr int kFiltProbes = 2;
 #ifndef SPC_FILT_LIST
 #define SPC_FILT_LIST 512
 #endif
@@ -384,7 +385,7 @@ struct RoundArgs {
     uint64_t *tmp_cnt;
     uint32_t *surv;
     unsigned long long *ctr;  // raw, merged, kept, tail, staged, row bytes, headers, filter bytes
-    // membership filter of L_{<=d-2}'s (row, hub) pairs past the landmarks
+    // membership filter of L_{<=d-2}'s (row, hub, distance) triples past the landmarks
     // (null: none this round); filt_mask = words - 1
     const unsigned long long *filt = nullptr;
     uint64_t filt_mask = 0;
@@ -394,14 +395,14 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t h, int bits) {
     return (h * 0x9E3779B1u) >> (32 - bits);
 }
 
-// Membership filter over the (row, hub) pairs of the older labels past the
-// landmarks: a Bloom filter with one 64-bit word per key, in which a key
-// sets (and a lookup tests) up to 4 bits.  A clear bit proves the pair
-// absent; a hit is confirmed in the label itself.  Keys are mixed with the
-// 64-bit finalizer of MurmurHash3; the low bits pick the word, the top 24
-// bits the 4 bit positions.
-__device__ __forceinline__ uint64_t filt_mix(uint32_t row, uint32_t hub) {
-    uint64_t x = ((uint64_t)row << 32) | hub;
+// Membership filter over the (row, hub, distance) triples of the older
+// labels past the landmarks: a Bloom filter with one 64-bit word per key, in
+// which a key sets (and a lookup tests) up to 4 bits.  A clear bit proves
+// the triple absent; a hit is confirmed in the label itself.  Keys are mixed
+// with the 64-bit finalizer of MurmurHash3; the low bits pick the word, the
+// top 24 bits the 4 bit positions.
+__device__ __forceinline__ uint64_t filt_mix(uint32_t row, uint32_t hub, uint32_t dist) {
+    uint64_t x = (((uint64_t)row << 32) | hub) ^ ((uint64_t)dist * 0x9E3779B97F4A7C15ull);
     x ^= x >> 33;
     x *= 0xff51afd7ed558ccdull;
     x ^= x >> 33;
@@ -904,11 +905,14 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         // takes the next, one 16-entry step per trip, and no group waits for
         // a slow one of another wave.
         if (T > 0 && pstaged && a.filt) {
-            // Filtered probes.  Every pair (candidate w, hub h of pl[0, cu_w))
-            // is looked up in the membership filter first: a miss proves h
-            // absent from L_{<=d-2}(w) past the landmarks.  The pairs that
-            // hit (the proving ones and the filter's rare false positives)
-            // are listed, then binary-searched in w's label, one per thread.
+            // Filtered probes.  Every pair (candidate w, entry (h, d_u) of
+            // pl[0, cu_w)) is looked up in the membership filter first, as
+            // (w, h, d_w) for each d_w < d - d_u (at most kFiltProbes of
+            // them; more count as a hit): misses prove that no entry of w
+            // past its landmarks gives d_u + d_w < d through h.  The pairs
+            // that hit (the proving ones and the filter's rare false
+            // positives) are listed, then binary-searched in w's label, one
+            // per thread.
             // Pairs are numbered candidate by candidate: pre[t] is the first
             // pair of tlist[t] (the candidate table's key array is idle here).
             uint32_t *pre = ckey;
@@ -960,14 +964,20 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
             uint32_t own = 0;  // owner of pair p: last t with pre[t] <= p (monotone in p)
             for (uint32_t pb = tid; pb < P; pb += kProbeUnroll * RB) {
                 uint32_t tq[kProbeUnroll], jq[kProbeUnroll];
-                unsigned long long mq[kProbeUnroll], wq[kProbeUnroll];
+                bool vq[kProbeUnroll], hq[kProbeUnroll];
+                unsigned long long mq[kProbeUnroll][kFiltProbes], wq[kProbeUnroll][kFiltProbes];
 #pragma unroll
                 for (int r = 0; r < kProbeUnroll; r++) {
                     const uint32_t p = pb + r * RB;
-                    mq[r] = 0;  // no pair
-                    wq[r] = 0;
+                    vq[r] = p < P;
+                    hq[r] = false;  // a hit without lookups (too many distances)
                     tq[r] = jq[r] = 0;
-                    if (p < P) {
+#pragma unroll
+                    for (int k = 0; k < kFiltProbes; k++) {
+                        mq[r][k] = 0;  // no lookup
+                        wq[r][k] = 0;
+                    }
+                    if (vq[r]) {
                         if (pre[own + 1] <= p) {
                             uint32_t lo2 = own + 1, hi2 = T - 1;
                             while (lo2 < hi2) {
@@ -981,15 +991,27 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                         }
                         tq[r] = own;
                         jq[r] = p - pre[own];
-                        const uint64_t x = filt_mix(lhub[tlist[own]] + poff, e_hub<DB>(pl[jq[r]]));
-                        mq[r] = filt_bits(x);
-                        wq[r] = a.filt[x & a.filt_mask];
-                        my_filt += sizeof(unsigned long long);
+                        const E e = pl[jq[r]];
+                        const uint32_t wr = lhub[tlist[own]] + poff, h = e_hub<DB>(e);
+                        const uint32_t nd = d - 1 - e_dist<DB>(e);  // d_w in [1, nd]; d_u <= d-2
+                        hq[r] = nd > (uint32_t)kFiltProbes;
+#pragma unroll
+                        for (int k = 0; k < kFiltProbes; k++)
+                            if (!hq[r] && (uint32_t)k < nd) {
+                                const uint64_t x = filt_mix(wr, h, (uint32_t)k + 1);
+                                mq[r][k] = filt_bits(x);
+                                wq[r][k] = a.filt[x & a.filt_mask];
+                                my_filt += sizeof(unsigned long long);
+                            }
                     }
                 }
 #pragma unroll
                 for (int r = 0; r < kProbeUnroll; r++) {
-                    if (mq[r] == 0 || (wq[r] & mq[r]) != mq[r]) continue;  // no pair, or absent
+                    bool hit = hq[r];
+#pragma unroll
+                    for (int k = 0; k < kFiltProbes; k++)
+                        hit |= mq[r][k] != 0 && (wq[r][k] & mq[r][k]) == mq[r][k];
+                    if (!vq[r] || !hit) continue;  // no pair, or absent
                     const uint32_t slot = atomicAdd(&s_nver, 1u);
                     if (slot < kVCap)
                         vlist[slot] = (tq[r] << 16) | jq[r];
@@ -1472,8 +1494,8 @@ __global__ void k_lc_init(uint32_t N, uint32_t nreal, const uint32_t *gbase, uin
 
 // Widen packed entries from 8-bit to 16-bit distances.
 // The round's membership filter: cleared, then every row's older label
-// entries past its landmarks, but its own entry (r, 0), inserted (one wave
-// per row).
+// entries past its landmarks, but its own entry (r, 0), inserted with their
+// distances (one wave per row).
 __global__ void k_filt_clear(unsigned long long *f, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -1490,7 +1512,7 @@ __global__ __launch_bounds__(kBlock) void k_filt_insert(uint32_t N, const uint64
     if (e <= b + 1) return;
     const E *lab = static_cast<const E *>(hd);
     for (uint64_t i = b + lane; i < e - 1; i += 64) {
-        const uint64_t x = filt_mix(r, e_hub<DB>(lab[i]));
+        const uint64_t x = filt_mix(r, e_hub<DB>(lab[i]), e_dist<DB>(lab[i]));
         atomicOr(&f[x & mask], filt_bits(x));
     }
 }
@@ -2264,7 +2286,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         SPC_TRY(B.arena.alloc(&B.tmp_cnt, tmp_want));
         B.tmp_cap = tmp_want;
     }
-    // Membership filter of L_{<=d-2}'s (row, hub) pairs for the prune probes
+    // Membership filter of L_{<=d-2}'s (row, hub, distance) triples for the prune probes
     // (16 bits per entry, 1/8 of the memory left at most), where inserting
     // the older labels costs less than a quarter of the round's pulls
     unsigned long long *filt = nullptr;
