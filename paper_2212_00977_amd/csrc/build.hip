@@ -260,6 +260,13 @@ __device__ __forceinline__ uint32_t land_count_le(uint64_t x, uint32_t lim) {
     return c;
 }
 
+// Landmark masks: per row and distance k in [1, kMaskK], the 256-bit set of
+// landmarks held at distance exactly k (32 bytes), so the landmark test of a
+// round d <= kMaskK + 2 reads (d-2) x 32 bytes of a candidate's masks, not
+// its row.
+constexpr int kMaskK = 6;
+constexpr int kMaskWords = kLand / 32;  // u32 words per mask
+
 template <int DB>
 __global__ void k_land_init(uint32_t N, uint32_t nreal, const uint32_t *gbase, typename Land<DB>::T *land) {
     using LT = typename Land<DB>::T;
@@ -371,6 +378,7 @@ struct RoundArgs {
     const uint32_t *lc_cur;          // landmark entries of L_{<=d-1}(v) / L_{<=d-2}(v)
     const uint32_t *lc_prev;
     const void *land;                // landmark rows [N][kLand]
+    const uint4 *lmask;              // landmark masks [N][kMaskK][kLand / 32], or null
     const uint32_t *gbase;           // first rank of each vertex's graph, or null
     const uint64_t *pstart;          // round d-1: segment start / length per vertex
     const uint32_t *plen;
@@ -824,7 +832,69 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         //      lane gl compares landmarks [16 gl, 16 gl + 16) of the two rows,
         //      reading w's slice only if u has a landmark within d-2 there.
         uint64_t my_tail = 0, my_hdr = 0, my_rowb = 0, my_filt = 0;
-        if (d >= 3) {
+        if (d >= 3 && a.lmask && d - 2 <= (uint32_t)kMaskK) {
+            // by the landmark masks, one candidate per thread: w is pruned
+            // if some landmark l it holds at distance k in [1, d-2] is held
+            // by u at distance <= d-1-k, i.e. E_k(w) meets A_{d-1-k}(u)
+            // with A_j(u) = {l : d_u(l) <= j}, built here from u's row in
+            // nb_off (idle outside the pull)
+            uint32_t *amask = nb_off;
+            static_assert(kLand == RB && kLand / 64 * 2 == kMaskWords, "one landmark per thread");
+            for (uint32_t j = 1; j + 2 <= d; j++) {
+                const uint64_t bal = __ballot((uint32_t)lrow_t[tid] <= j);
+                if (lane == 0) {
+                    amask[(j - 1) * kMaskWords + 2 * wv] = (uint32_t)bal;
+                    amask[(j - 1) * kMaskWords + 2 * wv + 1] = (uint32_t)(bal >> 32);
+                }
+            }
+            __syncthreads();
+            const uint32_t nk = d - 2;
+            for (uint32_t i0 = tid; i0 < M; i0 += kLandUnroll * RB) {
+                bool hit[kLandUnroll];
+#pragma unroll
+                for (int r = 0; r < kLandUnroll; r++) hit[r] = false;
+                // two levels per trip: their loads are in flight together
+                for (uint32_t k = 1; k <= nk; k += 2) {
+                    uint4 ev[kLandUnroll][4];
+#pragma unroll
+                    for (int r = 0; r < kLandUnroll; r++) {
+                        const uint32_t i = i0 + r * RB;
+                        if (i < M) {
+                            const uint4 *em = a.lmask + ((uint64_t)(lhub[i] + poff) * kMaskK + (k - 1)) * 2;
+                            ev[r][0] = em[0];
+                            ev[r][1] = em[1];
+                            if (k + 1 <= nk) {
+                                ev[r][2] = em[2];
+                                ev[r][3] = em[3];
+                            } else {
+                                ev[r][2] = ev[r][3] = make_uint4(0, 0, 0, 0);
+                            }
+                        } else {
+                            ev[r][0] = ev[r][1] = ev[r][2] = ev[r][3] = make_uint4(0, 0, 0, 0);
+                        }
+                    }
+                    const uint32_t *a0 = amask + (d - 2 - k) * kMaskWords;  // A_{d-1-k}
+                    const uint32_t *a1 = amask + (k + 1 <= nk ? d - 3 - k : 0) * kMaskWords;  // A_{d-2-k}
+#pragma unroll
+                    for (int r = 0; r < kLandUnroll; r++) {
+                        const uint4 x0 = ev[r][0], x1 = ev[r][1], y0 = ev[r][2], y1 = ev[r][3];
+                        uint32_t o = (x0.x & a0[0]) | (x0.y & a0[1]) | (x0.z & a0[2]) | (x0.w & a0[3]) |
+                                     (x1.x & a0[4]) | (x1.y & a0[5]) | (x1.z & a0[6]) | (x1.w & a0[7]);
+                        o |= (y0.x & a1[0]) | (y0.y & a1[1]) | (y0.z & a1[2]) | (y0.w & a1[3]) |
+                             (y1.x & a1[4]) | (y1.y & a1[5]) | (y1.z & a1[6]) | (y1.w & a1[7]);
+                        hit[r] |= o != 0;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kLandUnroll; r++) {
+                    const uint32_t i = i0 + r * RB;
+                    if (i < M) {
+                        lkeep[i] = hit[r] ? 0 : (lhub[i] - base >= (uint32_t)kLand ? 2 : 1);
+                        my_rowb += (uint64_t)nk * kMaskWords * sizeof(uint32_t);
+                    }
+                }
+            }
+        } else if (d >= 3) {
             // kLandUnroll candidates per group and trip, their row slices
             // loaded together
             for (uint32_t i0 = wv * 4; i0 < M; i0 += kLandUnroll * (RB / 16)) {
@@ -1418,7 +1488,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(uint32_t u_lo, uint32_t u_hi
                                                     uint32_t *pool_hub, uint64_t *pool_cnt,
                                                     uint64_t *rstart, uint32_t *rlen,
                                                     const uint32_t *gbase,
-                                                    typename Land<DB>::T *land) {
+                                                    typename Land<DB>::T *land, uint32_t *lmask) {
     uint32_t u = u_lo + blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (u >= u_hi) return;
     uint32_t lane = threadIdx.x & 63;
@@ -1430,7 +1500,12 @@ __global__ __launch_bounds__(kBlock) void k_compact(uint32_t u_lo, uint32_t u_hi
         uint32_t h = tmp_hub[src + i];
         pool_hub[dst + i] = h;
         pool_cnt[dst + i] = tmp_cnt[src + i];
-        if (h - base < (uint32_t)kLand) land[(uint64_t)u * kLand + (h - base)] = (typename Land<DB>::T)d;
+        if (h - base < (uint32_t)kLand) {
+            const uint32_t l = h - base;
+            land[(uint64_t)u * kLand + l] = (typename Land<DB>::T)d;
+            if (lmask && d >= 1 && d <= (uint32_t)kMaskK)
+                atomicOr(&lmask[((uint64_t)u * kMaskK + (d - 1)) * kMaskWords + (l >> 5)], 1u << (l & 31));
+        }
     }
     if (lane == 0) {
         rstart[u] = dst;
@@ -1496,6 +1571,11 @@ __global__ void k_lc_init(uint32_t N, uint32_t nreal, const uint32_t *gbase, uin
 // The round's membership filter: cleared, then every row's older label
 // entries past its landmarks, but its own entry (r, 0), inserted with their
 // distances (one wave per row).
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
 __global__ void k_filt_clear(unsigned long long *f, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -1676,6 +1756,7 @@ struct Build {
     uint64_t **cnt_tab = nullptr;
     size_t tab_cap = 0;
     void *land = nullptr;         // landmark rows [N][kLand]
+    uint32_t *lmask = nullptr;    // landmark masks [N][kMaskK][kLand / 32] (null: rows only)
     uint32_t *gbase = nullptr;    // per-rank graph base (batches only)
     uint32_t *lc = nullptr, *lc2 = nullptr;  // landmark prefix lengths of the two label buffers
     // per-round scratch
@@ -2404,6 +2485,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.lc_cur = B.lc;
         ra.lc_prev = B.lc2;
         ra.land = B.land;
+        ra.lmask = reinterpret_cast<const uint4 *>(B.lmask);
         ra.gbase = B.gbase;
         ra.pstart = pstart;
         ra.plen = plen;
@@ -2494,7 +2576,7 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         hipLaunchKernelGGL(k_compact<DB>, dim3(grid_for(b1 - b0, kWaves)), dim3(kBlock), 0, B.st, b0,
                            b1, d, B.raw_off, B.soff, B.surv, B.tmp_hub, B.tmp_cnt, B.rused[d],
                            B.rhub[d], B.rcnt[d], rs, rl, (const uint32_t *)B.gbase,
-                           static_cast<LT *>(B.land));
+                           static_cast<LT *>(B.land), B.lmask);
         SPC_LAUNCHED();
         B.rused[d] += sb;
         kept += sb;
@@ -3102,6 +3184,16 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
                                    B.nreal, (const uint32_t *)B.gbase, l16);
             }
             SPC_LAUNCHED();
+        }
+        {
+            // landmark masks (optional: without them the rows serve)
+            const uint64_t nw = (uint64_t)N * kMaskK * kMaskWords;
+            if (B.arena.alloc(&B.lmask, nw) == SPC_OK) {
+                hipLaunchKernelGGL(k_fill_u32, dim3(grid_stride(nw)), dim3(kBlock), 0, st, B.lmask, nw, 0u);
+                SPC_LAUNCHED();
+            } else {
+                B.lmask = nullptr;
+            }
         }
         SPC_TRY(B.arena.alloc(&B.lc, (uint64_t)N + 1));
         SPC_TRY(B.arena.alloc(&B.lc2, (uint64_t)N + 1));
