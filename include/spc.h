@@ -269,8 +269,17 @@ void spc_free(spc_index *ix);
 
 /* Return every cached device block to the HIP runtime (all devices).  The
  * cache is also flushed automatically when an allocation would fail, and
- * trimmed to a quarter of the device's memory after every build and free. */
+ * trimmed after every build and free to the limit spc_set_cache_limit sets
+ * (default: a quarter of the device's memory). */
 void spc_release_cached_memory(void);
+
+/* Most device memory, in bytes, that the cache keeps per device after a
+ * build or a free (UINT64_MAX: all of it, until spc_release_cached_memory).
+ * Memory the runtime takes back is cleared by the driver before it is
+ * handed out again (seconds per 100 GB), so a process that builds large
+ * indexes one after another keeps it.  Applies to later builds and frees
+ * of every device; there is no error. */
+void spc_set_cache_limit(uint64_t bytes);
 
 /* Summary numbers of a finished build (host struct). */
 spc_status spc_index_stats(const spc_index *ix, spc_stats *out);

@@ -308,12 +308,12 @@ __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
 //   4. sort the survivors by hub (bitonic, LDS);
 //   5. append them to u's slot of the temp buffer.
 // ---------------------------------------------------------------------------
-// LDS budget of the round kernel (about 40 KB with the defaults: four
-// workgroups per CU).  u's L_{<=d-2} part is staged for the probes in the
+// LDS budget of the round kernel (about 32 KB with the defaults; the
+// 128-VGPR bound keeps four workgroups per CU).  u's L_{<=d-2} part is staged for the probes in the
 // candidate table's count array, which is idle between a chunk's merge and
 // its sort, so it costs no occupancy.
 #ifndef SPC_LBITS
-#define SPC_LBITS 12
+#define SPC_LBITS 11
 #endif
 constexpr int kLBits = SPC_LBITS;
 constexpr int kLCap = 1 << kLBits;   // L(u) hash slots
@@ -344,12 +344,15 @@ constexpr uint32_t kTailSteps = SPC_TAIL_STEPS;
 #define SPC_PULL_UNROLL 4
 #endif
 #ifndef SPC_LAND_UNROLL
-#define SPC_LAND_UNROLL 2
+#define SPC_LAND_UNROLL 1
 #endif
 // pulled entries per thread whose loads are in flight together
 constexpr int kPullUnroll = SPC_PULL_UNROLL;
 // filter lookups per thread in flight together: pairs, and distances per pair
-constexpr int kProbeUnroll = 4;
+#ifndef SPC_PROBE_UNROLL
+#define SPC_PROBE_UNROLL 2
+#endif
+constexpr int kProbeUnroll = SPC_PROBE_UNROLL;
 constexpr int kFiltProbes = 2;
 #ifndef SPC_FILT_LIST
 #define SPC_FILT_LIST 512

@@ -2,15 +2,24 @@
 // host-side arguments, then runs the library's kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
 
 #include "spc_internal.h"
 
 namespace {
-// The block cache keeps at most a quarter of the current device's memory
-// after a build or a free: enough for the next build of a similar graph,
-// the rest goes back to the runtime for other allocators.
+// The cache keeps at most g_cache_limit bytes of freed memory after a build
+// or a free (0: a quarter of the current device's memory, enough for the
+// next build of a similar graph); the rest goes back to the runtime for
+// other allocators.
+std::atomic<uint64_t> g_cache_limit{0};
 void trim_cache() {
+    const uint64_t lim = g_cache_limit.load();
+    if (lim == UINT64_MAX) return;
+    if (lim) {
+        spc::cache_trim(lim);
+        return;
+    }
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess)
         spc::cache_trim(tot / 4);
@@ -96,6 +105,8 @@ void spc_free(spc_index *ix) {
 }
 
 void spc_release_cached_memory(void) { spc::cache_flush(); }
+
+void spc_set_cache_limit(uint64_t bytes) { g_cache_limit.store(bytes ? bytes : 1); }
 
 spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
     if (!ix || !out) return SPC_ERR_INVALID_ARG;

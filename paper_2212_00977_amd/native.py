@@ -25,7 +25,7 @@ EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_f
            "spc_status_string", "spc_release_cached_memory", "spc_query_config_count",
            "spc_query_config_info", "spc_tune_queries", "spc_set_query_config", "spc_hybrid_order",
            "spc_export_reduction", "spc_query_batch_multi", "spc_tune_query_buckets",
-           "spc_set_query_buckets", "spc_query_batch_multi_noalloc"]
+           "spc_set_query_buckets", "spc_query_batch_multi_noalloc", "spc_set_cache_limit"]
 
 
 # A test build with tiny on-chip tables (8-bit hash of 128 slots for the
@@ -108,6 +108,8 @@ def load(path: str | None = None):
     L.spc_free.restype = None
     L.spc_release_cached_memory.argtypes = []
     L.spc_release_cached_memory.restype = None
+    L.spc_set_cache_limit.argtypes = [u64]
+    L.spc_set_cache_limit.restype = None
     L.spc_index_stats.argtypes = [vp, C.POINTER(SpcStats)]
     L.spc_index_stats.restype = C.c_int
     L.spc_round_stats.argtypes = [vp, u32, vp, vp, vp, vp]

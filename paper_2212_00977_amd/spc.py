@@ -417,6 +417,13 @@ def release_cached_memory():
     native.load().spc_release_cached_memory()
 
 
+def set_cache_limit(nbytes=None):
+    """Most freed device memory the library keeps per device after a build
+    or a free (None: all of it, until release_cached_memory; 0: the default,
+    a quarter of the device)."""
+    native.load().spc_set_cache_limit((1 << 64) - 1 if nbytes is None else int(nbytes))
+
+
 def as_u64(count_tensor) -> np.ndarray:
     """Host uint64 view of a count tensor (int64 bit pattern)."""
     return count_tensor.cpu().numpy().view(np.uint64)
