@@ -305,7 +305,7 @@ __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
 //      h != u, w forces d_u, d_w >= 1) with hubs ranked above w, from the
 //      previous round's merged labels.  A hub with d_u(h) + d_w(h) < d
 //      prunes; equality keeps;
-//   4. sort the survivors by hub (bitonic, LDS);
+//   4. rank the survivors by hub (counting, LDS);
 //   5. append them to u's slot of the temp buffer.
 // ---------------------------------------------------------------------------
 // LDS budget of the round kernel (about 32 KB with the defaults; the
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     __shared__ uint32_t ckey[kCCap];
     __shared__ unsigned long long cval[kCCap];
     __shared__ uint8_t cwrap[kCCap];
-    __shared__ uint32_t lhub[kULimit];
+    __shared__ __align__(16) uint32_t lhub[kULimit];
     __shared__ unsigned long long lcnt[kULimit];
     __shared__ uint8_t lkeep[kULimit];   // 0 pruned, 1 kept, 2 needs the tail check
     // candidates that need the tail check (probe phase)
@@ -1421,35 +1421,24 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                 pos++;
             }
         __syncthreads();
-        // sort them by hub: a bitonic network over (hub, list index) keys in
-        // the candidate table's count array (unused until the next chunk),
-        // then write them out in order (coalesced)
-        uint32_t P = 1;
-        while (P < S) P <<= 1;
-        unsigned long long *sk = cval;
-        for (uint32_t i = tid; i < P; i += RB)
-            sk[i] = i < S ? ((unsigned long long)lhub[i] << 32) | i : ~0ull;
+        // place them in hub order: a survivor's rank is the number of
+        // survivors with a smaller hub (hubs are distinct), counted over the
+        // list read four hubs at a time (the same LDS words in every lane);
+        // the list is padded to a multiple of 4 with hubs above all
+        if (tid < ((4 - (S & 3)) & 3)) lhub[S + tid] = 0xFFFFFFFFu;
         __syncthreads();
-        for (uint32_t k = 2; k <= P; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = tid; i < P; i += RB) {
-                    const uint32_t l = i ^ j;
-                    if (l > i) {
-                        const unsigned long long x = sk[i], y = sk[l];
-                        if ((x > y) == ((i & k) == 0)) {
-                            sk[i] = y;
-                            sk[l] = x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
         const uint64_t obase = tbase + nout;
-        for (uint32_t k = tid; k < S; k += RB) {
-            const uint32_t idx = (uint32_t)sk[k];
-            a.tmp_hub[obase + k] = lhub[idx];
-            a.tmp_cnt[obase + k] = lcnt[idx];
+        const uint4 *h4 = reinterpret_cast<const uint4 *>(lhub);
+        const uint32_t S4 = (S + 3) >> 2;
+        for (uint32_t i = tid; i < S; i += RB) {
+            const uint32_t h = lhub[i];
+            uint32_t r = 0;
+            for (uint32_t j = 0; j < S4; j++) {
+                const uint4 v = h4[j];
+                r += (v.x < h) + (v.y < h) + (v.z < h) + (v.w < h);
+            }
+            a.tmp_hub[obase + r] = h;
+            a.tmp_cnt[obase + r] = lcnt[i];
         }
         nout += S;
         st_raw += chunk_raw;
