@@ -242,8 +242,10 @@ def bench_grid(args, dev, log):
     bms = float(np.mean([r[0] for r in runs]))
     qms = float(np.mean([r[1] for r in runs]))
     horizon = int(((f & spc.FLAG_HORIZON) != 0).sum())
-    out = {"metric": METRIC, "value": st["entries"] / (bms * 1e-3), "unit": "label entries/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": bms + qms,
+    # the paper counts ordering in indexing time: a host-side order is part
+    # of every build's time (the degree order runs inside the build)
+    out = {"metric": METRIC, "value": st["entries"] / ((order_ms + bms) * 1e-3), "unit": "label entries/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": order_ms + bms + qms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
            "data": "synthetic",
            "config": {"workload": f"grid {k}x{k}, 5% edges deleted, LCC, seed 3, "
@@ -253,7 +255,9 @@ def bench_grid(args, dev, log):
                       "n": g.n, "m": g.m, "entries": st["entries"], "rounds": st["rounds"],
                       "truncated": bool(st["truncated"]), "dist_bits": st["dist_bits"],
                       "parallelism": "single-gpu"},
-           "build_ms": bms, "query_ms": qms, "queries_per_s": args.queries / (qms * 1e-3),
+           "build_ms": order_ms + bms, "build_ms_device": bms,
+           "device_entries_per_s": st["entries"] / (bms * 1e-3),
+           "query_ms": qms, "queries_per_s": args.queries / (qms * 1e-3),
            "queries_beyond_horizon": horizon, "index_bytes": st["index_bytes"],
            "peak_build_bytes": st["peak_build_bytes"]}
     print(json.dumps(out), flush=True)

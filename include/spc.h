@@ -141,6 +141,18 @@ typedef struct {
      * SPC_ERR_INVALID_ARG. */
     uint32_t propagation;
     uint32_t reserved;   /* must be 0 */
+    /* Path of an on-disk tuning cache, or NULL.  The file holds text lines
+     * "<key> <cfg> <small>": key = 16 hex digits naming an index (a hash of
+     * its vertex, edge, entry and round counts, largest distance, graph
+     * count, direction, output width and the device's name), cfg its query
+     * launch configuration (spc_tune_queries), small its bucket threshold
+     * (spc_tune_query_buckets).  A build that finds its key takes both;
+     * the tuners, on an index built with a cache path, write their results
+     * back (the file is rewritten whole through a temporary file renamed
+     * over it).  A missing or unreadable file leaves the defaults; a failed
+     * write is ignored.  spc_stats.tune_cached tells whether the build found
+     * its key. */
+    const char *tune_cache;
 } spc_build_opts;
 
 typedef struct {
@@ -172,6 +184,9 @@ typedef struct {
                                         SPC_REDUCE_EQUIVALENCE (0 otherwise) */
     uint32_t directed;               /* 1 for an index of a directed graph (entries
                                         count both label sets) */
+    uint32_t query_small;            /* bucket threshold of spc_query_batch_multi */
+    uint32_t tune_cached;            /* 1 if the build took cfg and small from its
+                                        tuning cache (spc_build_opts.tune_cache) */
 } spc_stats;
 
 /* Build the index of one graph (Alg. 2 rounds until a round adds no entry).

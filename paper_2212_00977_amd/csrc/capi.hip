@@ -2,8 +2,15 @@
 // host-side arguments, then runs the library's kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <atomic>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
 
 #include "spc_internal.h"
 
@@ -26,6 +33,78 @@ void trim_cache() {
     else
         (void)hipGetLastError();
 }
+
+// On-disk tuning cache (spc_build_opts.tune_cache): lines "<key> <cfg>
+// <small>", key in 16 hex digits.
+uint64_t tune_key(const spc_index *ix) {
+    char dev[320] = {0};
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ix->device) == hipSuccess)
+        std::snprintf(dev, sizeof(dev), "%s/%s", prop.name, prop.gcnArchName);
+    else
+        (void)hipGetLastError();
+    const uint64_t vals[] = {ix->n, ix->m, ix->entries, ix->rounds, ix->max_dist, ix->gn.size(),
+                             ix->nreal ? 1u : 0u, ix->out_bits};
+    uint64_t h = 1469598103934665603ull;  // FNV-1a, 64 bit
+    auto mix = [&](const void *p, size_t n) {
+        for (size_t i = 0; i < n; i++) {
+            h ^= static_cast<const unsigned char *>(p)[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(vals, sizeof(vals));
+    mix(dev, std::strlen(dev));
+    return h;
+}
+
+std::vector<std::string> read_lines(const std::string &path) {
+    std::vector<std::string> out;
+    std::ifstream f(path);
+    std::string line;
+    while (f && std::getline(f, line))
+        if (!line.empty()) out.push_back(line);
+    return out;
+}
+
+void load_tune_cache(spc_index *ix, const char *path) {
+    ix->tune_cache = path;
+    ix->tune_key = tune_key(ix);
+    char key[17];
+    std::snprintf(key, sizeof(key), "%016llx", (unsigned long long)ix->tune_key);
+    for (const std::string &line : read_lines(path)) {
+        std::istringstream is(line);
+        std::string k;
+        uint32_t cfg = 0, small = 0;
+        if (!(is >> k >> cfg >> small) || k != key) continue;
+        if (cfg < spc::query_cfg_count()) {
+            ix->query_cfg = cfg;
+            ix->query_small = small;
+            ix->tune_cached = true;
+        }
+    }
+}
+
+void store_tune_cache(const spc_index *ix) {
+    if (ix->tune_cache.empty()) return;
+    char key[17];
+    std::snprintf(key, sizeof(key), "%016llx", (unsigned long long)ix->tune_key);
+    std::vector<std::string> lines;
+    for (const std::string &line : read_lines(ix->tune_cache))
+        if (line.compare(0, 16, key) != 0) lines.push_back(line);
+    char mine[64];
+    std::snprintf(mine, sizeof(mine), "%s %u %u", key, ix->query_cfg, ix->query_small);
+    lines.push_back(mine);
+    const std::string tmp = ix->tune_cache + ".tmp." + std::to_string((unsigned long)getpid());
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        for (const std::string &l : lines) f << l << '\n';
+        if (!f) {
+            std::remove(tmp.c_str());
+            return;
+        }
+    }
+    if (std::rename(tmp.c_str(), ix->tune_cache.c_str()) != 0) std::remove(tmp.c_str());
+}
 }  // namespace
 
 extern "C" {
@@ -46,6 +125,7 @@ spc_status spc_build_index(const spc_graph *g, const spc_build_opts *opts, void 
                            spc_index **out) {
     if (!g || !opts || !out) return SPC_ERR_INVALID_ARG;
     spc_status s = spc::build_impl(g, 1, opts, static_cast<hipStream_t>(stream), out);
+    if (s == SPC_OK && opts->tune_cache) load_tune_cache(*out, opts->tune_cache);
     trim_cache();
     return s;
 }
@@ -54,6 +134,7 @@ spc_status spc_build_index_batch(const spc_graph *gs, uint32_t k, const spc_buil
                                  void *stream, spc_index **out) {
     if (!gs || k == 0 || !opts || !out) return SPC_ERR_INVALID_ARG;
     spc_status s = spc::build_impl(gs, k, opts, static_cast<hipStream_t>(stream), out);
+    if (s == SPC_OK && opts->tune_cache) load_tune_cache(*out, opts->tune_cache);
     trim_cache();
     return s;
 }
@@ -82,8 +163,10 @@ spc_status spc_query_batch_multi_noalloc(const spc_index *ix, const uint32_t *gr
 
 spc_status spc_tune_query_buckets(spc_index *ix, const uint32_t *graph_ids, const uint32_t *s,
                                   const uint32_t *t, uint64_t nq, void *stream, uint32_t *small_out) {
-    return spc::tune_query_buckets_impl(ix, graph_ids, s, t, nq, static_cast<hipStream_t>(stream),
-                                        small_out);
+    spc_status r = spc::tune_query_buckets_impl(ix, graph_ids, s, t, nq, static_cast<hipStream_t>(stream),
+                                                small_out);
+    if (r == SPC_OK) store_tune_cache(ix);
+    return r;
 }
 
 spc_status spc_set_query_buckets(spc_index *ix, uint32_t small) {
@@ -135,6 +218,8 @@ spc_status spc_index_stats(const spc_index *ix, spc_stats *out) {
     out->round_kernel_launches = ix->round_kernel_launches;
     out->directed = ix->nreal ? 1u : 0u;
     out->query_config = ix->query_cfg;
+    out->query_small = ix->query_small;
+    out->tune_cached = ix->tune_cached ? 1u : 0u;
     return SPC_OK;
 }
 
@@ -146,7 +231,9 @@ spc_status spc_query_config_info(uint32_t cfg, uint32_t *stage, uint32_t *tiles)
 
 spc_status spc_tune_queries(spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                             uint64_t nq, void *stream, uint32_t *cfg_out) {
-    return spc::tune_queries_impl(ix, graph_id, s, t, nq, static_cast<hipStream_t>(stream), cfg_out);
+    spc_status r = spc::tune_queries_impl(ix, graph_id, s, t, nq, static_cast<hipStream_t>(stream), cfg_out);
+    if (r == SPC_OK) store_tune_cache(ix);
+    return r;
 }
 
 spc_status spc_hybrid_order(const spc_graph *g, uint32_t delta, uint32_t *order_out,

@@ -184,27 +184,40 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     // hub range are streamed kQTiles tiles at a time and each is binary-
     // searched in the staged part.  Hub ranges of consecutive stages abut,
     // so every common hub is met exactly once.
+    E eb[kQTiles];
+    auto load_tiles = [&]() {
+#pragma unroll
+        for (int j = 0; j < kQTiles; j++) {
+            const uint64_t i = ib + (uint64_t)j * G + lane;
+            eb[j] = i < nb ? hd[bs + i] : (E)~(E)0;
+        }
+    };
     while (ia < na && ib < nb) {
         const uint32_t cnt = (uint32_t)((na - ia) < kQStage ? (na - ia) : kQStage);
-        E nxt = (E)~(E)0;
+        // the slice of L(s) and the first tiles of L(t) are requested
+        // together (the tiles do not depend on the slice)
+        E sv[kQStage / G];
 #pragma unroll
         for (uint32_t j = 0; j < kQStage / G; j++) {
             const uint32_t k = j * G + lane;
-            if (k < cnt) st[k] = hd[as + ia + k];
+            sv[j] = k < cnt ? hd[as + ia + k] : (E)0;
         }
+        E nxt = (E)~(E)0;
         if (lane == 0 && ia + cnt < na) nxt = hd[as + ia + cnt];
+        load_tiles();
+#pragma unroll
+        for (uint32_t j = 0; j < kQStage / G; j++) {
+            const uint32_t k = j * G + lane;
+            if (k < cnt) st[k] = sv[j];
+        }
         wave_lds_sync();
         // staged hubs are [first, hub_hi): up to the next stage's first hub
         const uint32_t hub_hi = (ia + cnt < na) ? e_hub<DB>((E)__shfl(nxt, 0, G))
                                                 : e_hub<DB>(st[cnt - 1]) + 1;
-        bool more = true;
+        bool more = true, first = true;
         while (more && ib < nb) {
-            E eb[kQTiles];
-#pragma unroll
-            for (int j = 0; j < kQTiles; j++) {
-                const uint64_t i = ib + (uint64_t)j * G + lane;
-                eb[j] = i < nb ? hd[bs + i] : (E)~(E)0;
-            }
+            if (!first) load_tiles();
+            first = false;
             uint32_t pos[kQTiles];
             bool in[kQTiles];
             uint32_t n_in = 0;

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -391,6 +392,10 @@ struct spc_index {
     // queries with |L(s)| + |L(t)| at most this are answered 16 lanes per
     // query by spc_query_batch_multi (0: no bucketing)
     uint32_t query_small = 256;
+    // on-disk tuning cache of the index (empty: none): its path and key
+    std::string tune_cache;
+    uint64_t tune_key = 0;
+    bool tune_cached = false;
     uint32_t *g_tab = nullptr;  // per graph (vbase, gn, obase, on), device
     // directed: label rows [0, nreal) are out-labels, [nreal, 2 nreal)
     // in-labels (0: undirected)

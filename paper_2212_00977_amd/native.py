@@ -68,7 +68,7 @@ class SpcStats(C.Structure):
                 ("round_kernel_launches", C.c_uint64), ("query_config", C.c_uint32),
                 ("label_bits", C.c_uint32), ("fringe_vertices", C.c_uint64),
                 ("fringe_depth", C.c_uint32), ("twin_vertices", C.c_uint32),
-                ("directed", C.c_uint32)]
+                ("directed", C.c_uint32), ("query_small", C.c_uint32), ("tune_cached", C.c_uint32)]
 
 
 class SpcGraph(C.Structure):
@@ -80,7 +80,7 @@ class SpcGraph(C.Structure):
 class SpcBuildOpts(C.Structure):
     _fields_ = [("dist_bits", C.c_uint32), ("round_cap", C.c_uint32),
                 ("mem_budget", C.c_uint64), ("validate", C.c_uint32), ("reduce", C.c_uint32),
-                ("propagation", C.c_uint32), ("reserved", C.c_uint32)]
+                ("propagation", C.c_uint32), ("reserved", C.c_uint32), ("tune_cache", C.c_char_p)]
 
 
 _lib = None

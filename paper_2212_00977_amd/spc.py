@@ -6,6 +6,7 @@ kernels of libspc.so.  torch provides device memory and the stream.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -96,6 +97,7 @@ class BuildOptions:
     one_shell: bool = False  # SPC_REDUCE_ONE_SHELL: label the 2-core only
     equivalence: bool = False  # SPC_REDUCE_EQUIVALENCE: one weighted vertex per class of twins
     propagation: str = "pull"  # "pull" (Alg. 2), "push" (Alg. 1) or "auto" (chosen per round)
+    tune_cache: str | None = None  # on-disk tuning cache: query configuration and bucket threshold
 
     def struct(self):
         o = native.SpcBuildOpts()
@@ -106,6 +108,7 @@ class BuildOptions:
         o.reduce = (1 if self.one_shell else 0) | (2 if self.equivalence else 0)
         o.propagation = {"pull": 0, "push": 1, "auto": 2}[self.propagation]
         o.reserved = 0
+        o.tune_cache = None if self.tune_cache is None else os.fsencode(self.tune_cache)
         return o
 
 
