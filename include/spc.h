@@ -144,7 +144,8 @@ typedef struct {
     /* Path of an on-disk tuning cache, or NULL.  The file holds text lines
      * "<key> <cfg> <small>": key = 16 hex digits naming an index (a hash of
      * its vertex, edge, entry and round counts, largest distance, graph
-     * count, direction, output width and the device's name), cfg its query
+     * count, direction, output width, the device's name and the table of
+     * launch configurations), cfg its query
      * launch configuration (spc_tune_queries), small its bucket threshold
      * (spc_tune_query_buckets).  A build that finds its key takes both;
      * the tuners, on an index built with a cache path, write their results

@@ -54,6 +54,12 @@ uint64_t tune_key(const spc_index *ix) {
     };
     mix(vals, sizeof(vals));
     mix(dev, std::strlen(dev));
+    // the configuration table: a cached number means the same launch shape
+    for (uint32_t c = 0; c < spc::query_cfg_count(); c++) {
+        uint32_t st[2] = {0, 0};
+        (void)spc::query_cfg_info(c, &st[0], &st[1]);
+        mix(st, sizeof(st));
+    }
     return h;
 }
 
