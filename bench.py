@@ -297,6 +297,11 @@ def bench_batch(args, dev, log):
         return ix, (t1 - t0) * 1e3
 
     def plain():
+        # each form starts from the same memory state: the cache keeps freed
+        # blocks by size, and blocks given back to the runtime are cleared by
+        # the driver before their next use (seconds per 100 GB)
+        spc.release_cached_memory()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         entries = 0
         for g in dev_graphs:
@@ -305,6 +310,7 @@ def bench_batch(args, dev, log):
             ix.free()
         return entries, (time.perf_counter() - t0) * 1e3
 
+    spc.release_cached_memory()
     for _ in range(args.warmup):
         ix, _ = batched()
         ix.free()
@@ -318,12 +324,26 @@ def bench_batch(args, dev, log):
     st = ix.stats()
     entries = st["entries"]
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # every graph's queries in one bucketed call (threshold tuned on a sample
+    # of the same mix), against one launch per graph
+    gid_d = torch.cat([torch.full((10000,), gi, dtype=torch.int32, device=dev) for gi in range(len(graphs))])
+    sa_d, ta_d = torch.cat(s_d), torch.cat(t_d)
+    samp = torch.randperm(gid_d.shape[0], device=dev)[:200000]
+    small = ix.tune_query_buckets(gid_d[samp], sa_d[samp], ta_d[samp], stream=stream)
+    ix.query_multi(gid_d, sa_d, ta_d, stream=stream)  # warm
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    ix.query_multi(gid_d, sa_d, ta_d, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    qms = ev0.elapsed_time(ev1)
     ev0.record(stream)
     for gi in range(len(graphs)):
         ix.query(s_d[gi], t_d[gi], graph_id=gi, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
-    qms = ev0.elapsed_time(ev1)
+    qms_each = ev0.elapsed_time(ev1)
+    log(f"queries: one bucketed call {qms:.1f} ms (threshold {small}), one launch per graph {qms_each:.1f} ms")
     ix.free()
     pe, pms = plain()
     log(f"plain per-graph builds: {pms:.1f} ms ({pe} entries)")
@@ -340,7 +360,11 @@ def bench_batch(args, dev, log):
                       "twin_vertices": st["twin_vertices"], "parallelism": "single-gpu"},
            "batched_build_ms": bms, "plain_build_ms": pms,
            "plain_entries_per_s": pe / (pms * 1e-3), "batched_speedup": pms / bms,
-           "query_ms": qms, "queries_per_s": 10000 * len(graphs) / (qms * 1e-3)}
+           "batched_breakdown_ms": {"device_total": st["ms_total"], "round_kernel": st["ms_round_kernel"],
+                                    "host_and_launch": bms - st["ms_total"],
+                                    "round_kernel_launches": st["round_kernel_launches"]},
+           "query_ms": qms, "queries_per_s": 10000 * len(graphs) / (qms * 1e-3),
+           "query_bucket_threshold": small, "query_ms_one_launch_per_graph": qms_each}
     print(json.dumps(out), flush=True)
 
 

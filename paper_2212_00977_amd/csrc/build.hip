@@ -338,7 +338,7 @@ static_assert((1 << (SPC_CBITS - 1)) >= SPC_ROUND_BLOCK, "candidate limit below 
 // remaining hubs are binary-searched
 constexpr uint32_t kTailSteps = SPC_TAIL_STEPS;
 #ifndef SPC_PROBE_GROUP
-#define SPC_PROBE_GROUP 4
+#define SPC_PROBE_GROUP 16
 #endif
 #ifndef SPC_PULL_UNROLL
 #define SPC_PULL_UNROLL 4

@@ -169,8 +169,20 @@ void pool_give(int dev, const Handle *h, size_t n) {
     c.pieces.insert(c.pieces.end(), h, h + n);
 }
 
+// Blocks of 1 MiB or more are rounded up to a size class (eight per power
+// of two), so that builds of graphs of different sizes ask for the same
+// few sizes and the cache serves them again.
+static size_t size_class(size_t bytes) {
+    if (bytes < (size_t(1) << 20)) return bytes;
+    size_t p = size_t(1) << 20;
+    while (p * 2 <= bytes) p <<= 1;
+    const size_t step = p / 8;
+    return (bytes + step - 1) / step * step;
+}
+
 void *cache_alloc(size_t bytes, size_t *got) {
     const int dev = current_device();
+    bytes = size_class(bytes);
     if (bytes >= kPoolMin && vmm_supported()) {
         const size_t n = (bytes + kPoolPiece - 1) / kPoolPiece;
         if (void *p = mapped_alloc(dev, n)) {

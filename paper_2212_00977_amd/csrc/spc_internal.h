@@ -165,10 +165,11 @@ __device__ __forceinline__ uint64_t lower_bound_hub(const typename Ent<DB>::T *a
 // ---------------------------------------------------------------------------
 constexpr size_t kPoolPiece = size_t(512) << 20;
 constexpr size_t kPoolMin = size_t(4) << 30;
-// Returns a block of at least `bytes` bytes (size rounded to 256 B; *got =
-// what it holds): pooled pieces for large blocks, else a cached block of at
-// most 1.125 times that size, else hipMalloc (after flushing the cache if
-// that fails).  nullptr on failure.
+// Returns a block of at least `bytes` bytes (size rounded to 256 B, and from
+// 1 MiB on to one of eight classes per power of two; *got = what it holds):
+// pooled pieces for large blocks, else a cached block of at most 1.125 times
+// that size, else hipMalloc (after flushing the cache if that fails).
+// nullptr on failure.
 void *cache_alloc(size_t bytes, size_t *got);
 void cache_free(void *p, size_t bytes);
 // give a block straight back: a large block's pieces to the pool, a small
