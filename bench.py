@@ -32,27 +32,28 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "label entries built/sec + SPC queries/sec (bit-exact); p50/p99 query latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_round_chunglu_n2e20_traffic.json")
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def source_hash() -> str:
+def source_hash(src: str = "build.hip") -> str:
     h = hashlib.sha256()
-    p = os.path.join(ROOT, "paper_2212_00977_amd", "csrc", "build.hip")
+    p = os.path.join(ROOT, "paper_2212_00977_amd", "csrc", src)
     h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launches: int):
-    """HBM bytes per launch of the round kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(name: str, src: str = "build.hip"):
+    """HBM bytes per launch of a kernel on a workload from the committed
+    rocprofv3 counter summary profiles/<name>_traffic.json, if it was taken
+    on the current source of the kernel (else None)."""
+    path = os.path.join(PROFILES, f"{name}_traffic.json")
+    if not os.path.exists(path):
         return None
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(path))
     except Exception:
         return None
-    if t.get("source_hash") != source_hash():
+    if t.get("source_hash") != source_hash(src):
         return None
     return t.get("bytes_per_launch")
 
@@ -569,10 +570,12 @@ def bench_rmat21(args, dev, log):
     # rooflines: the round kernel (the build's dominant kernel) and the query kernel
     rk = _roofline("k_round", st["alg_bytes_round_kernel"], st["ms_round_kernel"],
                    st["round_kernel_launches"],
-                   "kernel-counted: pulled entries (12 B), staged label entries, landmark-row "
-                   "slices needed, probe entries up to the first proving one, label offsets, "
-                   "survivors written; the oracle cannot rebuild this index, so the byte model "
-                   "from the definitions is reported for the same kernel on the Chung-Lu side line")
+                   "kernel-counted: pulled entries (12 B), u's label entries staged, landmark "
+                   "masks or row slices read, filter words looked up, label entries the probe "
+                   "searches read, label offsets, survivors written; the oracle cannot rebuild "
+                   "this index, so the byte model from the definitions is reported for the same "
+                   "kernel on the Chung-Lu side line",
+                   traffic=measured_traffic("k_round_rmat21"))
     qb = _profile_json("oracle_bytes_k_query_rmat21.json")
     q_roof = None
     if qb and qb.get("n") == g.n and qb.get("m") == g.m:
@@ -580,6 +583,7 @@ def bench_rmat21(args, dev, log):
                            "oracle: (|L(s)|+|L(t)|)(4+delta) + 16 k* + 8 + (delta+8+1) per query, "
                            f"mean over {qb['queries']} sampled pairs of the query stream "
                            f"(standard error {qb['stderr_bytes']:.0f} B)",
+                           traffic=measured_traffic("k_query_rmat21", "query.hip"),
                            bytes_per_query=qb["mean_bytes"])
     out = {
         "metric": METRIC,
@@ -717,7 +721,7 @@ def bench_chunglu(args, dev, log, steps, warmup, side=False):
     query_ms = float(np.mean([r["query_ms"] for r in runs]))
     rk_ms = float(np.mean([r["stats"]["ms_round_kernel"] for r in runs]))
     launches = st["round_kernel_launches"]
-    traffic = measured_traffic(launches)
+    traffic = measured_traffic("k_round_chunglu_n2e20")
     kc = _roofline("k_round", st["alg_bytes_round_kernel"], rk_ms, launches,
                    "kernel-counted (the kernel's own count of what it must read and write)",
                    traffic=traffic)
