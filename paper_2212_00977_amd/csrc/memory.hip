@@ -1,6 +1,6 @@
 // Per-device cache of device memory: a pool of physical pieces behind large
-// blocks and growable arrays (virtual memory API), and hipMalloc blocks kept
-// by size for the small ones.
+// blocks and growable arrays (virtual memory API), and hipMalloc segments
+// sub-allocated (best fit, split, coalesced on free) for the smaller ones.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "spc_internal.h"
+#include "suballoc.h"
 
 namespace spc {
 
@@ -16,10 +17,25 @@ namespace {
 
 using Handle = hipMemGenericAllocationHandle_t;
 
+// hipMalloc segments of the current device for the sub-allocator (not
+// mapped pieces: the runtime refuses copies from mapped ranges into pageable
+// host memory, which the exports make)
+struct HipSegments {
+    size_t round(size_t n) const { return n; }
+    void *allocate(size_t n) {
+        void *p = nullptr;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void release(void *p, size_t) { (void)hipFree(p); }
+};
+
 struct DeviceCache {
-    std::multimap<size_t, void *> free_blocks;  // size -> hipMalloc block
-    size_t bytes = 0;                           // held in free_blocks
-    std::vector<Handle> pieces;                 // free pieces of kPoolPiece bytes
+    SubAlloc<HipSegments> sub;   // blocks below kPoolMin
+    std::vector<Handle> pieces;  // free pieces of kPoolPiece bytes
 };
 
 // a large block: an address range with pooled pieces mapped behind it
@@ -29,8 +45,8 @@ struct Mapped {
     std::vector<Handle> pieces;
 };
 
-std::mutex g_mu;  // guards g_cache and g_mapped
-std::vector<DeviceCache> g_cache;
+std::recursive_mutex g_mu;  // guards g_cache and g_mapped
+std::map<int, DeviceCache> g_cache;
 std::map<void *, Mapped> g_mapped;
 
 int current_device() {
@@ -42,16 +58,10 @@ int current_device() {
     return dev;
 }
 
-DeviceCache &cache_of(int dev) {
-    if ((size_t)dev >= g_cache.size()) g_cache.resize((size_t)dev + 1);
-    return g_cache[(size_t)dev];
-}
+DeviceCache &cache_of(int dev) { return g_cache[dev]; }
 
-void release_blocks_locked(DeviceCache &c) {
-    for (auto &kv : c.free_blocks) (void)hipFree(kv.second);
-    c.free_blocks.clear();
-    c.bytes = 0;
-}
+// whole free segments back to the runtime (the device must be current)
+void release_blocks_locked(DeviceCache &c) { c.sub.trim(0); }
 
 void release_pieces_locked(DeviceCache &c) {
     for (Handle h : c.pieces) (void)hipMemRelease(h);
@@ -103,7 +113,7 @@ void *mapped_alloc(int dev, size_t n) {
         pool_give(dev, hs.data(), hs.size());
         return nullptr;
     }
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     Mapped &m = g_mapped[va];
     m.bytes = bytes;
     m.dev = dev;
@@ -115,7 +125,7 @@ void *mapped_alloc(int dev, size_t n) {
 bool mapped_free(void *p) {
     Mapped m;
     {
-        std::lock_guard<std::mutex> lk(g_mu);
+        std::lock_guard<std::recursive_mutex> lk(g_mu);
         auto it = g_mapped.find(p);
         if (it == g_mapped.end()) return false;
         m = std::move(it->second);
@@ -133,7 +143,7 @@ bool mapped_free(void *p) {
 bool pool_take(int dev, size_t n, std::vector<Handle> *out) {
     out->clear();
     {
-        std::lock_guard<std::mutex> lk(g_mu);
+        std::lock_guard<std::recursive_mutex> lk(g_mu);
         DeviceCache &c = cache_of(dev);
         while (out->size() < n && !c.pieces.empty()) {
             out->push_back(c.pieces.back());
@@ -141,19 +151,13 @@ bool pool_take(int dev, size_t n, std::vector<Handle> *out) {
         }
     }
     const hipMemAllocationProp prop = device_prop(dev);
-    bool flushed = false;
     while (out->size() < n) {
         Handle h{};
-        if (hipMemCreate(&h, kPoolPiece, &prop, 0) == hipSuccess) {
-            out->push_back(h);
-            continue;
+        if (hipMemCreate(&h, kPoolPiece, &prop, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            break;
         }
-        (void)hipGetLastError();
-        if (flushed) break;
-        // the cached hipMalloc blocks may hold what is missing
-        std::lock_guard<std::mutex> lk(g_mu);
-        release_blocks_locked(cache_of(dev));
-        flushed = true;
+        out->push_back(h);
     }
     if (out->size() < n) {
         pool_give(dev, out->data(), out->size());
@@ -164,99 +168,78 @@ bool pool_take(int dev, size_t n, std::vector<Handle> *out) {
 }
 
 void pool_give(int dev, const Handle *h, size_t n) {
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     DeviceCache &c = cache_of(dev);
     c.pieces.insert(c.pieces.end(), h, h + n);
 }
 
-// Blocks of 1 MiB or more are rounded up to a size class (eight per power
-// of two), so that builds of graphs of different sizes ask for the same
-// few sizes and the cache serves them again.
-static size_t size_class(size_t bytes) {
-    if (bytes < (size_t(1) << 20)) return bytes;
-    size_t p = size_t(1) << 20;
-    while (p * 2 <= bytes) p <<= 1;
-    const size_t step = p / 8;
-    return (bytes + step - 1) / step * step;
+static void reclaim_segments(int dev) {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    cache_of(dev).sub.trim(0);  // whole free segments back to the runtime
 }
 
 void *cache_alloc(size_t bytes, size_t *got) {
     const int dev = current_device();
-    bytes = size_class(bytes);
     if (bytes >= kPoolMin && vmm_supported()) {
         const size_t n = (bytes + kPoolPiece - 1) / kPoolPiece;
-        if (void *p = mapped_alloc(dev, n)) {
-            *got = n * kPoolPiece;
-            return p;
+        for (int attempt = 0; attempt < 2; attempt++) {
+            if (void *p = mapped_alloc(dev, n)) {
+                *got = n * kPoolPiece;
+                return p;
+            }
+            if (attempt == 0) reclaim_segments(dev);  // free segments hold memory
         }
-        // out of memory with the pool emptied: hipMalloc will not do better
-        std::lock_guard<std::mutex> lk(g_mu);
-        if (cache_of(dev).pieces.empty()) return nullptr;
+        return nullptr;
     }
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        DeviceCache &c = cache_of(dev);
-        auto it = c.free_blocks.lower_bound(bytes);
-        if (it != c.free_blocks.end() && it->first <= bytes + bytes / 8) {
-            void *p = it->second;
-            *got = it->first;
-            c.bytes -= it->first;
-            c.free_blocks.erase(it);
-            return p;
-        }
-    }
-    void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            release_blocks_locked(cache_of(dev));
-            release_pieces_locked(cache_of(dev));
-        }
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
-        }
-    }
-    *got = bytes;
-    return p;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    DeviceCache &c = cache_of(dev);
+    if (void *p = c.sub.alloc(bytes, got)) return p;
+    // out of memory: whole free segments and pooled pieces go back to the
+    // runtime, then retry
+    c.sub.trim(0);
+    release_pieces_locked(c);
+    return c.sub.alloc(bytes, got);
 }
 
-void cache_free(void *p, size_t bytes) {
+void cache_free(void *p, size_t) {
     if (!p) return;
     if (mapped_free(p)) return;
-    std::lock_guard<std::mutex> lk(g_mu);
-    DeviceCache &c = cache_of(current_device());
-    c.free_blocks.emplace(bytes, p);
-    c.bytes += bytes;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    if (cache_of(current_device()).sub.release(p)) return;
+    for (auto &kv : g_cache)  // a block of another device
+        if (kv.second.sub.release(p)) return;
 }
 
-void cache_release(void *p) {
-    if (!p || mapped_free(p)) return;
-    (void)hipFree(p);
-}
+// a sub-allocated block cannot go back on its own: it is freed into its
+// segment, which a trim returns once it is whole
+void cache_release(void *p) { cache_free(p, 0); }
 
 void cache_trim(size_t max_bytes) {
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     DeviceCache &c = cache_of(current_device());
-    while (c.bytes + c.pieces.size() * kPoolPiece > max_bytes && !c.free_blocks.empty()) {
-        auto it = std::prev(c.free_blocks.end());  // largest first
-        (void)hipFree(it->second);
-        c.bytes -= it->first;
-        c.free_blocks.erase(it);
-    }
-    while (c.bytes + c.pieces.size() * kPoolPiece > max_bytes && !c.pieces.empty()) {
+    // pooled pieces first (they back the largest blocks), then whole free
+    // segments, largest first: the segments serve blocks of any size
+    while (c.sub.free_bytes() + c.pieces.size() * kPoolPiece > max_bytes && !c.pieces.empty()) {
         (void)hipMemRelease(c.pieces.back());
         c.pieces.pop_back();
     }
+    if (c.sub.free_bytes() > max_bytes) c.sub.trim(max_bytes);
 }
 
 void cache_flush() {
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto &c : g_cache) {
-        release_blocks_locked(c);
-        release_pieces_locked(c);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    for (auto &kv : g_cache) {
+        // segments are freed with their device current
+        if (have && kv.first != cur && hipSetDevice(kv.first) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        release_blocks_locked(kv.second);
+        release_pieces_locked(kv.second);
     }
+    if (have) (void)hipSetDevice(cur);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,7 +323,10 @@ spc_status VArray::ensure(size_t bytes, size_t *added) {
         if (piece >= kPoolPiece && reserved_ - mapped_ >= kPoolPiece) {
             const size_t n = std::min((piece + kPoolPiece - 1) / kPoolPiece, (reserved_ - mapped_) / kPoolPiece);
             std::vector<Handle> hs;
-            if (!pool_take(device_, n, &hs)) return SPC_ERR_OUT_OF_MEMORY;
+            if (!pool_take(device_, n, &hs)) {
+                reclaim_segments(device_);  // free segments hold memory
+                if (!pool_take(device_, n, &hs)) return SPC_ERR_OUT_OF_MEMORY;
+            }
             if (map_pieces(hs.data(), n, kPoolPiece) != SPC_OK) {
                 pool_give(device_, hs.data(), n);
                 return SPC_ERR_DEVICE;

@@ -160,16 +160,16 @@ __device__ __forceinline__ uint64_t lower_bound_hub(const typename Ent<DB>::T *a
 //    kPoolPiece bytes of physical memory mapped behind them (virtual memory
 //    API); a freed block's pieces go to the device's piece pool and back
 //    into any later block, whatever its size;
-//  * smaller blocks come from hipMalloc and are kept by size, and reused by
-//    later allocations of a similar size.
+//  * smaller blocks are carved out of hipMalloc segments (suballoc.h: best
+//    fit, split, coalesced on free), so freed memory serves requests of any
+//    size.
 // ---------------------------------------------------------------------------
 constexpr size_t kPoolPiece = size_t(512) << 20;
 constexpr size_t kPoolMin = size_t(4) << 30;
-// Returns a block of at least `bytes` bytes (size rounded to 256 B, and from
-// 1 MiB on to one of eight classes per power of two; *got = what it holds):
-// pooled pieces for large blocks, else a cached block of at most 1.125 times
-// that size, else hipMalloc (after flushing the cache if that fails).
-// nullptr on failure.
+// Returns a block of at least `bytes` bytes (*got = what it holds, 256-byte
+// aligned): pooled pieces for large blocks, else a block of a cached segment
+// or of a new hipMalloc segment (after giving back whole free segments and
+// pooled pieces if that fails).  nullptr on failure.
 void *cache_alloc(size_t bytes, size_t *got);
 void cache_free(void *p, size_t bytes);
 // give a block straight back: a large block's pieces to the pool, a small
@@ -177,8 +177,8 @@ void cache_free(void *p, size_t bytes);
 void cache_release(void *p);
 // give every cached block and pooled piece of every device back
 void cache_flush();
-// give the largest cached blocks, then pooled pieces, of the current device
-// back until at most max_bytes stay cached
+// give pooled pieces, then whole free segments (largest first), of the
+// current device back until at most max_bytes stay cached
 void cache_trim(size_t max_bytes);
 // n pieces of kPoolPiece bytes for device dev (pooled ones first, then new
 // ones); false, with nothing taken, when the device is out of memory
