@@ -316,8 +316,14 @@ __global__ void k_land_widen(const uint8_t *src, uint16_t *dst, uint64_t n) {
 #define SPC_LBITS 11
 #endif
 constexpr int kLBits = SPC_LBITS;
-constexpr int kLCap = 1 << kLBits;   // L(u) hash slots
-constexpr int kLStage = kLCap / 2;   // staged entries (load <= 1/2)
+#ifndef SPC_LBITS_LONG
+#define SPC_LBITS_LONG 12
+#endif
+// the instances of rounds past kMergeRound (long-diameter graphs, small
+// candidate sets per puller, labels of about a thousand entries) take a
+// table of 2^12 8-bit-label entries or 2^11 16-bit ones (16 KB; three
+// workgroups per CU by LDS)
+constexpr int kLBitsLong = SPC_LBITS_LONG;
 #ifndef SPC_CBITS
 #define SPC_CBITS 10
 #endif
@@ -461,7 +467,7 @@ __device__ __forceinline__ uint32_t gallop_u32(const uint32_t *a, uint32_t c, ui
     return lo + lower_bound_u32(a + lo, end - lo, key);
 }
 
-template <int DB>
+template <int DB, int LB>
 struct LabelLookup {
     using E = typename Ent<DB>::T;
     const E *tab;     // LDS table
@@ -470,12 +476,12 @@ struct LabelLookup {
     uint32_t x;       // hubs >= x live in the tail
     __device__ __forceinline__ uint32_t operator()(uint32_t h) const {
         if (h < x) {
-            uint32_t s = hash_slot(h, kLBits);
+            uint32_t s = hash_slot(h, LB);
             while (true) {
                 E e = tab[s];
                 if (e == (E)~(E)0) return kNone;
                 if (e_hub<DB>(e) == h) return e_dist<DB>(e);
-                s = (s + 1) & (kLCap - 1);
+                s = (s + 1) & ((1u << LB) - 1);
             }
         }
         uint64_t p = lower_bound_hub<DB>(tail, ntail, h);
@@ -496,6 +502,11 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     using E = typename Ent<DB>::T;
     using LT = typename Land<DB>::T;
     using LW = typename Land<DB>::W;
+    // L(u) hash: 2^LB slots (in the long-diameter instances the same bytes
+    // for both entry widths), at most half of them staged
+    constexpr int LB = TM ? kLBitsLong - (DB == 16 ? 1 : 0) : kLBits;
+    constexpr int kLCap = 1 << LB;
+    constexpr int kLStage = kLCap / 2;
     __shared__ E ltab[kLCap];
     __shared__ LW lrow[kLand / 4];
     __shared__ uint32_t ckey[kCCap];
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     auto stage = [&](const E *src, uint32_t cnt) {
         for (uint32_t i = tid; i < cnt; i += RB) {
             E e = src[i];
-            uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
+            uint32_t s = hash_slot(e_hub<DB>(e), LB);
             while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
         }
     };
@@ -572,14 +583,14 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
         npu = a.prev_off[u + 1] - q0 - qs;
     }
     // the table, which holds the current chunk's hubs of u's label
-    LabelLookup<DB> tabl;
+    LabelLookup<DB, LB> tabl;
     tabl.tab = ltab;
     tabl.tail = lab + nsp;
     tabl.ntail = 0;
     tabl.x = 0xFFFFFFFFu;
     // u's whole label past the landmarks for the probes: the table when
     // staged once, else HBM
-    LabelLookup<DB> look = tabl;
+    LabelLookup<DB, LB> look = tabl;
     if (big) {
         look.tail = lab;
         look.ntail = nsp;
@@ -690,7 +701,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                 const E e = j < nsp ? lab[j] : (E)0;
                 const bool in = j < nsp && e_hub<DB>(e) < hi;  // a prefix of the trip
                 if (in) {
-                    uint32_t s = hash_slot(e_hub<DB>(e), kLBits);
+                    uint32_t s = hash_slot(e_hub<DB>(e), LB);
                     while (atomicCAS(&ltab[s], kEmptyE, e) != kEmptyE) s = (s + 1) & (kLCap - 1);
                 }
                 const uint32_t cnt = (uint32_t)__syncthreads_count(in);

@@ -35,8 +35,8 @@ EXPORTS = ["spc_build_index", "spc_build_index_batch", "spc_query_batch", "spc_f
 # overflow and narrowing, many chunks per puller, many batches per round,
 # pullers with a buffer of their own) and a 16-pair list of filter hits (so
 # the probes that search at once run too).
-SMALL_TABLES = ["-DSPC_LBITS=7", "-DSPC_CBITS=9", "-DSPC_TEMP_LOG2=14", "-DSPC_TEMP_MAX_LOG2=14",
-                "-DSPC_FILT_LIST=16"]
+SMALL_TABLES = ["-DSPC_LBITS=7", "-DSPC_LBITS_LONG=7", "-DSPC_CBITS=9", "-DSPC_TEMP_LOG2=14",
+                "-DSPC_TEMP_MAX_LOG2=14", "-DSPC_FILT_LIST=16"]
 SMALL_TABLES_PATH = os.path.join(LIBDIR, "libspc_smalltab.so")
 
 
