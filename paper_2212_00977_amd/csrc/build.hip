@@ -360,6 +360,9 @@ constexpr int kPullUnroll = SPC_PULL_UNROLL;
 #endif
 constexpr int kProbeUnroll = SPC_PROBE_UNROLL;
 constexpr int kFiltProbes = 2;
+// older label entries per membership-filter word: 2 (32 bits an entry)
+// where the memory allows, else 4
+constexpr uint32_t kFiltShiftLo = 1, kFiltShiftHi = 2;
 #ifndef SPC_FILT_LIST
 #define SPC_FILT_LIST 512
 #endif
@@ -402,10 +405,12 @@ struct RoundArgs {
     uint64_t *tmp_cnt;
     uint32_t *surv;
     unsigned long long *ctr;  // raw, merged, kept, tail, staged, row bytes, headers, filter bytes
-    // membership filter of L_{<=d-2}'s (row, hub, distance) triples past the landmarks
-    // (null: none this round); filt_mask = words - 1
+    // membership filter of L_{<=d-2}'s (row, hub, distance) triples past the
+    // landmarks (null: none this round), filt_words 64-bit words, 2^filt_shift
+    // older entries a word
     const unsigned long long *filt = nullptr;
-    uint64_t filt_mask = 0;
+    uint64_t filt_words = 0;
+    uint32_t filt_shift = kFiltShiftHi;
 };
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t h, int bits) {
@@ -416,8 +421,11 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t h, int bits) {
 // labels past the landmarks: a Bloom filter with one 64-bit word per key, in
 // which a key sets (and a lookup tests) up to 4 bits.  A clear bit proves
 // the triple absent; a hit is confirmed in the label itself.  Keys are mixed
-// with the 64-bit finalizer of MurmurHash3; the low bits pick the word, the
-// top 24 bits the 4 bit positions.
+// with the 64-bit finalizer of MurmurHash3; the low 32 bits pick the word
+// among the row's own ones, the top 24 bits the 4 bit positions.  A row owns
+// the words its older label's entries span at 2^s entries a word
+// (neighbouring rows may share an end word), so the lookups of one candidate
+// row fall in a few cache lines rather than all over the filter.
 __device__ __forceinline__ uint64_t filt_mix(uint32_t row, uint32_t hub, uint32_t dist) {
     uint64_t x = (((uint64_t)row << 32) | hub) ^ ((uint64_t)dist * 0x9E3779B97F4A7C15ull);
     x ^= x >> 33;
@@ -426,6 +434,19 @@ __device__ __forceinline__ uint64_t filt_mix(uint32_t row, uint32_t hub, uint32_
     x *= 0xc4ceb9fe1a85ec53ull;
     x ^= x >> 33;
     return x;
+}
+// row words [x, x + y) from the row's older label offsets [o0, o1), within
+// the filter's nw >= 1 words whatever the offsets
+__device__ __forceinline__ uint2 filt_region(uint64_t o0, uint64_t o1, uint64_t nw, uint32_t s) {
+    uint64_t b1 = (o1 + (1ull << s) - 1) >> s;
+    if (b1 > nw) b1 = nw;
+    if (b1 == 0) b1 = 1;
+    uint64_t b0 = o0 >> s;
+    if (b0 >= b1) b0 = b1 - 1;
+    return make_uint2((uint32_t)b0, (uint32_t)(b1 - b0));
+}
+__device__ __forceinline__ uint32_t filt_word(uint2 reg, uint64_t x) {
+    return reg.x + (uint32_t)(((x & 0xFFFFFFFFull) * reg.y) >> 32);
 }
 __device__ __forceinline__ unsigned long long filt_bits(uint64_t x) {
     return (1ull << ((x >> 40) & 63)) | (1ull << ((x >> 46) & 63)) | (1ull << ((x >> 52) & 63)) |
@@ -517,6 +538,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     __shared__ uint8_t lkeep[kULimit];   // 0 pruned, 1 kept, 2 needs the tail check
     // candidates that need the tail check (probe phase)
     __shared__ uint16_t tlist[kULimit];
+    __shared__ uint2 freg[kULimit];      // filtered probes: tlist[t]'s filter words
     __shared__ uint64_t nb_start[RB];
     __shared__ uint32_t nb_off[RB];
     __shared__ uint32_t red32[RW];
@@ -998,17 +1020,26 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
             // positives) are listed, then binary-searched in w's label, one
             // per thread.
             // Pairs are numbered candidate by candidate: pre[t] is the first
-            // pair of tlist[t] (the candidate table's key array is idle here).
+            // pair of tlist[t] (the candidate table's key array is idle here),
+            // freg[t] its row's filter words.
             uint32_t *pre = ckey;
             uint32_t *vlist = reinterpret_cast<uint32_t *>(nb_start);  // (t << 16) | j
             constexpr uint32_t kVCap = kFiltList < RB * 2 ? kFiltList : RB * 2;  // nb_start's bytes
             uint32_t P = 0;
             {
                 uint32_t cq[PER], sum = 0;
+                uint64_t o0[PER], o1[PER];
 #pragma unroll
                 for (int q = 0; q < PER; q++) {
                     const uint32_t t = PER * tid + q;
-                    cq[q] = t < T ? (uint32_t)lower_bound_hub<DB>(pl, npu, lhub[tlist[t]]) : 0;  // >= 1
+                    cq[q] = 0;
+                    o0[q] = o1[q] = 0;
+                    if (t < T) {
+                        const uint32_t w = lhub[tlist[t]];
+                        o0[q] = a.prev_off[w + poff];
+                        o1[q] = a.prev_off[w + poff + 1];
+                        cq[q] = (uint32_t)lower_bound_hub<DB>(pl, npu, w);  // >= 1
+                    }
                     sum += cq[q];
                 }
                 uint32_t ex = block_excl_scan<uint32_t, RW>(sum, red32, P);
@@ -1018,6 +1049,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                     if (t < T) {
                         pre[t] = ex;
                         ex += cq[q];
+                        freg[t] = filt_region(o0[q], o1[q], a.filt_words, a.filt_shift);
                         lkeep[tlist[t]] = 1;  // until a search proves a shorter path
                     }
                 }
@@ -1030,6 +1062,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
             // binary search of u's entry pl[j] in w = lhub[tlist[t]]'s label
             auto search = [&](uint32_t t, uint32_t j) {
                 const uint32_t i = tlist[t];
+                if (!lkeep[i]) return;  // another pair has proved it already
                 const uint32_t wr = lhub[i] + poff;
                 const uint64_t q0 = a.prev_off[wr];
                 const uint64_t np = a.prev_off[wr + 1] - q0 - 1;  // the last entry is (w, 0)
@@ -1077,6 +1110,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                         jq[r] = p - pre[own];
                         const E e = pl[jq[r]];
                         const uint32_t wr = lhub[tlist[own]] + poff, h = e_hub<DB>(e);
+                        const uint2 reg = freg[own];
                         const uint32_t nd = d - 1 - e_dist<DB>(e);  // d_w in [1, nd]; d_u <= d-2
                         hq[r] = nd > (uint32_t)kFiltProbes;
 #pragma unroll
@@ -1084,7 +1118,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                             if (!hq[r] && (uint32_t)k < nd) {
                                 const uint64_t x = filt_mix(wr, h, (uint32_t)k + 1);
                                 mq[r][k] = filt_bits(x);
-                                wq[r][k] = a.filt[x & a.filt_mask];
+                                wq[r][k] = a.filt[filt_word(reg, x)];
                                 my_filt += sizeof(unsigned long long);
                             }
                     }
@@ -1570,15 +1604,14 @@ __global__ void k_lc_init(uint32_t N, uint32_t nreal, const uint32_t *gbase, uin
     if (v < N) lc[v] = (h - (gbase ? gbase[v] : 0)) < (uint32_t)kLand ? 1u : 0u;
 }
 
-// Widen packed entries from 8-bit to 16-bit distances.
-// The round's membership filter: cleared, then every row's older label
-// entries past its landmarks, but its own entry (r, 0), inserted with their
-// distances (one wave per row).
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+// The round's membership filter: cleared, then every row's older label
+// entries past its landmarks, but its own entry (r, 0), inserted with their
+// distances into the row's words (one wave per row).
 __global__ void k_filt_clear(unsigned long long *f, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -1586,19 +1619,23 @@ __global__ void k_filt_clear(unsigned long long *f, uint64_t n) {
 }
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_filt_insert(uint32_t N, const uint64_t *off, const void *hd,
-                                                        const uint32_t *lc, unsigned long long *f, uint64_t mask) {
+                                                        const uint32_t *lc, unsigned long long *f, uint64_t nw,
+                                                        uint32_t shift) {
     using E = typename Ent<DB>::T;
     const uint32_t r = blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (r >= N) return;
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t b = off[r] + lc[r], e = off[r + 1];
+    const uint64_t o0 = off[r], b = o0 + lc[r], e = off[r + 1];
     if (e <= b + 1) return;
+    const uint2 reg = filt_region(o0, e, nw, shift);
     const E *lab = static_cast<const E *>(hd);
     for (uint64_t i = b + lane; i < e - 1; i += 64) {
         const uint64_t x = filt_mix(r, e_hub<DB>(lab[i]), e_dist<DB>(lab[i]));
-        atomicOr(&f[x & mask], filt_bits(x));
+        atomicOr(&f[filt_word(reg, x)], filt_bits(x));
     }
 }
+
+// Widen packed entries from 8-bit to 16-bit distances.
 
 __global__ void k_widen(const uint32_t *src, uint64_t *dst, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1751,6 +1788,7 @@ struct Build {
     std::vector<uint32_t *> rlen;
     bool vmm = false;              // round arrays grow in place (virtual memory API)
     bool filter = true;            // membership filters for the prune probes
+    bool filter_dense = true;      // 32 bits per entry where the memory allows
     uint64_t dev_bytes = 0;        // device memory size (bounds reservations)
     std::vector<std::unique_ptr<VArray>> vhub, vcnt;
     uint64_t **rs_tab = nullptr;  // device copies of the per-round pointers
@@ -2371,21 +2409,25 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         B.tmp_cap = tmp_want;
     }
     // Membership filter of L_{<=d-2}'s (row, hub, distance) triples for the prune probes
-    // (16 bits per entry, 1/8 of the memory left at most), where inserting
-    // the older labels costs less than a quarter of the round's pulls
+    // (32 or else 16 bits per entry, 1/8 of the memory left at most, row
+    // words indexed in 32 bits), where inserting the older labels costs less
+    // than a quarter of the round's pulls
     unsigned long long *filt = nullptr;
     uint64_t filt_words = 0;
+    uint32_t filt_shift = kFiltShiftHi;
     if (B.filter && d >= 3 && !push && !fast1 && B.entries_prev > 0 && B.entries_prev * 4 <= total_raw) {
-        uint64_t words = 1024;
-        while (words < B.entries_prev / 4) words <<= 1;
         const uint64_t cap_bytes = B.arena.budget() ? B.arena.budget() : B.dev_bytes;
         const uint64_t left = cap_bytes > B.arena.used() ? cap_bytes - B.arena.used() : 0;
-        if (words * 8 <= left / 8 && B.arena.alloc(&filt, words) == SPC_OK) {
+        auto words_at = [&](uint32_t sh) { return (B.entries_prev + (1ull << sh) - 1) >> sh; };
+        auto fits = [&](uint32_t sh) { return words_at(sh) < (1ull << 32) && words_at(sh) * 8 <= left / 8; };
+        filt_shift = B.filter_dense && fits(kFiltShiftLo) ? kFiltShiftLo : kFiltShiftHi;
+        const uint64_t words = words_at(filt_shift);
+        if (fits(filt_shift) && B.arena.alloc(&filt, words) == SPC_OK) {
             filt_words = words;
             hipLaunchKernelGGL(k_filt_clear, dim3(grid_stride(words)), dim3(kBlock), 0, B.st, filt, words);
             SPC_LAUNCHED();
             hipLaunchKernelGGL(k_filt_insert<DB>, dim3(grid_for(N, kWaves)), dim3(kBlock), 0, B.st, N,
-                               B.lab_off2, B.lab_hd2, B.lc2, filt, words - 1);
+                               B.lab_off2, B.lab_hd2, B.lc2, filt, words, filt_shift);
             SPC_LAUNCHED();
         } else {
             filt = nullptr;
@@ -2513,7 +2555,8 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         ra.nxt = B.nxt;
         ra.ctr = B.ctr;
         ra.filt = filt;
-        ra.filt_mask = filt_words ? filt_words - 1 : 0;
+        ra.filt_words = filt_words;
+        ra.filt_shift = filt_shift;
         SPC_HIP(hipEventRecord(B.ev_a, B.st));
         // from round 17 on the graph has a long diameter: there, neighbours'
         // labels are nearly the same set, which the tail merge exploits
@@ -3058,9 +3101,11 @@ spc_status build_impl(const spc_graph *gs, uint32_t k, const spc_build_opts *o, 
         // SPC_VMM=0 in the environment turns in-place growth off
         const char *ev = std::getenv("SPC_VMM");
         B.vmm = vmm_supported() && !(ev && ev[0] == '0');
-        // SPC_FILTER=0 turns the prune probes' membership filter off
+        // SPC_FILTER=0 turns the prune probes' membership filter off, 16
+        // keeps it at 16 bits per entry (the density where memory is short)
         const char *ef = std::getenv("SPC_FILTER");
         B.filter = !(ef && ef[0] == '0');
+        B.filter_dense = !(ef && std::strcmp(ef, "16") == 0);
     }
     B.N = (uint32_t)rows64;
     B.NNZ = slots64;
