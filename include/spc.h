@@ -224,7 +224,15 @@ spc_status spc_build_index_batch(const spc_graph *gs, uint32_t k, const spc_buil
  * unreachable); otherwise the labels of the two representatives are joined,
  * each common hub other than the representatives counting once per member
  * of its class (a shortest path meets a class at most once, and any member
- * can take the place of the one it meets). */
+ * can take the place of the one it meets).
+ * Queries are independent ("Query Evaluation in Parallel"): a batch of at
+ * least 2^20 is answered grouped by the label the kernel stages (the longer
+ * of L(s), L(t) when undirected, L_out(s) when directed), so the queries that
+ * share it run side by side and read it from cache; answers are the same and
+ * are written by query index.  That grouping takes 8 bytes per query (at most
+ * 2^24 at a time) and 16 per label row of scratch from the device's
+ * stream-ordered allocator on `stream` (SPC_ERR_OUT_OF_MEMORY if it has
+ * none); SPC_QUERY_ORDER=0 in the environment turns it off. */
 spc_status spc_query_batch(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
                            const uint32_t *t, uint64_t nq, void *dist_out, uint64_t *count_out,
                            uint8_t *flags_out, void *stream);

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 
 #include <type_traits>
@@ -174,8 +175,17 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
         rs = uni(a.rank_of[vbase + s]);
         rt = uni(a.rank_of[vbase + t]) + a.t_row;
     }
-    const uint64_t as = a.lab_off[rs], na = a.lab_off[rs + 1] - as;
-    const uint64_t bs = a.lab_off[rt], nb = a.lab_off[rt + 1] - bs;
+    uint64_t as = a.lab_off[rs], na = a.lab_off[rs + 1] - as;
+    uint64_t bs = a.lab_off[rt], nb = a.lab_off[rt + 1] - bs;
+    // an undirected query is symmetric: the longer label is the staged one
+    // (the binary searches in the stage are per streamed entry)
+    if (a.t_row == 0 && na < nb) {
+        const uint64_t x = as, y = na;
+        as = bs;
+        na = nb;
+        bs = x;
+        nb = y;
+    }
     uint32_t best = 0xFFFFFFFFu;
     uint64_t sum = 0;
     uint64_t ia = 0, ib = 0;
@@ -306,6 +316,47 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
         a.count_out[qi] = cout;
         if (a.flags_out) a.flags_out[qi] = fl;
     }
+}
+
+// Locality order of a large batch: the queries grouped by the label row the
+// query kernel stages (the longer label of an undirected query, L(s) of a
+// directed one), so that the queries sharing it run side by side and find it
+// in cache.  A counting sort: row[q] and per-row counts, their exclusive
+// scan, then each query at its row's next slot (the order within a row is
+// arbitrary: answers are written by query index).  Invalid queries go to
+// row 0.  Single-graph launches (no gid).
+__global__ void k_qrow(QueryArgs a, uint32_t *row, uint32_t *cnt) {
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.nq;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = a.s[q], t = a.t[q];
+        const uint32_t lim = a.red_root ? a.on : a.gn;
+        uint32_t r = 0;
+        if (s < lim && t < lim) {
+            uint32_t rs, rt;
+            if (a.red_root) {
+                rs = a.rank_of[a.red_root[a.obase + s]];
+                rt = a.rank_of[a.red_root[a.obase + t]];
+            } else {
+                rs = a.rank_of[a.vbase + s];
+                rt = a.rank_of[a.vbase + t] + a.t_row;
+            }
+            const uint64_t na = a.lab_off[rs + 1] - a.lab_off[rs];
+            const uint64_t nb = a.lab_off[rt + 1] - a.lab_off[rt];
+            r = (a.t_row == 0 && na < nb) ? rt : rs;
+        }
+        row[q] = r;
+        atomicAdd(&cnt[r], 1u);
+    }
+}
+__global__ void k_qplace(const uint32_t *row, uint64_t nq, uint64_t *next, uint32_t *perm) {
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
+         q += (uint64_t)gridDim.x * blockDim.x)
+        perm[atomicAdd((unsigned long long *)&next[row[q]], 1ull)] = (uint32_t)q;
+}
+__global__ void k_qfill0(uint32_t *p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 // Bucketing of a query batch by its work, |L(s)| + |L(t)|: queries at most
@@ -481,11 +532,68 @@ spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, 
 
 }  // namespace
 
+// batches of at least this many queries are answered in locality order
+// (k_qrow) unless SPC_QUERY_ORDER=0 in the environment
+constexpr uint64_t kOrderMin = 1ull << 20;
+
 spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
                       uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
                       hipStream_t st) {
     if (!ix) return SPC_ERR_INVALID_ARG;
-    return query_run(ix, graph_id, s, t, nq, dist_out, count_out, flags_out, ix->query_cfg, st);
+    const char *eo = std::getenv("SPC_QUERY_ORDER");
+    if (nq < kOrderMin || (eo && eo[0] == '0'))
+        return query_run(ix, graph_id, s, t, nq, dist_out, count_out, flags_out, ix->query_cfg, st);
+    if (graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
+    if (!s || !t || !dist_out || !count_out) return SPC_ERR_INVALID_ARG;
+    QueryArgs a = index_args(ix);
+    a.vbase = ix->vbase[graph_id];
+    a.gn = ix->gn[graph_id];
+    a.obase = ix->reduced ? ix->obase[graph_id] : 0;
+    a.on = ix->reduced ? ix->on[graph_id] : 0;
+    // scratch in stream order, freed after the launches that read it:
+    // row and perm per query, counts and offsets per label row, scan space
+    const uint64_t rows = (uint64_t)ix->n + ix->nreal;
+    const uint64_t np = std::min<uint64_t>(nq, kMultiChunk);
+    const uint64_t wse = scan_ws_elems(rows + 1);
+    const uint64_t bytes = (2 * np + rows + 64) * sizeof(uint32_t) + (rows + 1 + wse + 8) * sizeof(uint64_t);
+    void *buf = nullptr;
+    if (hipMallocAsync(&buf, bytes, st) != hipSuccess) return SPC_ERR_OUT_OF_MEMORY;
+    uint64_t *next = static_cast<uint64_t *>(buf);
+    uint64_t *ws = next + rows + 1;
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + wse + 8);
+    uint32_t *row = cnt + rows;
+    uint32_t *perm = row + np;
+    const size_t dsz = ix->out_bits == 8 ? 1 : 2;
+    spc_status r = SPC_OK;
+    for (uint64_t q0 = 0; q0 < nq && r == SPC_OK; q0 += kMultiChunk) {
+        const uint64_t nc = std::min<uint64_t>(kMultiChunk, nq - q0);
+        QueryArgs c = a;
+        c.s = s + q0;
+        c.t = t + q0;
+        c.nq = nc;
+        c.dist_out = static_cast<char *>(dist_out) + q0 * dsz;
+        c.count_out = count_out + q0;
+        c.flags_out = flags_out ? flags_out + q0 : nullptr;
+        const uint32_t gq = std::min<uint32_t>(grid1(nc), 8192);
+        hipLaunchKernelGGL(k_qfill0, dim3(std::min<uint32_t>(grid1(rows), 4096)), dim3(kBlock), 0, st, cnt,
+                           rows);
+        hipLaunchKernelGGL(k_qrow, dim3(gq), dim3(kBlock), 0, st, c, row, cnt);
+        if (hipGetLastError() != hipSuccess) {
+            r = SPC_ERR_DEVICE;
+            break;
+        }
+        r = scan_u32(cnt, next, rows, ws, st);
+        if (r != SPC_OK) break;
+        hipLaunchKernelGGL(k_qplace, dim3(gq), dim3(kBlock), 0, st, row, nc, next, perm);
+        if (hipGetLastError() != hipSuccess) {
+            r = SPC_ERR_DEVICE;
+            break;
+        }
+        c.perm = perm;
+        r = launch_query(ix->dist_bits, ix->out_bits, ix->query_cfg, c, st);
+    }
+    if (hipFreeAsync(buf, st) != hipSuccess && r == SPC_OK) r = SPC_ERR_DEVICE;
+    return r;
 }
 
 spc_status query_multi_impl(const spc_index *ix, const uint32_t *gid, const uint32_t *s,

@@ -319,7 +319,7 @@ class Arena {
 };
 
 // ---------------------------------------------------------------------------
-// Library-wide primitives (scan.hip, sort.hip)
+// Library-wide primitives (primitives.hip)
 // ---------------------------------------------------------------------------
 // Exclusive prefix sum: out[i] = sum in[0..i), out[n] = total.  `ws` must hold
 // scan_ws_elems(n) uint64 values.
