@@ -372,7 +372,9 @@ spc_status spc_query_config_info(uint32_t cfg, uint32_t *stage, uint32_t *tiles)
 /* Autotuner ("Query Evaluation in Parallel": queries are independent, so
  * any launch shape gives the same answers): run the nq sample queries s, t
  * (device pointers, ids of graph graph_id) once per configuration, twice
- * each, timed with events on `stream`; check that every configuration's
+ * each, timed with events on `stream`, grouped by staged label as large
+ * batches of spc_query_batch are (unless SPC_QUERY_ORDER=0), so a sample of
+ * the size of the batches to come tunes for them best; check that every configuration's
  * answers equal configuration 0's (SPC_ERR_DEVICE if not); keep the fastest
  * as the index's configuration and return its number in *cfg_out (may be
  * NULL).  Allocates scratch device memory for the outputs, synchronises

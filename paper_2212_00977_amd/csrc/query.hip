@@ -73,6 +73,9 @@ struct QueryArgs {
     uint32_t t_row;
 };
 
+// neighbouring workgroups of a query launch kept on one XCD (k_query)
+constexpr uint32_t kXcdRun = 16;
+
 // kQStage: L(s) entries staged per query; kQTiles: L(t) tiles of G entries
 // requested together; G: lanes per query (64: one query per wave, fewer:
 // several queries per wave for short labels).  The triple is a launch
@@ -86,7 +89,17 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs a) {
     static_assert(G == 64 || G == 32 || G == 16, "lanes per query");
     constexpr bool kWave = G == 64;  // one query per wave: uniform values in scalar registers
     __shared__ E stage[kBlock / G][kQStage];
-    const uint64_t q = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+    // Workgroups go to the 8 XCDs in turn; within every 8 kXcdRun
+    // consecutive blocks, XCD x takes the kXcdRun neighbouring ones from
+    // x kXcdRun, so that the neighbouring queries of an ordered batch (which
+    // share their staged label) meet in one L2 while the XCDs still share
+    // the batch evenly (a block past the last whole span keeps its index).
+    constexpr uint32_t span = 8 * kXcdRun;
+    const uint32_t b0 = blockIdx.x / span * span;
+    const uint32_t bk = b0 + span <= gridDim.x
+                            ? b0 + (blockIdx.x % 8) * kXcdRun + ((blockIdx.x / 8) % kXcdRun)
+                            : blockIdx.x;
+    const uint64_t q = ((uint64_t)bk * kBlock + threadIdx.x) / G;
     const uint64_t nq = a.cnt ? (uint64_t)*a.cnt : a.nq;
     if (q >= nq) return;
     const uint32_t lane = threadIdx.x & (G - 1);
@@ -530,19 +543,20 @@ spc_status query_run(const spc_index *ix, uint32_t graph_id, const uint32_t *s, 
                      uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
                      uint32_t cfg, hipStream_t st);
 
-}  // namespace
-
 // batches of at least this many queries are answered in locality order
 // (k_qrow) unless SPC_QUERY_ORDER=0 in the environment
 constexpr uint64_t kOrderMin = 1ull << 20;
 
-spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
-                      uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
-                      hipStream_t st) {
-    if (!ix) return SPC_ERR_INVALID_ARG;
+bool order_enabled() {
     const char *eo = std::getenv("SPC_QUERY_ORDER");
-    if (nq < kOrderMin || (eo && eo[0] == '0'))
-        return query_run(ix, graph_id, s, t, nq, dist_out, count_out, flags_out, ix->query_cfg, st);
+    return !(eo && eo[0] == '0');
+}
+
+// A batch answered in locality order with configuration cfg.
+spc_status query_ordered(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                         uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
+                         uint32_t cfg, hipStream_t st) {
+    if (nq == 0) return SPC_OK;
     if (graph_id >= ix->gn.size()) return SPC_ERR_INVALID_ARG;
     if (!s || !t || !dist_out || !count_out) return SPC_ERR_INVALID_ARG;
     QueryArgs a = index_args(ix);
@@ -590,10 +604,21 @@ spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s,
             break;
         }
         c.perm = perm;
-        r = launch_query(ix->dist_bits, ix->out_bits, ix->query_cfg, c, st);
+        r = launch_query(ix->dist_bits, ix->out_bits, cfg, c, st);
     }
     if (hipFreeAsync(buf, st) != hipSuccess && r == SPC_OK) r = SPC_ERR_DEVICE;
     return r;
+}
+
+}  // namespace
+
+spc_status query_impl(const spc_index *ix, uint32_t graph_id, const uint32_t *s, const uint32_t *t,
+                      uint64_t nq, void *dist_out, uint64_t *count_out, uint8_t *flags_out,
+                      hipStream_t st) {
+    if (!ix) return SPC_ERR_INVALID_ARG;
+    if (nq < kOrderMin || !order_enabled())
+        return query_run(ix, graph_id, s, t, nq, dist_out, count_out, flags_out, ix->query_cfg, st);
+    return query_ordered(ix, graph_id, s, t, nq, dist_out, count_out, flags_out, ix->query_cfg, st);
 }
 
 spc_status query_multi_impl(const spc_index *ix, const uint32_t *gid, const uint32_t *s,
@@ -733,7 +758,11 @@ spc_status tune_queries_impl(spc_index *ix, uint32_t graph_id, const uint32_t *s
         float ms = 0;
         for (int rep = 0; rep < 2; rep++) {  // the first run warms caches
             SPC_HIP(hipEventRecord(e0, st));
-            SPC_TRY(query_run(ix, graph_id, s, t, nq, d, c, f, cfg, st));
+            // the path large batches take
+            if (order_enabled())
+                SPC_TRY(query_ordered(ix, graph_id, s, t, nq, d, c, f, cfg, st));
+            else
+                SPC_TRY(query_run(ix, graph_id, s, t, nq, d, c, f, cfg, st));
             SPC_HIP(hipEventRecord(e1, st));
             SPC_HIP(hipEventSynchronize(e1));
             SPC_HIP(hipEventElapsedTime(&ms, e0, e1));

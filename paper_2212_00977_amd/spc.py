@@ -122,7 +122,12 @@ class Index:
         self._sizes = sizes  # input vertex count of each graph
 
     def __del__(self):
-        self.free()
+        # at interpreter exit the module globals may already be gone; the
+        # process's device memory goes with it then
+        try:
+            self.free()
+        except (AttributeError, TypeError):
+            pass
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
