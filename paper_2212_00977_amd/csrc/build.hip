@@ -1564,6 +1564,9 @@ __global__ void k_new_len(uint32_t N, const uint64_t *lab_off, const uint32_t *r
 // Each element's output position is its own index plus the number of smaller
 // hubs in the other list.  Also the number of landmark entries of the merged
 // label (its landmark prefix).  One wave per vertex.
+// outputs of one merge-path step of k_merge (a multiple of 64)
+constexpr uint32_t kMergeW = 256;
+
 template <int DB>
 __global__ __launch_bounds__(kBlock) void k_merge(uint32_t N, uint32_t d, const uint64_t *lab_off,
                                                   const typename Ent<DB>::T *lab_hd,
@@ -1588,13 +1591,66 @@ __global__ __launch_bounds__(kBlock) void k_merge(uint32_t N, uint32_t d, const 
         for (uint64_t i = lane; i < na; i += 64) out[i] = A[i];
         return;
     }
-    for (uint64_t i = lane; i < na; i += 64) {
-        E e = A[i];
-        out[i + lower_bound_u32(B, nb, e_hub<DB>(e))] = e;
-    }
-    for (uint32_t j = lane; j < nb; j += 64) {
-        uint32_t h = B[j];
-        out[j + lower_bound_hub<DB>(A, na, h)] = e_make<DB>(h, d);
+    // Merge path, kMergeW outputs per step: the next kMergeW entries of each
+    // list go to LDS (hubs; past a list's end a hub above every vertex), and
+    // an entry's place among the step's outputs is its index in its own
+    // window plus the count of smaller hubs in the other window (the hubs of
+    // the two lists are distinct).  That place is below kMergeW exactly for
+    // the entries that come first in the merge, so every step writes the
+    // next kMergeW outputs (fewer at the end) and consumes them from A and B.
+    constexpr uint32_t K = kMergeW / 64;
+    constexpr uint32_t kPast = 0xFFFFFFFFu;
+    __shared__ uint32_t sa[kWaves][kMergeW], sb[kWaves][kMergeW];
+    const uint32_t wv = threadIdx.x >> 6;
+    // entries of window s smaller than x
+    auto below = [](const uint32_t *s, uint32_t x) -> uint32_t {
+        uint32_t pos = 0;
+#pragma unroll
+        for (uint32_t step = kMergeW; step > 0; step >>= 1)
+            if (pos + step <= kMergeW && s[pos + step - 1] < x) pos += step;
+        return pos;
+    };
+    const uint64_t nt = na + nb;
+    uint64_t ia = 0, ib = 0;
+    while (ia + ib < nt) {
+        E ea[K];
+        uint32_t ha[K], hb[K];
+#pragma unroll
+        for (uint32_t k = 0; k < K; k++) {
+            const uint64_t i = ia + k * 64 + lane;
+            ea[k] = i < na ? A[i] : (E)0;
+            const uint64_t j = ib + k * 64 + lane;
+            hb[k] = j < nb ? B[j] : kPast;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < K; k++) {
+            ha[k] = ia + k * 64 + lane < na ? e_hub<DB>(ea[k]) : kPast;
+            sa[wv][k * 64 + lane] = ha[k];
+            sb[wv][k * 64 + lane] = hb[k];
+        }
+        wave_lds_sync();
+        E *o = out + ia + ib;
+        uint32_t take_a = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < K; k++) {
+            if (ha[k] != kPast) {
+                const uint32_t r = k * 64 + lane + below(sb[wv], ha[k]);
+                if (r < kMergeW) {
+                    o[r] = ea[k];
+                    take_a++;
+                }
+            }
+            if (hb[k] != kPast) {
+                const uint32_t r = k * 64 + lane + below(sa[wv], hb[k]);
+                if (r < kMergeW) o[r] = e_make<DB>(hb[k], d);
+            }
+        }
+        const uint32_t na_step = wave_sum(take_a);
+        const uint64_t left = nt - ia - ib;
+        const uint32_t made = left < kMergeW ? (uint32_t)left : kMergeW;
+        ia += na_step;
+        ib += made - na_step;
+        wave_lds_sync();  // the windows are rewritten next
     }
 }
 
@@ -1677,8 +1733,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(uint32_t N, const uint64_t 
 // Count of every final entry by rank (8-bit distances): a label and each of
 // its round segments are sorted by hub, so the j-th entry of distance r in
 // L(u) is the j-th entry of u's round-r segment.  One wave per vertex walks
-// L(u) in chunks of 64, ranking lanes of equal distance with ballots and
-// keeping a running count per distance in LDS.
+// L(u) kFinalK chunks of 64 at a time (their loads, then their count
+// gathers, in flight together), ranking lanes of equal distance with ballots
+// and keeping a running count per distance in LDS.
+constexpr uint32_t kFinalK = 4;
 __global__ __launch_bounds__(kBlock) void k_finalize_rank(uint32_t N, uint32_t R,
                                                           const uint64_t *lab_off,
                                                           const uint32_t *lab_hd,
@@ -1687,6 +1745,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize_rank(uint32_t N, uint32_t R
                                                           uint64_t *lab_cnt, unsigned long long *nsat) {
     __shared__ uint32_t seen[kWaves][256];
     __shared__ uint64_t seg[kWaves][256];
+    __shared__ const uint64_t *ctab[256];
+    for (uint32_t r = threadIdx.x; r < 256; r += blockDim.x) ctab[r] = r < R ? cnt_tab[r] : nullptr;
+    __syncthreads();
     const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t u = blockIdx.x * kWaves + wv;
     if (u >= N) return;
@@ -1697,26 +1758,40 @@ __global__ __launch_bounds__(kBlock) void k_finalize_rank(uint32_t N, uint32_t R
     wave_lds_sync();
     const uint64_t a0 = lab_off[u], na = lab_off[u + 1] - a0;
     uint32_t sat = 0;
-    for (uint64_t i0 = 0; i0 < na; i0 += 64) {
-        const uint64_t i = i0 + lane;
-        const bool valid = i < na;
-        const uint32_t r = valid ? e_dist<8>(lab_hd[a0 + i]) : 0;
-        uint64_t peers = __ballot(valid);
+    for (uint64_t i0 = 0; i0 < na; i0 += 64 * kFinalK) {
+        uint32_t r[kFinalK];
+        bool valid[kFinalK];
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
-            const uint64_t bb = __ballot((r >> b) & 1);
-            peers &= ((r >> b) & 1) ? bb : ~bb;
+        for (uint32_t k = 0; k < kFinalK; k++) {
+            const uint64_t i = i0 + k * 64 + lane;
+            valid[k] = i < na;
+            r[k] = valid[k] ? e_dist<8>(lab_hd[a0 + i]) : 0;
         }
-        const uint32_t rank = __popcll(peers & lanemask_lt());
-        const uint32_t base = seen[wv][r];
-        if (valid) {
-            const uint64_t c = cnt_tab[r][seg[wv][r] + base + rank];
-            lab_cnt[a0 + i] = c;
-            sat += (c == kSat);
+        uint64_t at[kFinalK];
+#pragma unroll
+        for (uint32_t k = 0; k < kFinalK; k++) {
+            uint64_t peers = __ballot(valid[k]);
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                const uint64_t bb = __ballot((r[k] >> b) & 1);
+                peers &= ((r[k] >> b) & 1) ? bb : ~bb;
+            }
+            const uint32_t rank = __popcll(peers & lanemask_lt());
+            const uint32_t base = seen[wv][r[k]];
+            at[k] = seg[wv][r[k]] + base + rank;
+            wave_lds_sync();
+            if (valid[k] && (peers & lanemask_lt()) == 0) seen[wv][r[k]] = base + (uint32_t)__popcll(peers);
+            wave_lds_sync();
         }
-        wave_lds_sync();
-        if (valid && (peers & lanemask_lt()) == 0) seen[wv][r] = base + (uint32_t)__popcll(peers);
-        wave_lds_sync();
+        uint64_t c[kFinalK];
+#pragma unroll
+        for (uint32_t k = 0; k < kFinalK; k++) c[k] = valid[k] ? ctab[r[k]][at[k]] : 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kFinalK; k++)
+            if (valid[k]) {
+                lab_cnt[a0 + i0 + k * 64 + lane] = c[k];
+                sat += (c[k] == kSat);
+            }
     }
     sat = wave_sum(sat);
     if (lane == 0 && sat) atomicAdd(nsat, (unsigned long long)sat);
