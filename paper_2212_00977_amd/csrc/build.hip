@@ -2509,10 +2509,11 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
         }
     }
     std::vector<uint32_t> bounds{0};
+    std::vector<uint64_t> ro;  // raw_off on the host (several batches)
     if (total_raw <= B.tmp_cap && N <= kBatchVerts) {
         bounds.push_back(N);
     } else {
-        std::vector<uint64_t> ro((size_t)N + 1);
+        ro.resize((size_t)N + 1);
         SPC_HIP(hipMemcpyAsync(ro.data(), B.raw_off, ((size_t)N + 1) * sizeof(uint64_t),
                                hipMemcpyDeviceToHost, B.st));
         SPC_HIP(hipStreamSynchronize(B.st));
@@ -2539,9 +2540,8 @@ spc_status run_round(Build &B, uint32_t d, uint64_t *kept_out, bool *any_cand) {
     }
     for (size_t bi = 0; bi + 1 < bounds.size(); bi++) {
         const uint32_t b0 = bounds[bi], b1 = bounds[bi + 1];
-        uint64_t need;  // pulled entries of the batch
-        SPC_TRY(B.read_u64(B.raw_off + b1, &need));
-        need -= raw_lo;
+        // pulled entries of the batch (raw_off[N] = total_raw)
+        const uint64_t need = (ro.empty() ? total_raw : ro[b1]) - raw_lo;
         if (need > B.tmp_cap) {  // a single puller pulling more than the buffer holds
             B.arena.release(B.tmp_hub);
             B.arena.release(B.tmp_cnt);
