@@ -646,7 +646,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     // galloping search per neighbour; a chunk is sized from its exact pull
     // count and the pulls-per-distinct-candidate ratio seen so far, so that
     // the candidate table rarely overflows.
-    constexpr uint32_t kTarget = kULimit * 3 / 4;  // distinct candidates aimed at
+    constexpr uint32_t kTarget = kULimit * 7 / 8;  // distinct candidates aimed at
     const bool one_group = deg <= (uint32_t)RB;   // cursors live in registers
     uint32_t my_v = 0, my_ln = 0, my_c = 0, my_e = 0;
     uint64_t my_ps = 0;
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                     width = w2 ? w2 : 1;
                     continue;
                 }
-                if (may_widen && expect < 0.5f * kTarget && hi < hend) {
+                if (may_widen && expect < 0.75f * kTarget && hi < hend) {
                     float f = expect > 1.0f ? (float)kTarget / expect : 8.0f;
                     f = f > 8.0f ? 8.0f : f;
                     uint64_t w2 = (uint64_t)((double)(hi - lo) * f);
