@@ -646,7 +646,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     // galloping search per neighbour; a chunk is sized from its exact pull
     // count and the pulls-per-distinct-candidate ratio seen so far, so that
     // the candidate table rarely overflows.
-    constexpr uint32_t kTarget = kULimit * 7 / 8;  // distinct candidates aimed at
+    constexpr uint32_t kTarget = kULimit * 3 / 4;  // distinct candidates aimed at
     const bool one_group = deg <= (uint32_t)RB;   // cursors live in registers
     uint32_t my_v = 0, my_ln = 0, my_c = 0, my_e = 0;
     uint64_t my_ps = 0;
