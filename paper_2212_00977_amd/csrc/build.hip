@@ -647,6 +647,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     // count and the pulls-per-distinct-candidate ratio seen so far, so that
     // the candidate table rarely overflows.
     constexpr uint32_t kTarget = kULimit * 3 / 4;  // distinct candidates aimed at
+    constexpr int kSizePasses = 8;                  // pull counts taken per chunk at most
     const bool one_group = deg <= (uint32_t)RB;   // cursors live in registers
     uint32_t my_v = 0, my_ln = 0, my_c = 0, my_e = 0;
     uint64_t my_ps = 0;
@@ -666,8 +667,9 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     // 2-5, chunk by chunk
     while (lo < ur) {
         // A. size the chunk.  With cursors in registers the exact pull count
-        //    of [lo, hi) is cheap: the range is narrowed or widened once so
-        //    that the expected distinct count fits.  Wider pullers take the
+        //    of [lo, hi) is cheap: the range is narrowed or widened, up to
+        //    kSizePasses - 1 times, until the expected distinct count falls
+        //    in the band (the count is exact for each try).  Wider pullers take the
         //    width learned from the previous chunk.  A label staged chunk by
         //    chunk caps the range at the hub of its entry kLStage past the
         //    cursor (which is above lo).
@@ -688,7 +690,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                     t = my_e - my_c;
                 }
                 block_excl_scan<uint32_t, RW>(t, red32, tot);
-                if (it == 1) break;
+                if (it + 1 == kSizePasses) break;
                 const float expect = (float)tot / ratio;
                 if (expect > 1.25f * kTarget && hi - lo > 1) {
                     uint32_t w2 = (uint32_t)((float)(hi - lo) * ((float)kTarget / expect));
