@@ -658,10 +658,13 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
     }
     float ratio = 2.0f;      // pulls per distinct candidate
     bool may_widen = true;   // false from an overflow until a chunk completes
-    uint32_t lo = 0, width = ur;
+    // u's hubs are vertices of its own graph, ids [base, ur): the chunks
+    // start at base (a batch's other graphs hold none)
+    const uint32_t lo0 = base < ur ? base : ur;
+    uint32_t lo = lo0, width = ur - lo0;
     if (raw_u > (uint64_t)(2 * kTarget)) {
         uint64_t parts = (raw_u + 2 * kTarget - 1) / (2 * kTarget);
-        width = (uint32_t)(ur / parts) > 0 ? (uint32_t)(ur / parts) : 1;
+        width = (uint32_t)((ur - lo0) / parts) > 0 ? (uint32_t)((ur - lo0) / parts) : 1;
     }
 
     // 2-5, chunk by chunk
@@ -750,7 +753,7 @@ __global__ __launch_bounds__(RB, 4) void k_round(RoundArgs a) {  // at most 128 
                     const uint32_t v = a.gadj[g0 + nb];
                     const uint32_t ln = a.plen[v];
                     ps = ln ? a.pstart[v] : 0;
-                    c = lo ? a.cur[g0 + nb] : 0;
+                    c = lo > lo0 ? a.cur[g0 + nb] : 0;  // the first chunk starts the cursors
                     e = (real(v) >= lo && c < ln) ? gallop_u32(a.pool_hub + ps, c, ln, hi) : c;
                     a.nxt[g0 + nb] = e;
                 }
